@@ -1,0 +1,6 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+Only input generation lives here (meshes, Q1 assembly, box hierarchies, random
+coefficients and right-hand sides).  None of the RSD method's arithmetic does.
+"""
+from .problems import Problem, diffusion_problem, config_problem, strip_problem  # noqa: F401

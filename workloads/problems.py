@@ -1,0 +1,101 @@
+"""Seeded problem instances: matrix, hierarchy and right-hand sides.
+
+Random numbers come from NumPy's PCG64 (``numpy.random.default_rng(seed)``) in
+a fixed draw order: element coefficients first, then right-hand sides, then
+any further targets.
+
+Instances
+---------
+* ``config_problem("poisson12")`` -- Poisson on 12^3 Q1 hexahedra, 2x2x2 box
+  sub-domains (octree of height 1), f ~ U[-1,1] per free dof.
+* ``config_problem("diffusion64")`` -- -div(k grad u) = f on 64^3 Q1 hexahedra,
+  k_e = exp(z_e), z_e ~ N(0,1) per element, 4x4x4 box sub-domains (octree of
+  height 2: two interface levels below three RSD recursion levels), f ~ U[-1,1].
+* ``config_problem("adjoint32")`` -- 32^3, k_e = exp(theta_e), theta_e ~ N(0, 0.5^2),
+  octree of height 2; b ~ U[-1,1] and a target x_t ~ U[-1,1].
+* ``diffusion_problem(ne, height, ...)`` -- any size, for parity cases.
+* ``strip_problem(N, P, ...)`` -- the paper's 2-D strip workloads (Section 4):
+  P sub-domains of N x N nodes in a binary tree, manufactured right-hand side
+  b = K x_true with x_true ~ U[-1,1].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+from .fem import assemble_diffusion_3d, assemble_strip_2d
+from .hierarchy import build_box_tree, dof_node_map
+
+
+@dataclass
+class Problem:
+    name: str
+    K: sp.csr_matrix
+    parent: np.ndarray        # int32[T]
+    dof_node: np.ndarray      # int32[n]
+    b: np.ndarray             # float64[n, nrhs]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.K.shape[0]
+
+    def csr_arrays(self):
+        """(row_ptr int64[n+1], col_idx int32[nnz], values float64[nnz])."""
+        K = self.K
+        return (K.indptr.astype(np.int64), K.indices.astype(np.int32),
+                K.data.astype(np.float64))
+
+
+def diffusion_problem(ne: int, height: int, sigma: float = 0.0, seed: int = 0,
+                      nrhs: int = 1, name: str | None = None, cut_fn=None) -> Problem:
+    """-div(k grad u) = f on ne^3 Q1 hexahedra with an octree of the given height.
+
+    sigma = 0 gives Poisson (k = 1, no coefficient draw); otherwise
+    k_e = exp(sigma * z_e) with z_e ~ N(0, 1) drawn first.  f ~ U[-1,1] per free
+    dof, nrhs columns, drawn after the coefficients.
+    """
+    rng = np.random.default_rng(seed)
+    k = None
+    if sigma > 0.0:
+        k = np.exp(sigma * rng.standard_normal(ne ** 3))
+    sysm = assemble_diffusion_3d(ne, k)
+    tree = build_box_tree(sysm.shape_nodes, height, cut_fn=cut_fn)
+    dof_node = dof_node_map(tree, sysm.free_ijk, 1)
+    b = rng.uniform(-1.0, 1.0, size=(sysm.K.shape[0], nrhs))
+    return Problem(name or f"diffusion{ne}_h{height}", sysm.K, tree.parent, dof_node, b,
+                   meta=dict(ne=ne, height=height, sigma=sigma, seed=seed, k_elem=k,
+                             free_ijk=sysm.free_ijk, tree=tree))
+
+
+def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
+    if name == "poisson12":
+        return diffusion_problem(12, 1, 0.0, seed, nrhs, name)
+    if name == "diffusion64":
+        return diffusion_problem(64, 2, 1.0, seed, nrhs, name)
+    if name == "adjoint32":
+        p = diffusion_problem(32, 2, 0.5, seed, nrhs, name)
+        # draw order continues after b: the adjoint target
+        rng = np.random.default_rng(seed)
+        rng.standard_normal(32 ** 3)
+        rng.uniform(-1.0, 1.0, size=(p.n, nrhs))
+        p.meta["x_target"] = rng.uniform(-1.0, 1.0, size=p.n)
+        return p
+    raise KeyError(name)
+
+
+def strip_problem(N: int, P: int, problem: str = "poisson", seed: int = 0) -> Problem:
+    """The paper's 2-D long strip with P = 2^H sub-domains of N x N nodes."""
+    H = int(round(np.log2(P)))
+    if 2 ** H != P:
+        raise ValueError("P must be a power of two")
+    sysm = assemble_strip_2d(N, P, problem)
+    tree = build_box_tree(sysm.shape_nodes, H, axes_per_level=lambda d: (0,))
+    dof_node = dof_node_map(tree, sysm.free_ijk, sysm.ndof)
+    rng = np.random.default_rng(seed)
+    x_true = rng.uniform(-1.0, 1.0, size=sysm.K.shape[0])
+    b = (sysm.K @ x_true)[:, None]
+    return Problem(f"strip_{problem}_N{N}_P{P}", sysm.K, tree.parent, dof_node, b,
+                   meta=dict(N=N, P=P, x_true=x_true, tree=tree, free_ijk=sysm.free_ijk))
