@@ -1,0 +1,220 @@
+/*
+ * rsd.h -- C ABI of the MI355X Recursive Schur Decomposition (RSD) solver library.
+ *
+ * The library solves K u = f for a sparse symmetric positive definite
+ * finite-element matrix K with a Krylov method preconditioned by RSD
+ * (Sampath, Philip, Allu, Simunovic, "Recursive Schur Decomposition"; the
+ * problem statement opens Section 3).  The caller describes K in CSR form and
+ * the hierarchical domain decomposition of Section 2 as a tree whose leaves
+ * are the true sub-domains and whose internal nodes each stand for the
+ * interface between their children.
+ *
+ * Conventions for every entry point
+ *   - Every call returns an rsd_status; nothing throws or aborts across the ABI.
+ *   - Array arguments are plain pointers.  Unless stated otherwise they are
+ *     HIP device pointers owned by the caller; the library never frees them and
+ *     keeps no reference after the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *     device work of a call is enqueued on it, in order.
+ *   - Vectors are FP64, column-major n x nrhs blocks with leading dimension
+ *     ld >= n, in the caller's dof numbering.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef RSD_H_
+#define RSD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSD_OK = 0,
+  RSD_ERR_INVALID_ARGUMENT = 1,  /* malformed CSR / tree / map, bad sizes or pointers     */
+  RSD_ERR_MAP_NOT_SEPARABLE = 2, /* K couples two dofs whose tree nodes are not on one
+                                    root-to-leaf path (e.g. two different leaves)        */
+  RSD_ERR_NOT_SPD = 3,           /* a sub-domain or interface block has a pivot <= 0 or
+                                    a non-finite pivot; rsd_last_error names the block    */
+  RSD_ERR_NOT_CONVERGED = 4,     /* Krylov reached maxit; x holds the last iterate       */
+  RSD_ERR_BREAKDOWN = 5,         /* NaN/Inf in the Krylov recurrence                     */
+  RSD_ERR_OUT_OF_MEMORY = 6,     /* device allocation failed                             */
+  RSD_ERR_DEVICE = 7,            /* any other HIP runtime error                          */
+  RSD_ERR_UNSUPPORTED = 8        /* valid request this build does not implement          */
+} rsd_status;
+
+typedef struct rsd_ctx* rsd_handle;
+
+/* Sparse matrix K (n x n) in CSR form: row_ptr[n+1] (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n] = nnz), col_idx[nnz] strictly increasing within a
+ * row, values[nnz].  K must be symmetric (structure checked, values assumed). */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+} rsd_csr;
+
+/* The sub-domain hierarchy of Section 2 (Fig. 1): num_nodes tree nodes with
+ * parent[0] = -1 and 0 <= parent[t] < t for t > 0 (so ids are topologically
+ * ordered).  A node without children is a true sub-domain (leaf).  dof_node[i]
+ * (n entries) names the node that owns dof i: a leaf for a dof in the interior
+ * of that true sub-domain, an internal node for a dof on the interface that
+ * node represents.  Any node may own no dofs. */
+typedef struct {
+  int32_t num_nodes;
+  const int32_t* parent;
+  const int32_t* dof_node;
+} rsd_hierarchy;
+
+/* Storage / arithmetic precision of a class of dense blocks. */
+enum { RSD_PREC_FP64 = 0, RSD_PREC_FP32 = 1 };
+
+typedef struct {
+  int32_t struct_size;   /* sizeof(rsd_options) */
+  int32_t leaf_prec;     /* inverses of the true sub-domain matrices K_ll              */
+  int32_t sigma_prec;    /* leaf boundary Schur blocks Sigma_l = K_Bl K_ll^-1 K_lB      */
+  int32_t iface_prec;    /* inverses of the non-root interface Schur complements       */
+  int32_t root_prec;     /* inverse of the root interface Schur complement             */
+  int32_t host_pointers; /* 0: csr and hierarchy arrays are device pointers;
+                            1: they are host pointers (values are copied to the device) */
+  int32_t timing;        /* 1: time every kernel class with HIP events (rsd_get_stats) */
+} rsd_options;
+
+/* Fills *opt with the defaults: all FP64, device pointers, no timing. */
+void rsd_options_default(rsd_options* opt);
+
+enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };
+
+typedef struct {
+  int32_t method;   /* RSD_SOLVER_FGMRES (right-preconditioned, flexible) or RSD_SOLVER_PCG */
+  int32_t restart;  /* FGMRES restart length m (1..256)                                       */
+  int32_t maxit;    /* maximum number of Krylov iterations per right-hand side               */
+  double rtol;      /* stop when ||b - K x||_2 <= rtol ||b||_2 (true residual)               */
+  int32_t use_x0;   /* 1: x holds the initial guess on entry; 0: x0 = 0                       */
+} rsd_solve_options;
+
+typedef struct {
+  int32_t iterations; /* Krylov iterations taken                                        */
+  double relres;      /* final true relative residual ||b - K x|| / ||b||               */
+  int32_t status;     /* rsd_status of this right-hand side                             */
+} rsd_solve_info;
+
+/* Counts produced by the host analysis of the hierarchy (rsd_analyze) and the
+ * per-apply / per-setup algorithmic work used for roofline accounting. */
+typedef struct {
+  int32_t num_leaves;
+  int32_t num_levels;           /* interface levels (internal-node depths)              */
+  int32_t max_leaf_dofs;
+  int32_t max_iface_dofs;
+  int32_t max_boundary_dofs;    /* max over leaves of m_l = |B_l|                        */
+  int64_t leaf_dofs;            /* dofs in leaf interiors                              */
+  int64_t skeleton_dofs;        /* dofs on interfaces                                  */
+  int64_t sum_leaf_sq;          /* sum_l n_l^2                                         */
+  int64_t sum_iface_sq;         /* sum_t n_t^2                                         */
+  int64_t sum_sigma_apply;      /* entries of the Sigma_l blocks read by one apply     */
+  int64_t sum_sigma_sq;         /* sum_l m_l^2                                         */
+  double leaf_inverse_flops;    /* sum_l n_l^3 (symmetric in-place inversion)          */
+  double iface_inverse_flops;   /* sum_t n_t^3                                         */
+} rsd_analysis;
+
+/* Host-only analysis of (csr structure, hierarchy): validates the input
+ * exactly as rsd_setup does and reports the counts above.  All pointers are
+ * HOST pointers; csr->values may be NULL.  Makes no HIP call.
+ * Errors: RSD_ERR_INVALID_ARGUMENT, RSD_ERR_MAP_NOT_SEPARABLE. */
+rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analysis* out);
+
+/* Set-up of the RSD preconditioner (Section 3).
+ *  1. Host analysis: validates the CSR, the tree and dof_node; checks that the
+ *     decomposition separates K (every non-zero K_ij joins dofs whose nodes lie
+ *     on one root-to-leaf path -- the block structure of eq. (matPart)); orders
+ *     dofs as [leaf interiors | interfaces, deepest level first].
+ *  2. Device: extracts every true sub-domain matrix K_ll and inverts it exactly
+ *     (the direct sub-domain solve of Section 3.1), forms the leaf boundary
+ *     blocks Sigma_l = K_Bl K_ll^-1 K_lB, assembles for every internal node t the
+ *     interface operator of Alg. 1,
+ *        S~_t = K_tt - sum over leaves l of subtree(t) coupled to I_t of Sigma_l[I_t, I_t],
+ *     and inverts it (the exact interface solve: the limit of the paper's inner
+ *     Krylov iteration).  Dense blocks use the precisions in *opt.
+ * csr / hier: device pointers unless opt->host_pointers = 1.  opt may be NULL
+ * (defaults).  On success *out receives a new handle; on failure *out = NULL and
+ * rsd_last_error(NULL) describes the error (thread-local).  Synchronises `stream`
+ * once at the end (pivot status read-back).
+ * Errors: INVALID_ARGUMENT, MAP_NOT_SEPARABLE, NOT_SPD, OUT_OF_MEMORY, DEVICE. */
+rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_options* opt,
+                     void* stream, rsd_handle* out);
+
+/* z = M^{-1} r: one application of the RSD preconditioner (Alg. 2) to each of
+ * nrhs columns: all sub-domain solves, then the interface levels from the
+ * deepest to the root (right-hand side g of eq. (schur), interface solve,
+ * back-substitution of eq. (backSub) onto the adjacent sub-domains), then the
+ * final sub-domain solves.  r and z are device arrays (n x nrhs, ld >= n) and
+ * must not overlap.  nrhs = 0 is a no-op.  Asynchronous on `stream`.
+ * Errors: INVALID_ARGUMENT, DEVICE. */
+rsd_status rsd_apply(rsd_handle h, int32_t nrhs, const double* r, int64_t ldr, double* z,
+                     int64_t ldz, void* stream);
+
+/* y = K x with the handle's matrix (the Krylov MatVec), x and y device arrays
+ * (n x nrhs), not overlapping.  Asynchronous.  Errors: INVALID_ARGUMENT, DEVICE. */
+rsd_status rsd_spmv(rsd_handle h, int32_t nrhs, const double* x, int64_t ldx, double* y,
+                    int64_t ldy, void* stream);
+
+/* Solves K x = b for each of nrhs columns with RSD-preconditioned Krylov
+ * iterations (Section 3: GMRES with RSD as preconditioner; here right-
+ * preconditioned flexible GMRES(m), or PCG), in FP64, to the true relative
+ * residual ||b - K x||_2 <= rtol ||b||_2.  b and x are device arrays; info is a
+ * HOST array of nrhs entries (may be NULL).  opt may be NULL (FGMRES(30),
+ * rtol 1e-10, maxit 500, x0 = 0).  Synchronises `stream` once per iteration.
+ * Returns the worst per-column status: NOT_CONVERGED (x holds the last
+ * iterate), BREAKDOWN, or OK. */
+rsd_status rsd_solve(rsd_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                     int64_t ldx, const rsd_solve_options* opt, rsd_solve_info* info,
+                     void* stream);
+
+/* Replaces the values of K (same sparsity pattern, `values` in the caller's CSR
+ * order, device pointer unless the handle was set up with host_pointers = 1)
+ * and recomputes every dense block, skipping the host analysis.
+ * Errors: INVALID_ARGUMENT, NOT_SPD, DEVICE. */
+rsd_status rsd_update_values(rsd_handle h, const double* values, void* stream);
+
+/* Per-handle statistics.  Times are accumulated device times in milliseconds
+ * measured with HIP events when the handle was created with timing = 1. */
+enum {
+  RSD_T_SETUP_EXTRACT = 0, /* value gathers, dense block extraction            */
+  RSD_T_LEAF_INVERSE,      /* batched in-place inversion of the K_ll          */
+  RSD_T_SIGMA,             /* Sigma_l blocks                                  */
+  RSD_T_IFACE_ASSEMBLY,    /* S~_t assembly (extend-add)                      */
+  RSD_T_IFACE_INVERSE,     /* batched inversion of the S~_t                   */
+  RSD_T_LEAF_APPLY,        /* batched symmetric products with K_ll^-1         */
+  RSD_T_IFACE_APPLY,       /* batched symmetric products with S~_t^-1         */
+  RSD_T_COUPLING,          /* sparse couplings, Sigma products, g assembly    */
+  RSD_T_SPMV,              /* global SpMV                                     */
+  RSD_T_KRYLOV,            /* dots, orthogonalisation, vector updates         */
+  RSD_T_PERMUTE,           /* user <-> internal dof ordering                  */
+  RSD_T_COUNT
+};
+typedef struct {
+  rsd_analysis analysis;
+  double time_ms[RSD_T_COUNT];
+  int64_t launches[RSD_T_COUNT];
+  double host_analysis_ms; /* wall time of step 1 of rsd_setup                 */
+  int64_t device_bytes;    /* device memory held by the handle                */
+} rsd_stats;
+
+/* Copies the handle's statistics (synchronises `stream` when timing is on).
+ * reset = 1 clears the accumulated times and launch counts afterwards. */
+rsd_status rsd_get_stats(rsd_handle h, rsd_stats* out, int32_t reset, void* stream);
+
+/* Frees the handle and its device memory (after its pending work completes). */
+void rsd_destroy(rsd_handle h);
+
+/* Message of the last error on h; with h = NULL, of the last failed rsd_setup
+ * or rsd_analyze on the calling thread.  Never NULL. */
+const char* rsd_last_error(rsd_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSD_H_ */

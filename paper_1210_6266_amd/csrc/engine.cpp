@@ -1,0 +1,767 @@
+// The RSD engine: set-up (Section 3: exact sub-domain inverses, interface Schur
+// complements of Alg. 1, their inverses), the preconditioner apply (Alg. 2 with
+// exact interface solves), the MatVec, and FGMRES / PCG drivers.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace rsd {
+
+namespace {
+
+struct Fail {
+  rsd_status st;
+};
+
+void hip_check(rsd_ctx* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  h->err = std::string(what) + ": " + hipGetErrorString(e);
+  throw Fail{e == hipErrorOutOfMemory ? RSD_ERR_OUT_OF_MEMORY : RSD_ERR_DEVICE};
+}
+
+template <typename T>
+T* dalloc(rsd_ctx* h, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hip_check(h, hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  h->allocs.push_back({p, count * sizeof(T)});
+  h->device_bytes += int64_t(count * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+void dfree(rsd_ctx* h, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i].first == p) {
+      h->device_bytes -= int64_t(h->allocs[i].second);
+      h->allocs.erase(h->allocs.begin() + long(i));
+      break;
+    }
+  (void)hipFree(p);
+}
+
+template <typename T>
+T* upload(rsd_ctx* h, const std::vector<T>& v, hipStream_t s) {
+  T* d = dalloc<T>(h, v.size());
+  if (!v.empty())
+    hip_check(h, hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync H2D");
+  return d;
+}
+
+// Times the launches enqueued during its lifetime on stream s (when timing is on).
+struct Timer {
+  rsd_ctx* h;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timer(rsd_ctx* h_, int cls_, hipStream_t s_) : h(h_), cls(cls_), s(s_) {
+    h->launches[cls]++;
+    if (!h->opt.timing) return;
+    a = take();
+    hip_check(h, hipEventRecord(a, s), "hipEventRecord");
+  }
+  ~Timer() {
+    if (!a) return;
+    hipEvent_t b = take();
+    (void)hipEventRecord(b, s);
+    h->pending.push_back({cls, a, b});
+  }
+  hipEvent_t take() {
+    if (!h->pool.empty()) {
+      hipEvent_t e = h->pool.back();
+      h->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hip_check(h, hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+};
+
+void fold_timings(rsd_ctx* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
+      h->time_ms[p.cls] += ms;
+    h->pool.push_back(p.a);
+    h->pool.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
+DevBatch upload_batch(rsd_ctx* h, const SymBatch& b, bool fp32, hipStream_t s) {
+  DevBatch d;
+  d.count = b.count;
+  d.max_nt = b.max_nt;
+  d.max_tiles = b.max_tiles;
+  d.n = upload(h, b.n, s);
+  d.nt = upload(h, b.nt, s);
+  d.tile_off = upload(h, b.tile_off, s);
+  d.vec_off = upload(h, b.vec_off, s);
+  d.num_items = int32_t(b.item_mat.size());
+  d.item_mat = upload(h, b.item_mat, s);
+  d.item_J = upload(h, b.item_J, s);
+  d.item_I0 = upload(h, b.item_I0, s);
+  d.item_I1 = upload(h, b.item_I1, s);
+  d.item_cslot = upload(h, b.item_cslot, s);
+  d.rslot_off = upload(h, b.rslot_off, s);
+  d.cstrip_ptr = upload(h, b.cstrip_ptr, s);
+  d.cstrip_base = upload(h, b.cstrip_base, s);
+  d.fp32 = fp32 ? 1 : 0;
+  if (b.total_elems > 0) {
+    if (fp32)
+      d.tiles = dalloc<float>(h, size_t(b.total_elems));
+    else
+      d.tiles = dalloc<double>(h, size_t(b.total_elems));
+  }
+  return d;
+}
+
+int choose_lpr(double avg) {
+  if (avg <= 6) return 4;
+  if (avg <= 12) return 8;
+  if (avg <= 40) return 16;
+  return 32;
+}
+
+}  // namespace
+
+void fill_analysis(const Plan& P, rsd_analysis* a) {
+  std::memset(a, 0, sizeof(*a));
+  a->num_leaves = int32_t(P.leaf_node.size());
+  a->num_levels = int32_t(P.level_depth.size());
+  a->max_leaf_dofs = P.max_leaf;
+  a->max_iface_dofs = P.max_iface;
+  a->max_boundary_dofs = P.max_m;
+  a->leaf_dofs = P.n_leaf;
+  a->skeleton_dofs = P.n - P.n_leaf;
+  a->sum_leaf_sq = P.sum_leaf_sq;
+  a->sum_iface_sq = P.sum_iface_sq;
+  a->sum_sigma_apply = P.sum_sigma_apply;
+  a->sum_sigma_sq = P.sum_sigma_sq;
+  a->leaf_inverse_flops = P.leaf_flops;
+  a->iface_inverse_flops = P.iface_flops;
+}
+
+rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier,
+                       const rsd_options* opt, hipStream_t s) {
+  try {
+    if (opt) {
+      h->opt = *opt;
+    } else {
+      rsd_options_default(&h->opt);
+    }
+    const int32_t n = csr->n;
+    const int64_t nnz = csr->nnz;
+    const int32_t T = hier->num_nodes;
+    // ---- host copies of the structure
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci, par, dn;
+    const int64_t* rpp = csr->row_ptr;
+    const int32_t* cip = csr->col_idx;
+    const int32_t* parp = hier->parent;
+    const int32_t* dnp = hier->dof_node;
+    if (!h->opt.host_pointers) {
+      rp.resize(size_t(n) + 1);
+      ci.resize(size_t(nnz));
+      par.resize(size_t(T));
+      dn.resize(size_t(n));
+      hip_check(h, hipMemcpyAsync(rp.data(), csr->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, s), "copy row_ptr");
+      if (nnz > 0)
+        hip_check(h, hipMemcpyAsync(ci.data(), csr->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, s), "copy col_idx");
+      hip_check(h, hipMemcpyAsync(par.data(), hier->parent, par.size() * 4, hipMemcpyDeviceToHost, s), "copy parent");
+      hip_check(h, hipMemcpyAsync(dn.data(), hier->dof_node, dn.size() * 4, hipMemcpyDeviceToHost, s), "copy dof_node");
+      hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+      rpp = rp.data();
+      cip = ci.data();
+      parp = par.data();
+      dnp = dn.data();
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string msg;
+    const PlanError pe = build_plan(n, nnz, rpp, cip, T, parp, dnp, &h->P, &msg);
+    h->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (pe != PlanError::kOk) {
+      h->err = msg;
+      return pe == PlanError::kNotSeparable ? RSD_ERR_MAP_NOT_SEPARABLE : RSD_ERR_INVALID_ARGUMENT;
+    }
+    hip_check(h, hipGetDevice(&h->device), "hipGetDevice");
+    const Plan& P = h->P;
+    if (const char* g = std::getenv("RSD_SWEEP_GROUP")) h->group = std::max(1, std::min(2, std::atoi(g)));
+    h->lpr = choose_lpr(double(nnz) / double(n));
+    // ---- upload structure
+    h->prow = upload(h, P.prow, s);
+    h->pcol = upload(h, P.pcol, s);
+    h->pmap = upload(h, P.pmap, s);
+    h->segA = upload(h, P.segA, s);
+    h->segB = upload(h, P.segB, s);
+    h->segC = upload(h, P.segC, s);
+    h->perm = upload(h, P.perm, s);
+    h->pval = dalloc<double>(h, size_t(nnz));
+    h->B_off = upload(h, P.B_off, s);
+    h->B = upload(h, P.B, s);
+    h->adj_ptr = upload(h, P.adj_ptr, s);
+    h->adj_leaf = upload(h, P.adj_leaf, s);
+    h->adj_pos = upload(h, P.adj_pos, s);
+    h->sig_off_d = upload(h, P.sig_off, s);
+    SigmaArgs& a = h->sig;
+    a.num_leaves = int32_t(P.leaf_node.size());
+    a.max_m = P.max_m;
+    a.B_off = h->B_off;
+    a.B = h->B;
+    a.shell_off = upload(h, P.shell_off, s);
+    a.shell = upload(h, P.shell, s);
+    a.kcol_ptr = upload(h, P.kcol_ptr, s);
+    a.kcol_row = upload(h, P.kcol_row, s);
+    a.kcol_val = upload(h, P.kcol_val, s);
+    a.krow_ptr = upload(h, P.krow_ptr, s);
+    a.krow_col = upload(h, P.krow_col, s);
+    a.krow_val = upload(h, P.krow_val, s);
+    a.w_off = upload(h, P.w_off, s);
+    a.sig_off = h->sig_off_d;
+    a.pval = h->pval;
+    h->sigma_fp32 = h->opt.sigma_prec == RSD_PREC_FP32;
+    if (h->sigma_fp32)
+      h->sigma = dalloc<float>(h, size_t(P.sig_total));
+    else
+      h->sigma = dalloc<double>(h, size_t(P.sig_total));
+    h->leaf = upload_batch(h, P.leaf_batch, h->opt.leaf_prec == RSD_PREC_FP32, s);
+    const int NL = int(P.level_depth.size());
+    h->lev.clear();
+    h->lev_items.clear();
+    int64_t max_c = P.leaf_batch.num_cslots, max_r = P.leaf_batch.num_rslots;
+    for (int q = 0; q < NL; ++q) {
+      const bool root = P.level_depth[q] == 0;
+      const int prec = root ? h->opt.root_prec : h->opt.iface_prec;
+      h->lev.push_back(upload_batch(h, P.level_batch[q], prec == RSD_PREC_FP32, s));
+      max_c = std::max(max_c, P.level_batch[q].num_cslots);
+      max_r = std::max(max_r, P.level_batch[q].num_rslots);
+      // Sigma products of this level, split into row chunks of 64
+      std::vector<int32_t> il, ir0, ia0, ia1;
+      for (const auto& it : P.level_sigma[q])
+        for (int32_t a0 = it.r0; a0 < it.r1; a0 += 64) {
+          il.push_back(it.leaf);
+          ir0.push_back(it.r0);
+          ia0.push_back(a0);
+          ia1.push_back(std::min(it.r1, a0 + 64));
+        }
+      SigmaLevelItems li;
+      li.count = int32_t(il.size());
+      li.leaf = upload(h, il, s);
+      li.r0 = upload(h, ir0, s);
+      li.a0 = upload(h, ia0, s);
+      li.a1 = upload(h, ia1, s);
+      h->lev_items.push_back(li);
+    }
+    const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
+    h->flags = dalloc<int32_t>(h, size_t(nflags));
+    h->e = dalloc<double>(h, std::max<size_t>(1, P.B.size()));
+    h->t = dalloc<double>(h, size_t(n));
+    h->rin = dalloc<double>(h, size_t(n));
+    h->zin = dalloc<double>(h, size_t(n));
+    h->cpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_c)) * kTile);
+    h->rpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_r)) * kTile);
+    hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    return RSD_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+// Dense set-up from the values of K (caller order, device pointer): Section 3.1's
+// exact sub-domain inverses, the Sigma_l blocks, and per interface level the
+// operator of Alg. 1 assembled and inverted.
+rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
+  try {
+    const Plan& P = h->P;
+    {
+      Timer tm(h, RSD_T_SETUP_EXTRACT, s);
+      hip_check(h, launch_gather(values, h->pmap, P.nnz, h->pval, s), "gather values");
+      const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
+      hip_check(h, hipMemsetAsync(h->flags, 0, size_t(nflags) * 4, s), "hipMemsetAsync flags");
+      hip_check(h, launch_sym_fill(h->leaf, s), "leaf fill");
+      hip_check(h, launch_sym_extract(h->leaf, h->prow, h->segA, h->pcol, h->pval, P.max_leaf, s),
+                "leaf extract");
+    }
+    // scratch of the sweeps: sized for the largest batch
+    size_t pb = 0, cb = 0, need_p = 0, need_c = 0;
+    sym_invert_scratch_bytes(h->leaf, h->group, &pb, &cb);
+    need_p = pb;
+    need_c = cb;
+    for (const auto& L : h->lev) {
+      sym_invert_scratch_bytes(L, h->group, &pb, &cb);
+      need_p = std::max(need_p, pb);
+      need_c = std::max(need_c, cb);
+    }
+    char* pbuf = dalloc<char>(h, need_p);
+    char* cbuf = dalloc<char>(h, need_c);
+    char* bbuf = dalloc<char>(h, need_c);
+    {
+      Timer tm(h, RSD_T_LEAF_INVERSE, s);
+      hip_check(h, launch_sym_invert(h->leaf, pbuf, cbuf, bbuf, h->flags, h->group, s),
+                "leaf inversion");
+    }
+    double* W = dalloc<double>(h, size_t(std::max<int64_t>(1, P.w_total)));
+    {
+      Timer tm(h, RSD_T_SIGMA, s);
+      hip_check(h, launch_sigma_w(h->leaf, h->sig, W, s), "sigma W");
+      hip_check(h, launch_sigma_s(h->sig, W, h->sigma, h->sigma_fp32, s), "sigma S");
+    }
+    int32_t* iflags = h->flags + P.leaf_node.size();
+    for (size_t q = 0; q < h->lev.size(); ++q) {
+      {
+        Timer tm(h, RSD_T_IFACE_ASSEMBLY, s);
+        int32_t maxn = 0;
+        for (int32_t v : P.level_batch[q].n) maxn = std::max(maxn, v);
+        hip_check(h, launch_sym_fill(h->lev[q], s), "iface fill");
+        hip_check(h, launch_sym_extract(h->lev[q], h->segB, h->segC, h->pcol, h->pval, maxn, s),
+                  "iface extract");
+        hip_check(h, launch_schur_assemble(h->lev[q], h->adj_ptr, h->adj_leaf, h->adj_pos,
+                                           h->B_off, h->sig_off_d, h->sigma, h->sigma_fp32,
+                                           P.n_leaf, s),
+                  "schur assembly");
+      }
+      {
+        Timer tm(h, RSD_T_IFACE_INVERSE, s);
+        hip_check(h, launch_sym_invert(h->lev[q], pbuf, cbuf, bbuf,
+                                       iflags + P.level_iface_begin[q], h->group, s),
+                  "interface inversion");
+      }
+    }
+    std::vector<int32_t> fl(P.leaf_node.size() + P.iface_node.size());
+    if (!fl.empty())
+      hip_check(h, hipMemcpyAsync(fl.data(), h->flags, fl.size() * 4, hipMemcpyDeviceToHost, s),
+                "flags D2H");
+    hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    dfree(h, W);
+    dfree(h, pbuf);
+    dfree(h, cbuf);
+    dfree(h, bbuf);
+    for (size_t i = 0; i < fl.size(); ++i)
+      if (fl[i]) {
+        char buf[256];
+        if (i < P.leaf_node.size())
+          std::snprintf(buf, sizeof(buf),
+                        "sub-domain matrix of leaf node %d is not positive definite "
+                        "(non-positive pivot near tile column %d)",
+                        P.leaf_node[i], fl[i] - 1);
+        else
+          std::snprintf(buf, sizeof(buf),
+                        "interface Schur complement of node %d is not positive definite "
+                        "(non-positive pivot near tile column %d)",
+                        P.iface_node[i - P.leaf_node.size()], fl[i] - 1);
+        h->err = buf;
+        return RSD_ERR_NOT_SPD;
+      }
+    return RSD_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+namespace {
+
+// z = M^{-1} r on internal-order vectors (Alg. 2 with exact interface solves):
+// every sub-domain solve; per interface level from the deepest: right-hand side g
+// of eq. (schur) -- the interface part of r minus the couplings to the already
+// computed values below it -- and the interface solve; then the back-substitution
+// of eq. (backSub) on every sub-domain at once.
+void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
+  const Plan& P = h->P;
+  const int64_t n = P.n, nl = P.n_leaf;
+  {
+    Timer tm(h, RSD_T_LEAF_APPLY, s);
+    hip_check(h, launch_symv(h->leaf, r, h->cpart, h->rpart, -1.0, nullptr, z, s), "leaf symv");
+  }
+  {
+    Timer tm(h, RSD_T_COUPLING, s);
+    // interface rows: q_B = r_B - K_{B,leaves} y
+    hip_check(h, launch_seg_spmv(nl, n - nl, h->prow, h->segA, h->pcol, h->pval, z, r, -1.0, z,
+                                 h->lpr, s), "condense");
+    hip_check(h, launch_fill(h->e, int64_t(P.B.size()), 0.0, s), "fill e");
+  }
+  for (size_t q = 0; q < h->lev.size(); ++q) {
+    {
+      Timer tm(h, RSD_T_COUPLING, s);
+      hip_check(h, launch_sigma_level(h->lev_items[q], h->sigma, h->sigma_fp32, h->sig_off_d,
+                                      h->B_off, h->B, z, h->e, s), "sigma level");
+      const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
+      hip_check(h, launch_level_rhs(r0, r1 - r0, nl, h->pcol, h->pval, h->segA, h->segB,
+                                    h->adj_ptr, h->adj_leaf, h->adj_pos, h->B_off, h->e, z, s),
+                "level rhs");
+    }
+    {
+      Timer tm(h, RSD_T_IFACE_APPLY, s);
+      hip_check(h, launch_symv(h->lev[q], z, h->cpart, h->rpart, -1.0, nullptr, z, s),
+                "interface symv");
+    }
+  }
+  {
+    Timer tm(h, RSD_T_COUPLING, s);
+    // leaf rows: r_l - K_{l,B} u_B
+    hip_check(h, launch_seg_spmv(0, nl, h->segA, h->prow + 1, h->pcol, h->pval, z, r, -1.0, h->t,
+                                 h->lpr, s), "back-substitution rhs");
+  }
+  {
+    Timer tm(h, RSD_T_LEAF_APPLY, s);
+    hip_check(h, launch_symv(h->leaf, h->t, h->cpart, h->rpart, -1.0, nullptr, z, s), "leaf symv");
+  }
+}
+
+void core_spmv(rsd_ctx* h, const double* x, const double* base, double alpha, double* y,
+               hipStream_t s) {
+  Timer tm(h, RSD_T_SPMV, s);
+  hip_check(h, launch_seg_spmv(0, h->P.n, h->prow, h->prow + 1, h->pcol, h->pval, x, base, alpha,
+                               y, h->lpr, s), "spmv");
+}
+
+void permute(rsd_ctx* h, const double* x, int64_t ldx, double* y, int64_t ldy, int inverse,
+             hipStream_t s) {
+  Timer tm(h, RSD_T_PERMUTE, s);
+  hip_check(h, launch_permute(x, ldx, y, ldy, h->perm, h->P.n, 1, inverse, s), "permute");
+}
+
+void ensure_krylov(rsd_ctx* h, int m) {
+  if (h->kry_m >= m && h->V) return;
+  for (double* p : {h->V, h->Z, h->w, h->hdev, h->tmp, h->part, h->scal, h->bint, h->xint})
+    dfree(h, p);
+  if (h->hhost) (void)hipHostFree(h->hhost);
+  const size_t n = size_t(h->P.n);
+  h->V = dalloc<double>(h, n * size_t(m + 1));
+  h->Z = dalloc<double>(h, n * size_t(m));
+  h->w = dalloc<double>(h, n);
+  h->hdev = dalloc<double>(h, size_t(m + 2));
+  h->tmp = dalloc<double>(h, size_t(m + 2));
+  h->part = dalloc<double>(h, size_t(mdot_blocks(h->P.n)) * size_t(m + 2));
+  h->scal = dalloc<double>(h, 16);
+  h->bint = dalloc<double>(h, n);
+  h->xint = dalloc<double>(h, n);
+  hip_check(h, hipHostMalloc((void**)&h->hhost, sizeof(double) * size_t(m + 16)), "hipHostMalloc");
+  h->kry_m = m;
+}
+
+double dev_norm(rsd_ctx* h, const double* v, double* out_dev, hipStream_t s) {
+  {
+    Timer tm(h, RSD_T_KRYLOV, s);
+    hip_check(h, launch_mdot(v, h->P.n, 1, v, h->P.n, h->part, out_dev, 1, s), "norm");
+  }
+  hip_check(h, hipMemcpyAsync(h->hhost, out_dev, 8, hipMemcpyDeviceToHost, s), "D2H");
+  hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+  return h->hhost[0];
+}
+
+// Right-preconditioned flexible GMRES(m) in internal order; x (internal) holds the
+// initial guess.  Returns the status of this right-hand side.
+rsd_status fgmres_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_options& o,
+                      rsd_solve_info* info, hipStream_t s) {
+  const int64_t n = h->P.n;
+  const int m = o.restart;
+  double* beta_d = h->scal;      // scal[0]: ||r||, scal[1]: ||b||
+  const double bnorm = dev_norm(h, b, h->scal + 1, s);
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) {
+    info->iterations = 0;
+    info->relres = NAN;
+    return RSD_ERR_BREAKDOWN;
+  }
+  if (bnorm == 0.0) {
+    hip_check(h, launch_fill(x, n, 0.0, s), "zero x");
+    info->iterations = 0;
+    info->relres = 0.0;
+    return RSD_OK;
+  }
+  const double tol = o.rtol * bnorm;
+  double* r = h->w;
+  core_spmv(h, x, b, -1.0, r, s);
+  double beta = dev_norm(h, r, beta_d, s);
+  int its = 0;
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  for (;;) {
+    if (beta <= tol) {
+      info->iterations = its;
+      info->relres = beta / bnorm;
+      return RSD_OK;
+    }
+    if (!(beta == beta)) {
+      info->iterations = its;
+      info->relres = NAN;
+      return RSD_ERR_BREAKDOWN;
+    }
+    if (its >= o.maxit) {
+      info->iterations = its;
+      info->relres = beta / bnorm;
+      return RSD_ERR_NOT_CONVERGED;
+    }
+    {
+      Timer tm(h, RSD_T_KRYLOV, s);
+      hip_check(h, launch_scale_div(r, beta_d, h->V, n, s), "v0");
+    }
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool bad = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V + size_t(j) * n;
+      double* zj = h->Z + size_t(j) * n;
+      core_apply(h, vj, zj, s);
+      core_spmv(h, zj, nullptr, 1.0, h->w, s);
+      {
+        Timer tm(h, RSD_T_KRYLOV, s);
+        // classical Gram-Schmidt, twice
+        hip_check(h, launch_mdot(h->V, n, j + 1, h->w, n, h->part, h->hdev, 0, s), "cgs dots");
+        hip_check(h, launch_gemv_acc(h->V, n, j + 1, h->hdev, -1.0, h->w, n, s), "cgs update");
+        hip_check(h, launch_mdot(h->V, n, j + 1, h->w, n, h->part, h->tmp, 0, s), "cgs2 dots");
+        hip_check(h, launch_gemv_acc(h->V, n, j + 1, h->tmp, -1.0, h->w, n, s), "cgs2 update");
+        hip_check(h, launch_small_add(h->hdev, h->tmp, j + 1, s), "h add");
+        hip_check(h, launch_mdot(h->w, n, 1, h->w, n, h->part, h->hdev + j + 1, 1, s), "norm");
+        hip_check(h, launch_scale_div(h->w, h->hdev + j + 1, h->V + size_t(j + 1) * n, n, s),
+                  "normalise");
+      }
+      hip_check(h, hipMemcpyAsync(h->hhost, h->hdev, sizeof(double) * size_t(j + 2),
+                                  hipMemcpyDeviceToHost, s), "h D2H");
+      hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+      double* hc = &H[size_t(j) * (m + 1)];
+      for (int i = 0; i <= j + 1; ++i) {
+        hc[i] = h->hhost[i];
+        if (!(hc[i] == hc[i]) || std::isinf(hc[i])) bad = true;
+      }
+      if (bad) break;
+      const double hnext = hc[j + 1];
+      for (int i = 0; i < j; ++i) {
+        const double t0 = cs[i] * hc[i] + sn[i] * hc[i + 1];
+        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+        hc[i] = t0;
+      }
+      const double den = std::hypot(hc[j], hc[j + 1]);
+      cs[j] = den > 0 ? hc[j] / den : 1.0;
+      sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
+      hc[j] = den;
+      hc[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= tol || its >= o.maxit || hnext == 0.0) break;
+    }
+    if (bad) {
+      info->iterations = its;
+      info->relres = NAN;
+      return RSD_ERR_BREAKDOWN;
+    }
+    // y = R^{-1} g (upper triangular k x k)
+    for (int i = k - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int c = i + 1; c < k; ++c) v -= H[size_t(c) * (m + 1) + i] * y[c];
+      const double d = H[size_t(i) * (m + 1) + i];
+      y[i] = d != 0.0 ? v / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) h->hhost[i] = y[i];
+    hip_check(h, hipMemcpyAsync(h->tmp, h->hhost, sizeof(double) * size_t(k),
+                                hipMemcpyHostToDevice, s), "y H2D");
+    {
+      Timer tm(h, RSD_T_KRYLOV, s);
+      hip_check(h, launch_gemv_acc(h->Z, n, k, h->tmp, 1.0, x, n, s), "x update");
+    }
+    core_spmv(h, x, b, -1.0, r, s);
+    beta = dev_norm(h, r, beta_d, s);
+  }
+}
+
+// Preconditioned CG in internal order (x holds the initial guess).
+rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_options& o,
+                   rsd_solve_info* info, hipStream_t s) {
+  const int64_t n = h->P.n;
+  // columns of V: r, z, p, q ; scalars: scal[0..1] rz (ping-pong), scal[2] pq, scal[3] norm
+  double* r = h->V;
+  double* z = h->V + n;
+  double* p = h->V + 2 * n;
+  double* q = h->V + 3 * n;
+  const double bnorm = dev_norm(h, b, h->scal + 4, s);
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) {
+    info->iterations = 0;
+    info->relres = NAN;
+    return RSD_ERR_BREAKDOWN;
+  }
+  if (bnorm == 0.0) {
+    hip_check(h, launch_fill(x, n, 0.0, s), "zero x");
+    info->iterations = 0;
+    info->relres = 0.0;
+    return RSD_OK;
+  }
+  const double tol = o.rtol * bnorm;
+  core_spmv(h, x, b, -1.0, r, s);
+  double rn = dev_norm(h, r, h->scal + 3, s);
+  int its = 0;
+  int cur = 0;
+  if (rn <= tol) {
+    info->iterations = 0;
+    info->relres = rn / bnorm;
+    return RSD_OK;
+  }
+  core_apply(h, r, z, s);
+  {
+    Timer tm(h, RSD_T_KRYLOV, s);
+    hip_check(h, launch_mdot(r, n, 1, z, n, h->part, h->scal + cur, 0, s), "rz");
+    hip_check(h, hipMemcpyAsync(p, z, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, s),
+              "p = z");
+  }
+  for (;;) {
+    core_spmv(h, p, nullptr, 1.0, q, s);
+    {
+      Timer tm(h, RSD_T_KRYLOV, s);
+      hip_check(h, launch_mdot(p, n, 1, q, n, h->part, h->scal + 2, 0, s), "pq");
+      hip_check(h, launch_axpy_ratio(x, p, h->scal + cur, h->scal + 2, 1.0, x, n, s), "x");
+      hip_check(h, launch_axpy_ratio(r, q, h->scal + cur, h->scal + 2, -1.0, r, n, s), "r");
+      hip_check(h, launch_mdot(r, n, 1, r, n, h->part, h->scal + 3, 1, s), "|r|");
+    }
+    hip_check(h, hipMemcpyAsync(h->hhost, h->scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s),
+              "D2H");
+    hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    ++its;
+    rn = h->hhost[3];
+    const double pq = h->hhost[2];
+    if (!(rn == rn) || !(pq > 0.0) || std::isinf(rn)) {
+      info->iterations = its;
+      info->relres = NAN;
+      return RSD_ERR_BREAKDOWN;
+    }
+    if (rn <= tol) {
+      core_spmv(h, x, b, -1.0, r, s);
+      const double rt = dev_norm(h, r, h->scal + 3, s);
+      if (rt <= tol) {
+        info->iterations = its;
+        info->relres = rt / bnorm;
+        return RSD_OK;
+      }
+    }
+    if (its >= o.maxit) {
+      core_spmv(h, x, b, -1.0, h->w, s);
+      info->iterations = its;
+      info->relres = dev_norm(h, h->w, h->scal + 5, s) / bnorm;
+      return RSD_ERR_NOT_CONVERGED;
+    }
+    core_apply(h, r, z, s);
+    {
+      Timer tm(h, RSD_T_KRYLOV, s);
+      const int nxt = 1 - cur;
+      hip_check(h, launch_mdot(r, n, 1, z, n, h->part, h->scal + nxt, 0, s), "rz");
+      hip_check(h, launch_axpy_ratio(z, p, h->scal + nxt, h->scal + cur, 1.0, p, n, s), "p");
+      cur = nxt;
+    }
+  }
+}
+
+}  // namespace
+
+rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, double* z,
+                        int64_t ldz, hipStream_t s) {
+  try {
+    for (int j = 0; j < nrhs; ++j) {
+      permute(h, r + size_t(j) * ldr, h->P.n, h->rin, h->P.n, 0, s);
+      core_apply(h, h->rin, h->zin, s);
+      permute(h, h->zin, h->P.n, z + size_t(j) * ldz, h->P.n, 1, s);
+    }
+    return RSD_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, double* y,
+                       int64_t ldy, hipStream_t s) {
+  try {
+    for (int j = 0; j < nrhs; ++j) {
+      permute(h, x + size_t(j) * ldx, h->P.n, h->rin, h->P.n, 0, s);
+      core_spmv(h, h->rin, nullptr, 1.0, h->zin, s);
+      permute(h, h->zin, h->P.n, y + size_t(j) * ldy, h->P.n, 1, s);
+    }
+    return RSD_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, double* x,
+                        int64_t ldx, const rsd_solve_options* opt, rsd_solve_info* info,
+                        hipStream_t s) {
+  try {
+    rsd_solve_options o;
+    if (opt) {
+      o = *opt;
+    } else {
+      o.method = RSD_SOLVER_FGMRES;
+      o.restart = 30;
+      o.maxit = 500;
+      o.rtol = 1e-10;
+      o.use_x0 = 0;
+    }
+    ensure_krylov(h, o.method == RSD_SOLVER_PCG ? 4 : o.restart);
+    rsd_status worst = RSD_OK;
+    for (int j = 0; j < nrhs; ++j) {
+      rsd_solve_info inf{0, 0.0, RSD_OK};
+      permute(h, b + size_t(j) * ldb, h->P.n, h->bint, h->P.n, 0, s);
+      if (o.use_x0)
+        permute(h, x + size_t(j) * ldx, h->P.n, h->xint, h->P.n, 0, s);
+      else
+        hip_check(h, launch_fill(h->xint, h->P.n, 0.0, s), "x0");
+      const rsd_status st = o.method == RSD_SOLVER_PCG ? pcg_one(h, h->bint, h->xint, o, &inf, s)
+                                                       : fgmres_one(h, h->bint, h->xint, o, &inf, s);
+      permute(h, h->xint, h->P.n, x + size_t(j) * ldx, h->P.n, 1, s);
+      inf.status = st;
+      if (info) info[j] = inf;
+      if (st == RSD_ERR_BREAKDOWN || (st != RSD_OK && worst == RSD_OK)) worst = st;
+    }
+    hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (worst == RSD_ERR_NOT_CONVERGED) h->err = "Krylov iteration reached maxit";
+    if (worst == RSD_ERR_BREAKDOWN) h->err = "NaN/Inf or breakdown in the Krylov recurrence";
+    return worst;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
+  try {
+    if (h->opt.timing) {
+      hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+      fold_timings(h);
+    }
+    std::memset(out, 0, sizeof(*out));
+    fill_analysis(h->P, &out->analysis);
+    for (int i = 0; i < RSD_T_COUNT; ++i) {
+      out->time_ms[i] = h->time_ms[i];
+      out->launches[i] = h->launches[i];
+    }
+    out->host_analysis_ms = h->host_ms;
+    out->device_bytes = h->device_bytes;
+    if (reset) {
+      std::memset(h->time_ms, 0, sizeof(h->time_ms));
+      std::memset(h->launches, 0, sizeof(h->launches));
+    }
+    return RSD_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
+}
+
+void engine_free(rsd_ctx* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  for (auto& p : h->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  for (auto& p : h->allocs) (void)hipFree(p.first);
+  h->allocs.clear();
+  if (h->hhost) (void)hipHostFree(h->hhost);
+  h->hhost = nullptr;
+}
+
+}  // namespace rsd

@@ -1,0 +1,76 @@
+// The RSD engine: device state of one handle, set-up, apply, SpMV and Krylov drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rsd.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct rsd_ctx {
+  rsd::Plan P;
+  rsd_options opt{};
+  std::string err;
+  int device = 0;
+
+  // every device allocation of the handle
+  std::vector<std::pair<void*, size_t>> allocs;
+  int64_t device_bytes = 0;
+
+  // K in internal order and the index structures of the plan
+  int64_t *prow = nullptr, *segA = nullptr, *segB = nullptr, *segC = nullptr, *pmap = nullptr;
+  int32_t *pcol = nullptr, *perm = nullptr;
+  double* pval = nullptr;
+  int64_t *B_off = nullptr, *adj_ptr = nullptr, *sig_off_d = nullptr;
+  int32_t *B = nullptr, *adj_leaf = nullptr, *adj_pos = nullptr;
+  rsd::SigmaArgs sig{};
+  void* sigma = nullptr;
+  int sigma_fp32 = 0;
+  rsd::DevBatch leaf{};
+  std::vector<rsd::DevBatch> lev;
+  std::vector<rsd::SigmaLevelItems> lev_items;
+  int32_t* flags = nullptr;  // one per leaf, then one per interface
+  int lpr = 16;
+  int group = 2;             // pivot tiles per sweep step
+
+  // apply work vectors (internal order)
+  double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;
+  double *cpart = nullptr, *rpart = nullptr;
+
+  // Krylov work space (grown on demand)
+  int kry_m = 0;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *hdev = nullptr, *tmp = nullptr,
+         *part = nullptr, *scal = nullptr, *bint = nullptr, *xint = nullptr;
+  double* hhost = nullptr;   // pinned
+
+  // timing
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double time_ms[RSD_T_COUNT] = {};
+  int64_t launches[RSD_T_COUNT] = {};
+  double host_ms = 0.0;
+};
+
+namespace rsd {
+
+// All return RSD_OK or an error with h->err set.
+rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier,
+                       const rsd_options* opt, hipStream_t s);
+rsd_status engine_numeric(rsd_ctx* h, const double* values_dev, hipStream_t s);
+rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, double* z,
+                        int64_t ldz, hipStream_t s);
+rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, double* y,
+                       int64_t ldy, hipStream_t s);
+rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, double* x,
+                        int64_t ldx, const rsd_solve_options* opt, rsd_solve_info* info,
+                        hipStream_t s);
+rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s);
+void engine_free(rsd_ctx* h);
+void fill_analysis(const Plan& P, rsd_analysis* a);
+
+}  // namespace rsd

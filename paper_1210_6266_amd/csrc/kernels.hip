@@ -1,0 +1,873 @@
+// HIP kernels for gfx950 (CDNA4): sparse couplings, batched dense symmetric
+// blocks (in-place inversion on MFMA, symmetric products), Schur complements of
+// the sub-domain hierarchy, and the Krylov vector kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace rsd {
+
+namespace {
+
+constexpr int TS = 64;            // tile side
+constexpr int TT = TS * TS;       // tile elements
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int64_t tri(int64_t I) { return I * (I + 1) / 2; }
+__device__ __forceinline__ int64_t tile_index(int I, int J) { return tri(I) + J; }
+
+// (I, J) of the t-th lower tile in row-major tile order
+__device__ __forceinline__ void tile_ij(int64_t t, int* I, int* J) {
+  int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (tri(i) > t) --i;
+  while (tri(i + 1) <= t) ++i;
+  *I = i;
+  *J = int(t - tri(i));
+}
+
+// element (r, c) of the symmetric matrix whose lower tiles start at base
+template <typename T>
+__device__ __forceinline__ T sym_elem(const T* base, int r, int c) {
+  const int I = r / TS, J = c / TS;
+  if (I >= J) return base[tile_index(I, J) * TT + (r % TS) + (c % TS) * TS];
+  return base[tile_index(J, I) * TT + (c % TS) + (r % TS) * TS];
+}
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// 64 x 64 block product on MFMA 16x16x4 by 4 waves (each wave a 32 x 32 quadrant):
+// acc += A(64 x K) * B(K x 64).  A(r, k) = lda(r, k), B(k, c) = ldb(k, c).
+// The position of accumulator element acc[bi][bj][v] is given by acc_pos<T>.
+template <typename T, int K, typename LA, typename LB>
+__device__ __forceinline__ void mfma_block(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 8
+  for (int k = 0; k < K; k += 4) {
+    const T a0 = lda(r0 + li, k + lk), a1 = lda(r0 + 16 + li, k + lk);
+    const T b0 = ldb(k + lk, c0 + li), b1 = ldb(k + lk, c0 + 16 + li);
+    acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+  }
+}
+
+// Position in the 64 x 64 block of accumulator element acc[bi][bj][v].  Both
+// instructions take A(i, k) from lane i + 16 k and B(k, j) from lane j + 16 k; the
+// 16 x 16 result lies in lane j + 16 g, element v, with row i = 4 g + v for FP32 but
+// row i = 4 v + g for FP64 (checked on gfx950).
+template <typename T>
+__device__ __forceinline__ void acc_pos(int bi, int bj, int v, int* r, int* c) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int i = (sizeof(T) == 8) ? 4 * v + g : 4 * g + v;
+  *r = (w >> 1) * 32 + 16 * bi + i;
+  *c = (w & 1) * 32 + 16 * bj + (lane & 15);
+}
+
+// ================================================================ sparse / vectors
+__global__ void k_gather(const double* __restrict__ src, const int64_t* __restrict__ map,
+                         int64_t count, double* __restrict__ dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[map[i]];
+}
+
+__global__ void k_permute(const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
+                          int64_t ldy, const int32_t* __restrict__ perm, int64_t n,
+                          int inverse) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  if (inverse)
+    y[int64_t(perm[i]) + j * ldy] = x[i + j * ldx];   // internal -> caller
+  else
+    y[i + j * ldy] = x[int64_t(perm[i]) + j * ldx];   // caller -> internal
+}
+
+template <int LPR>
+__global__ __launch_bounds__(kBlock) void k_seg_spmv(int64_t row0, int64_t nrows,
+                                                     const int64_t* __restrict__ s0,
+                                                     const int64_t* __restrict__ s1,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ base,
+                                                     double alpha, double* __restrict__ y) {
+  const int64_t gid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t lr = gid / LPR;
+  const int lane = int(gid % LPR);
+  if (lr >= nrows) return;
+  const int64_t row = row0 + lr;
+  double s = 0.0;
+  const int64_t e = s1[row];
+  for (int64_t k = s0[row] + lane; k < e; k += LPR) s += val[k] * x[col[k]];
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+  if (lane == 0) y[row] = (base ? base[row] : 0.0) + alpha * s;
+}
+
+__global__ void k_fill(double* p, int64_t count, double v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// ================================================================ dense batches
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sym_fill(T* tiles, const int64_t* tile_off,
+                                                     const int32_t* n_arr,
+                                                     const int32_t* nt_arr) {
+  const int m = blockIdx.y;
+  const int nt = nt_arr[m];
+  const int64_t t = blockIdx.x;
+  if (t >= tri(nt)) return;
+  int I, J;
+  tile_ij(t, &I, &J);
+  T* p = tiles + tile_off[m] + t * TT;
+  const int n = n_arr[m];
+  for (int e = threadIdx.x; e < TT; e += kBlock) {
+    const int r = I * TS + (e % TS), c = J * TS + (e / TS);
+    p[e] = (r == c && r >= n) ? T(1) : T(0);   // padding: identity
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sym_extract(T* tiles, const int64_t* tile_off,
+                                                        const int32_t* n_arr,
+                                                        const int64_t* vec_off,
+                                                        const int64_t* s0, const int64_t* s1,
+                                                        const int32_t* pcol,
+                                                        const double* pval) {
+  const int m = blockIdx.y;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int n = n_arr[m];
+  if (i >= n) return;
+  const int64_t off = vec_off[m];
+  const int64_t r = off + i;
+  T* base = tiles + tile_off[m];
+  for (int64_t k = s0[r]; k < s1[r]; ++k) {
+    const int64_t j = int64_t(pcol[k]) - off;
+    if (j < 0 || j >= n) continue;
+    const int I = i / TS, J = int(j) / TS;
+    if (I < J) continue;
+    base[tile_index(I, J) * TT + (i % TS) + (j % TS) * TS] = T(pval[k]);
+  }
+}
+
+// ---- blocked symmetric sweep (in-place inversion) --------------------------------------
+// Step over pivot tile columns [c0, c0 + g): with the pivot block P = A_pp^{-1},
+//   A_ij -= A_ip P A_pj  (i, j outside the pivot group),
+//   A_ip <- A_ip P,  A_pj <- P A_pj,  A_pp <- -P.
+// After all steps the tiles hold -A^{-1}.
+
+// (1) pivot block: scalar sweeps of the G*64 x G*64 block held in registers
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_pivot(T* tiles, const int64_t* tile_off,
+                                                        const int32_t* nt_arr, int c0, T* pbuf,
+                                                        int32_t* flags) {
+  constexpr int PB = G * TS, R = PB / 16;
+  const int m = blockIdx.x;
+  const int nt = nt_arr[m];
+  if (c0 >= nt) return;
+  const int g = min(G, nt - c0), pbm = g * TS;
+  T* base = tiles + tile_off[m];
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  T a[R][R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int gi = ty * R + i, gj = tx * R + j;
+      if (gi < pbm && gj < pbm)
+        a[i][j] = sym_elem(base, c0 * TS + gi, c0 * TS + gj);
+      else
+        a[i][j] = (gi == gj) ? T(1) : T(0);
+    }
+  __shared__ T colbuf[2][PB];
+  int fail = 0;
+  for (int p = 0; p < pbm; ++p) {
+    T* cb = colbuf[p & 1];
+    if (tx == p / R) {   // owner of column p publishes it (select keeps a[][] in VGPRs)
+      const int pj = p % R;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        T v = a[i][0];
+#pragma unroll
+        for (int j = 1; j < R; ++j) v = (j == pj) ? a[i][j] : v;
+        cb[ty * R + i] = v;
+      }
+    }
+    __syncthreads();
+    T d = cb[p];
+    if (!(d > T(0)) || !(d < T(INFINITY))) {
+      fail = 1;
+      d = T(1);
+    }
+    const T inv = T(1) / d;
+    T ci[R], cj[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) ci[i] = cb[ty * R + i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) cj[j] = cb[tx * R + j];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int gi = ty * R + i, gj = tx * R + j;
+        if (gi == p) {
+          a[i][j] = (gj == p) ? -inv : cj[j] * inv;
+        } else if (gj == p) {
+          a[i][j] = ci[i] * inv;
+        } else {
+          a[i][j] -= (ci[i] * cj[j]) * inv;
+        }
+      }
+  }
+  T* P = pbuf + int64_t(m) * PB * PB;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int gi = ty * R + i, gj = tx * R + j;
+      P[gi + gj * PB] = -a[i][j];
+      if (gi < pbm && gj < pbm) {
+        const int I = c0 + gi / TS, J = c0 + gj / TS;
+        if (I >= J) base[tile_index(I, J) * TT + (gi % TS) + (gj % TS) * TS] = a[i][j];
+      }
+    }
+  if (fail && threadIdx.x == 0) flags[m] = c0 + 1;
+}
+
+// (2) panel: C_i = A_{i,p} (64 x PB), B_i = C_i P
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_panel(const T* tiles, const int64_t* tile_off,
+                                                        const int32_t* nt_arr, int c0,
+                                                        const T* pbuf, T* cbuf, T* bbuf,
+                                                        int64_t stride) {
+  constexpr int PB = G * TS;
+  const int m = blockIdx.y, i = blockIdx.x;
+  const int nt = nt_arr[m];
+  if (c0 >= nt || i >= nt) return;
+  const int g = min(G, nt - c0), pbm = g * TS;
+  if (i >= c0 && i < c0 + g) return;
+  const T* base = tiles + tile_off[m];
+  __shared__ T C[TS * PB];
+  for (int e = threadIdx.x; e < TS * PB; e += kBlock) {
+    const int r = e % TS, cc = e / TS;
+    T v = T(0);
+    if (cc < pbm) {
+      const int J = c0 + cc / TS;
+      v = (i > J) ? base[tile_index(i, J) * TT + r + (cc % TS) * TS]
+                  : base[tile_index(J, i) * TT + (cc % TS) + r * TS];
+    }
+    C[e] = v;
+  }
+  __syncthreads();
+  T* Cout = cbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
+  for (int e = threadIdx.x; e < TS * PB; e += kBlock) Cout[e] = C[e];
+  const T* P = pbuf + int64_t(m) * PB * PB;
+  T* Bout = bbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
+#pragma unroll
+  for (int cb = 0; cb < G; ++cb) {
+    typename Mfma<T>::v4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+    mfma_block<T, PB>([&](int r, int k) { return C[r + k * TS]; },
+                      [&](int k, int c) { return P[k + (cb * TS + c) * PB]; }, acc);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int r, c;
+          acc_pos<T>(bi, bj, v, &r, &c);
+          Bout[r + (cb * TS + c) * TS] = acc[bi][bj][v];
+        }
+  }
+}
+
+// (3) update of every lower tile outside the pivot group
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_update(T* tiles, const int64_t* tile_off,
+                                                         const int32_t* nt_arr, int c0,
+                                                         const T* cbuf, const T* bbuf,
+                                                         int64_t stride) {
+  constexpr int PB = G * TS;
+  const int m = blockIdx.y;
+  const int nt = nt_arr[m];
+  const int64_t t = blockIdx.x;
+  if (c0 >= nt || t >= tri(nt)) return;
+  int i, j;
+  tile_ij(t, &i, &j);
+  const int g = min(G, nt - c0);
+  const bool in_i = i >= c0 && i < c0 + g, in_j = j >= c0 && j < c0 + g;
+  if (in_i && in_j) return;
+  T* A = tiles + tile_off[m] + t * TT;
+  const T* Bb = bbuf + int64_t(m) * stride;
+  const T* Cb = cbuf + int64_t(m) * stride;
+  if (in_i) {   // row of the pivot group, j < c0:  A_ij <- (B_j[:, i block])^T
+    const T* Bj = Bb + int64_t(j) * TS * PB + int64_t(i - c0) * TS * TS;
+    for (int e = threadIdx.x; e < TT; e += kBlock) {
+      const int r = e % TS, c = e / TS;
+      A[e] = Bj[c + r * TS];
+    }
+    return;
+  }
+  if (in_j) {   // column of the pivot group, i >= c0 + g:  A_ij <- B_i[:, j block]
+    const T* Bi = Bb + int64_t(i) * TS * PB + int64_t(j - c0) * TS * TS;
+    for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Bi[e];
+    return;
+  }
+  const T* Bi = Bb + int64_t(i) * TS * PB;
+  const T* Cj = Cb + int64_t(j) * TS * PB;
+  typename Mfma<T>::v4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+  mfma_block<T, PB>([&](int r, int k) { return Bi[r + k * TS]; },
+                    [&](int k, int c) { return Cj[c + k * TS]; }, acc);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r, c;
+        acc_pos<T>(bi, bj, v, &r, &c);
+        A[r + c * TS] -= acc[bi][bj][v];
+      }
+}
+
+// ---- symmetric products y = base + alpha A x -------------------------------------------
+// phase 1: one work item = tiles (I, J), I in [I0, I1), of strip J.  Column parts
+// (A_IJ^T x_I, and A_JJ x_J on the diagonal tile) accumulate per item; row parts
+// A_IJ x_J (I > J) go to their own slot.  No atomics: phase 2 sums slots in order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_symv1(
+    const T* __restrict__ tiles, const int64_t* __restrict__ tile_off,
+    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off,
+    const int32_t* __restrict__ item_mat, const int32_t* __restrict__ item_J,
+    const int32_t* __restrict__ item_I0, const int32_t* __restrict__ item_I1,
+    const int64_t* __restrict__ item_cslot, const int64_t* __restrict__ rslot_off,
+    const double* __restrict__ x, double* __restrict__ cpart, double* __restrict__ rpart) {
+  const int it = blockIdx.x;
+  const int m = item_mat[it], J = item_J[it], I0 = item_I0[it], I1 = item_I1[it];
+  const int n = n_arr[m];
+  const int64_t xo = vec_off[m];
+  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  double xj[16], acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = J * TS + cg * 16 + c;
+    xj[c] = col < n ? x[xo + col] : 0.0;
+    acc[c] = 0.0;
+  }
+  __shared__ double rp[2][4][TS];
+  __shared__ double red[TS][TS + 1];
+  const T* base = tiles + tile_off[m];
+  for (int I = I0; I < I1; ++I) {
+    const int row = I * TS + r;
+    const double xi = row < n ? x[xo + row] : 0.0;
+    const T* tl = base + tile_index(I, J) * TT + r + cg * 16 * TS;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double a = double(tl[c * TS]);
+      acc[c] += a * xi;
+      s += a * xj[c];
+    }
+    if (I > J) {
+      rp[I & 1][cg][r] = s;
+      __syncthreads();
+      if (threadIdx.x < TS) {
+        const double v = rp[I & 1][0][r] + rp[I & 1][1][r] + rp[I & 1][2][r] + rp[I & 1][3][r];
+        rpart[(rslot_off[m] + tri(I - 1) + J) * TS + r] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) red[cg * 16 + c][r] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    double s = 0.0;
+    for (int k = 0; k < TS; ++k) s += red[threadIdx.x][k];
+    cpart[item_cslot[it] * TS + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_symv2(const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
+                        const int64_t* __restrict__ vec_off,
+                        const int64_t* __restrict__ cstrip_base,
+                        const int64_t* __restrict__ cstrip_ptr,
+                        const int64_t* __restrict__ rslot_off, const double* __restrict__ cpart,
+                        const double* __restrict__ rpart, double alpha,
+                        const double* __restrict__ base, double* __restrict__ y) {
+  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x;
+  if (I >= nt_arr[m]) return;
+  const int row = I * TS + r;
+  if (row >= n_arr[m]) return;
+  double s = 0.0;
+  const int64_t sb = cstrip_base[m] + I;
+  for (int64_t c = cstrip_ptr[sb]; c < cstrip_ptr[sb + 1]; ++c) s += cpart[c * TS + r];
+  const int64_t rb = rslot_off[m] + tri(I - 1);
+  for (int Jc = 0; Jc < I; ++Jc) s += rpart[(rb + Jc) * TS + r];
+  const int64_t o = vec_off[m] + row;
+  y[o] = (base ? base[o] : 0.0) + alpha * s;
+}
+
+// ================================================================ Schur complements
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sigma_w(const T* __restrict__ tiles,
+                                                    const int64_t* __restrict__ tile_off,
+                                                    SigmaArgs a, double* __restrict__ W) {
+  const int l = blockIdx.y, b = blockIdx.x;
+  const int64_t m = a.B_off[l + 1] - a.B_off[l];
+  if (b >= m) return;
+  const int64_t s = a.shell_off[l + 1] - a.shell_off[l];
+  const T* base = tiles + tile_off[l];
+  const int64_t f = a.B_off[l] + b;
+  double* Wc = W + a.w_off[l] + int64_t(b) * s;
+  const int32_t* sh = a.shell + a.shell_off[l];
+  for (int64_t si = threadIdx.x; si < s; si += kBlock) {
+    const int i = sh[si];
+    double v = 0.0;
+    for (int64_t e = a.kcol_ptr[f]; e < a.kcol_ptr[f + 1]; ++e)
+      v -= double(sym_elem(base, i, a.kcol_row[e])) * a.pval[a.kcol_val[e]];  // tiles hold -K^-1
+    Wc[si] = v;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_sigma_s(SigmaArgs a, const double* __restrict__ W,
+                                                    S* __restrict__ sigma) {
+  const int l = blockIdx.y, b = blockIdx.x;
+  const int64_t m = a.B_off[l + 1] - a.B_off[l];
+  if (b >= m) return;
+  const int64_t s = a.shell_off[l + 1] - a.shell_off[l];
+  const double* Wc = W + a.w_off[l] + int64_t(b) * s;
+  S* out = sigma + a.sig_off[l] + int64_t(b) * m;
+  for (int64_t r = threadIdx.x; r < m; r += kBlock) {
+    const int64_t f = a.B_off[l] + r;
+    double v = 0.0;
+    for (int64_t e = a.krow_ptr[f]; e < a.krow_ptr[f + 1]; ++e)
+      v += a.pval[a.krow_val[e]] * Wc[a.krow_col[e]];
+    out[r] = S(v);
+  }
+}
+
+template <typename T, typename S>
+__global__ __launch_bounds__(kBlock) void k_schur_assemble(
+    T* tiles, const int64_t* tile_off, const int32_t* n_arr, const int32_t* nt_arr,
+    const int64_t* vec_off, const int64_t* __restrict__ adj_ptr,
+    const int32_t* __restrict__ adj_leaf, const int32_t* __restrict__ adj_pos,
+    const int64_t* __restrict__ B_off, const int64_t* __restrict__ sig_off,
+    const S* __restrict__ sigma, int64_t n_leaf) {
+  const int m = blockIdx.y;
+  const int64_t t = blockIdx.x;
+  if (t >= tri(nt_arr[m])) return;
+  int I, J;
+  tile_ij(t, &I, &J);
+  const int n = n_arr[m];
+  T* tl = tiles + tile_off[m] + t * TT;
+  for (int e = threadIdx.x; e < TT; e += kBlock) {
+    const int p = I * TS + (e % TS), q = J * TS + (e / TS);
+    if (p >= n || q >= n) continue;
+    const int64_t P = vec_off[m] + p - n_leaf, Q = vec_off[m] + q - n_leaf;
+    int64_t ip = adj_ptr[P];
+    const int64_t ep = adj_ptr[P + 1];
+    int64_t iq = adj_ptr[Q];
+    const int64_t eq = adj_ptr[Q + 1];
+    double v = double(tl[e]);
+    while (ip < ep && iq < eq) {   // leaves adjacent to both dofs (lists sorted by leaf)
+      const int lp = adj_leaf[ip], lq = adj_leaf[iq];
+      if (lp < lq) {
+        ++ip;
+      } else if (lq < lp) {
+        ++iq;
+      } else {
+        const int64_t mm = B_off[lp + 1] - B_off[lp];
+        v -= double(sigma[sig_off[lp] + adj_pos[ip] + int64_t(adj_pos[iq]) * mm]);
+        ++ip;
+        ++iq;
+      }
+    }
+    tl[e] = T(v);
+  }
+}
+
+// ================================================================ apply helpers
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_sigma_level(
+    const int32_t* __restrict__ it_leaf, const int32_t* __restrict__ it_r0,
+    const int32_t* __restrict__ it_a0, const int32_t* __restrict__ it_a1,
+    const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
+    const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
+    const double* __restrict__ z, double* __restrict__ e) {
+  const int it = blockIdx.x;
+  const int l = it_leaf[it], r0 = it_r0[it], a0 = it_a0[it], a1 = it_a1[it];
+  const int64_t m = B_off[l + 1] - B_off[l];
+  const S* Sg = sigma + sig_off[l];
+  const int32_t* Bl = B + B_off[l];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a = a0 + lane;
+  double s = 0.0;
+  if (a < a1)
+    for (int b = w; b < r0; b += 4) s += double(Sg[a + int64_t(b) * m]) * z[Bl[b]];
+  __shared__ double red[4][64];
+  red[w][lane] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && a0 + int(threadIdx.x) < a1)
+    e[B_off[l] + a0 + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_level_rhs(
+    int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* __restrict__ pcol,
+    const double* __restrict__ pval, const int64_t* __restrict__ segA,
+    const int64_t* __restrict__ segB, const int64_t* __restrict__ adj_ptr,
+    const int32_t* __restrict__ adj_leaf, const int32_t* __restrict__ adj_pos,
+    const int64_t* __restrict__ B_off, const double* __restrict__ e, double* z) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  const int64_t r = row0 + i;
+  double s = z[r];
+  for (int64_t k = segA[r]; k < segB[r]; ++k) s -= pval[k] * z[pcol[k]];
+  const int64_t p = r - n_leaf;
+  for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += e[B_off[adj_leaf[k]] + adj_pos[k]];
+  z[r] = s;
+}
+
+// ================================================================ Krylov
+constexpr int kDotCols = 8;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = sh[0] + sh[1] + sh[2] + sh[3];
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(const double* __restrict__ V,
+                                                         int64_t ldv, int ncols,
+                                                         const double* __restrict__ w,
+                                                         int64_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = int64_t(blockIdx.x) * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  for (int c0 = 0; c0 < ncols; c0 += kDotCols) {
+    double acc[kDotCols];
+#pragma unroll
+    for (int u = 0; u < kDotCols; ++u) acc[u] = 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+      const double wr = w[r];
+#pragma unroll
+      for (int u = 0; u < kDotCols; ++u)
+        if (c0 + u < ncols) acc[u] += V[r + (c0 + u) * ldv] * wr;
+    }
+#pragma unroll
+    for (int u = 0; u < kDotCols; ++u) {
+      if (c0 + u >= ncols) break;
+      const double t = block_sum(acc[u], sh);
+      if (threadIdx.x == 0) part[int64_t(blockIdx.x) * ncols + c0 + u] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mdot_final(const double* __restrict__ part,
+                                                       int nblocks, int ncols,
+                                                       double* __restrict__ out, int mode) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) v += part[int64_t(b) * ncols + c];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) out[c] = (mode == 1) ? sqrt(t) : t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemv_acc(const double* __restrict__ V, int64_t ldv,
+                                                     int ncols, const double* __restrict__ h,
+                                                     double sign, double* __restrict__ w,
+                                                     int64_t n) {
+  const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < ncols; ++c) s += V[r + c * ldv] * h[c];
+  w[r] += sign * s;
+}
+
+__global__ void k_scale_div(const double* __restrict__ x, const double* __restrict__ d,
+                            double* __restrict__ y, int64_t n) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double dv = d[0];
+  y[r] = dv != 0.0 ? x[r] / dv : 0.0;
+}
+
+__global__ void k_small_add(double* a, const double* b, int k) {
+  const int i = threadIdx.x;
+  if (i < k) a[i] += b[i];
+}
+
+__global__ void k_axpy_ratio(const double* __restrict__ x, const double* __restrict__ z,
+                             const double* __restrict__ num, const double* __restrict__ den,
+                             double sgn, double* __restrict__ y, int64_t n) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double dn = den[0];
+  const double alpha = dn != 0.0 ? sgn * num[0] / dn : 0.0;
+  y[r] = x[r] + alpha * z[r];
+}
+
+inline unsigned blocks_for(int64_t n, int per = kBlock) { return unsigned((n + per - 1) / per); }
+
+}  // namespace
+
+// ================================================================ launchers
+hipError_t launch_gather(const double* src, const int64_t* map, int64_t count, double* dst,
+                         hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_gather<<<blocks_for(count), kBlock, 0, s>>>(src, map, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
+                          const int32_t* perm, int64_t n, int32_t nrhs, int32_t inverse,
+                          hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  k_permute<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(x, ldx, y, ldy, perm, n, inverse);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
+                           const int32_t* col, const double* val, const double* x,
+                           const double* base, double alpha, double* y, int lpr,
+                           hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(nrows * lpr);
+  switch (lpr) {
+    case 4: k_seg_spmv<4><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
+    case 8: k_seg_spmv<8><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
+    case 16: k_seg_spmv<16><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
+    default: k_seg_spmv<32><<<blocks_for(nrows * 32), kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_fill<<<blocks_for(count), kBlock, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_fill(const DevBatch& b, hipStream_t s) {
+  if (b.count == 0 || b.max_tiles == 0) return hipSuccess;
+  dim3 grid(unsigned(b.max_tiles), b.count);
+  if (b.fp32)
+    k_sym_fill<float><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.n, b.nt);
+  else
+    k_sym_fill<double><<<grid, kBlock, 0, s>>>((double*)b.tiles, b.tile_off, b.n, b.nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_extract(const DevBatch& b, const int64_t* s0, const int64_t* s1,
+                              const int32_t* pcol, const double* pval, int32_t max_n,
+                              hipStream_t s) {
+  if (b.count == 0 || max_n == 0) return hipSuccess;
+  dim3 grid(blocks_for(max_n), b.count);
+  if (b.fp32)
+    k_sym_extract<float><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.n, b.vec_off,
+                                                  s0, s1, pcol, pval);
+  else
+    k_sym_extract<double><<<grid, kBlock, 0, s>>>((double*)b.tiles, b.tile_off, b.n, b.vec_off,
+                                                   s0, s1, pcol, pval);
+  return hipGetLastError();
+}
+
+size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, size_t* cbytes) {
+  const size_t es = b.fp32 ? 4 : 8;
+  const size_t PB = size_t(group) * TS;
+  *pbytes = size_t(b.count) * PB * PB * es;
+  *cbytes = size_t(b.count) * size_t(b.max_nt) * TS * PB * es;
+  return *pbytes + 2 * *cbytes;
+}
+
+template <typename T, int G>
+static hipError_t sym_invert_t(const DevBatch& b, T* pbuf, T* cbuf, T* bbuf, int32_t* flags,
+                               hipStream_t s) {
+  const int64_t stride = int64_t(b.max_nt) * TS * G * TS;
+  for (int c0 = 0; c0 < b.max_nt; c0 += G) {
+    k_sweep_pivot<T, G><<<b.count, kBlock, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0, pbuf, flags);
+    k_sweep_panel<T, G><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
+        (const T*)b.tiles, b.tile_off, b.nt, c0, pbuf, cbuf, bbuf, stride);
+    k_sweep_update<T, G><<<dim3(unsigned(b.max_tiles), b.count), kBlock, 0, s>>>(
+        (T*)b.tiles, b.tile_off, b.nt, c0, cbuf, bbuf, stride);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_sym_invert(const DevBatch& b, void* pbuf, void* cbuf, void* bbuf,
+                             int32_t* flags, int group, hipStream_t s) {
+  if (b.count == 0 || b.max_nt == 0) return hipSuccess;
+  if (b.fp32) {
+    if (group == 2) return sym_invert_t<float, 2>(b, (float*)pbuf, (float*)cbuf, (float*)bbuf, flags, s);
+    return sym_invert_t<float, 1>(b, (float*)pbuf, (float*)cbuf, (float*)bbuf, flags, s);
+  }
+  if (group == 2) return sym_invert_t<double, 2>(b, (double*)pbuf, (double*)cbuf, (double*)bbuf, flags, s);
+  return sym_invert_t<double, 1>(b, (double*)pbuf, (double*)cbuf, (double*)bbuf, flags, s);
+}
+
+hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
+                       double alpha, const double* base, double* y, hipStream_t s) {
+  if (b.count == 0 || b.num_items == 0) return hipSuccess;
+  if (b.fp32)
+    k_symv1<float><<<b.num_items, kBlock, 0, s>>>(
+        (const float*)b.tiles, b.tile_off, b.n, b.vec_off, b.item_mat, b.item_J, b.item_I0,
+        b.item_I1, b.item_cslot, b.rslot_off, x, cpart, rpart);
+  else
+    k_symv1<double><<<b.num_items, kBlock, 0, s>>>(
+        (const double*)b.tiles, b.tile_off, b.n, b.vec_off, b.item_mat, b.item_J, b.item_I0,
+        b.item_I1, b.item_cslot, b.rslot_off, x, cpart, rpart);
+  k_symv2<<<dim3(b.max_nt, b.count), TS, 0, s>>>(b.n, b.nt, b.vec_off, b.cstrip_base,
+                                                  b.cstrip_ptr, b.rslot_off, cpart, rpart,
+                                                  alpha, base, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_w(const DevBatch& leaf, const SigmaArgs& a, double* W, hipStream_t s) {
+  if (a.num_leaves == 0 || a.max_m == 0) return hipSuccess;
+  dim3 grid(a.max_m, a.num_leaves);
+  if (leaf.fp32)
+    k_sigma_w<float><<<grid, kBlock, 0, s>>>((const float*)leaf.tiles, leaf.tile_off, a, W);
+  else
+    k_sigma_w<double><<<grid, kBlock, 0, s>>>((const double*)leaf.tiles, leaf.tile_off, a, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_s(const SigmaArgs& a, const double* W, void* sigma, int sigma_fp32,
+                          hipStream_t s) {
+  if (a.num_leaves == 0 || a.max_m == 0) return hipSuccess;
+  dim3 grid(a.max_m, a.num_leaves);
+  if (sigma_fp32)
+    k_sigma_s<float><<<grid, kBlock, 0, s>>>(a, W, (float*)sigma);
+  else
+    k_sigma_s<double><<<grid, kBlock, 0, s>>>(a, W, (double*)sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
+                                 const int32_t* adj_leaf, const int32_t* adj_pos,
+                                 const int64_t* B_off, const int64_t* sig_off,
+                                 const void* sigma, int sigma_fp32, int64_t n_leaf,
+                                 hipStream_t s) {
+  if (b.count == 0 || b.max_tiles == 0) return hipSuccess;
+  dim3 grid(unsigned(b.max_tiles), b.count);
+#define RSD_ASM(T, S)                                                                       \
+  k_schur_assemble<T, S><<<grid, kBlock, 0, s>>>((T*)b.tiles, b.tile_off, b.n, b.nt, b.vec_off, \
+                                                 adj_ptr, adj_leaf, adj_pos, B_off, sig_off, \
+                                                 (const S*)sigma, n_leaf)
+  if (b.fp32) {
+    if (sigma_fp32) RSD_ASM(float, float); else RSD_ASM(float, double);
+  } else {
+    if (sigma_fp32) RSD_ASM(double, float); else RSD_ASM(double, double);
+  }
+#undef RSD_ASM
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int sigma_fp32,
+                              const int64_t* sig_off, const int64_t* B_off, const int32_t* B,
+                              const double* z, double* e, hipStream_t s) {
+  if (it.count == 0) return hipSuccess;
+  if (sigma_fp32)
+    k_sigma_level<float><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,
+                                                      (const float*)sigma, sig_off, B_off, B, z, e);
+  else
+    k_sigma_level<double><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,
+                                                       (const double*)sigma, sig_off, B_off, B, z, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_rhs(int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* pcol,
+                            const double* pval, const int64_t* segA, const int64_t* segB,
+                            const int64_t* adj_ptr, const int32_t* adj_leaf,
+                            const int32_t* adj_pos, const int64_t* B_off, const double* e,
+                            double* z, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  k_level_rhs<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, n_leaf, pcol, pval, segA, segB,
+                                                   adj_ptr, adj_leaf, adj_pos, B_off, e, z);
+  return hipGetLastError();
+}
+
+int mdot_blocks(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return int(b);
+}
+
+hipError_t launch_mdot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n,
+                       double* partial, double* out, int mode, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  const int nb = mdot_blocks(n);
+  k_mdot_partial<<<nb, kBlock, 0, s>>>(V, ldv, ncols, w, n, partial);
+  k_mdot_final<<<ncols, kBlock, 0, s>>>(partial, nb, ncols, out, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_acc(const double* V, int64_t ldv, int ncols, const double* h,
+                           double sign, double* w, int64_t n, hipStream_t s) {
+  if (ncols <= 0 || n <= 0) return hipSuccess;
+  k_gemv_acc<<<blocks_for(n), kBlock, 0, s>>>(V, ldv, ncols, h, sign, w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_div(const double* x, const double* d, double* y, int64_t n,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_scale_div<<<blocks_for(n), kBlock, 0, s>>>(x, d, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_add(double* a, const double* b, int k, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  k_small_add<<<1, 512, 0, s>>>(a, b, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_ratio(const double* x, const double* z, const double* num,
+                             const double* den, double sgn, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axpy_ratio<<<blocks_for(n), kBlock, 0, s>>>(x, z, num, den, sgn, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace rsd

@@ -1,0 +1,130 @@
+// Host-side launchers of the HIP kernels (implemented in kernels.hip).
+//
+// Every launcher enqueues on `s` and returns hipGetLastError() of its launch.
+// Dense symmetric blocks are stored as packed lower tiles (see plan.hpp):
+// tile (I, J), I >= J, of matrix m starts at tiles + tile_off[m] + (I(I+1)/2 + J)*64*64
+// and is column-major 64 x 64; diagonal tiles hold both triangles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rsd {
+
+// Device view of a SymBatch (arrays live on the device).
+struct DevBatch {
+  int32_t count = 0;
+  int32_t max_nt = 0;
+  int64_t max_tiles = 0;
+  const int32_t* n = nullptr;
+  const int32_t* nt = nullptr;
+  const int64_t* tile_off = nullptr;
+  const int64_t* vec_off = nullptr;
+  int32_t num_items = 0;
+  const int32_t* item_mat = nullptr;
+  const int32_t* item_J = nullptr;
+  const int32_t* item_I0 = nullptr;
+  const int32_t* item_I1 = nullptr;
+  const int64_t* item_cslot = nullptr;
+  const int64_t* rslot_off = nullptr;
+  const int64_t* cstrip_ptr = nullptr;
+  const int64_t* cstrip_base = nullptr;
+  void* tiles = nullptr;  // double* or float*
+  int32_t fp32 = 0;
+};
+
+// ---- sparse / vector ------------------------------------------------------------------
+hipError_t launch_gather(const double* src, const int64_t* map, int64_t count, double* dst,
+                         hipStream_t s);
+hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
+                          const int32_t* perm, int64_t n, int32_t nrhs, int32_t inverse,
+                          hipStream_t s);
+// y[r] = (base ? base[r] : 0) + alpha * sum_{k in [s0[r], s1[r])} val[k] x[col[k]],
+// rows r in [row0, row0 + nrows); lanes_per_row in {4, 8, 16, 32}
+hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
+                           const int32_t* col, const double* val, const double* x,
+                           const double* base, double alpha, double* y, int lanes_per_row,
+                           hipStream_t s);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+
+// ---- dense symmetric batches ------------------------------------------------------------
+hipError_t launch_sym_fill(const DevBatch& b, hipStream_t s);
+// scatters rows' segments [s0[r], s1[r]) of the internal CSR into the batch tiles
+hipError_t launch_sym_extract(const DevBatch& b, const int64_t* s0, const int64_t* s1,
+                              const int32_t* pcol, const double* pval, int32_t max_n,
+                              hipStream_t s);
+// in-place inversion by blocked symmetric sweeps; returns -A^{-1} in the tiles;
+// flags[m] != 0 marks a non-positive or non-finite pivot in matrix m
+hipError_t launch_sym_invert(const DevBatch& b, void* pbuf, void* cbuf, void* bbuf,
+                             int32_t* flags, int group, hipStream_t s);
+size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, size_t* cbytes);
+// y = base + alpha * A x for every matrix of the batch (x, y internal vectors)
+hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
+                       double alpha, const double* base, double* y, hipStream_t s);
+
+// ---- Schur complements --------------------------------------------------------------------
+struct SigmaArgs {
+  int32_t num_leaves, max_m;
+  const int64_t* B_off;
+  const int32_t* B;
+  const int64_t* shell_off;
+  const int32_t* shell;
+  const int64_t* kcol_ptr;
+  const int32_t* kcol_row;
+  const int64_t* kcol_val;
+  const int64_t* krow_ptr;
+  const int32_t* krow_col;
+  const int64_t* krow_val;
+  const int64_t* w_off;
+  const int64_t* sig_off;
+  const double* pval;
+};
+// W_l = K_ll^{-1}[shell, :] K_{l,B_l}  (from the leaf batch's -K_ll^{-1} tiles)
+hipError_t launch_sigma_w(const DevBatch& leaf, const SigmaArgs& a, double* W, hipStream_t s);
+// Sigma_l = K_{B_l,l} W_l   (stored fp64 or fp32)
+hipError_t launch_sigma_s(const SigmaArgs& a, const double* W, void* sigma, int sigma_fp32,
+                          hipStream_t s);
+// S~ tiles (already holding K_tt) -= sum over adjacent leaves of Sigma_l[I_t, I_t]
+hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
+                                 const int32_t* adj_leaf, const int32_t* adj_pos,
+                                 const int64_t* B_off, const int64_t* sig_off,
+                                 const void* sigma, int sigma_fp32, int64_t n_leaf,
+                                 hipStream_t s);
+
+// ---- apply helpers -------------------------------------------------------------------------
+struct SigmaLevelItems {
+  int32_t count = 0;
+  const int32_t* leaf = nullptr;
+  const int32_t* r0 = nullptr;
+  const int32_t* a0 = nullptr;
+  const int32_t* a1 = nullptr;
+};
+hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int sigma_fp32,
+                              const int64_t* sig_off, const int64_t* B_off, const int32_t* B,
+                              const double* z, double* e, hipStream_t s);
+hipError_t launch_level_rhs(int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* pcol,
+                            const double* pval, const int64_t* segA, const int64_t* segB,
+                            const int64_t* adj_ptr, const int32_t* adj_leaf,
+                            const int32_t* adj_pos, const int64_t* B_off, const double* e,
+                            double* z, hipStream_t s);
+
+// ---- Krylov ----------------------------------------------------------------------------------
+int mdot_blocks(int64_t n);
+// out[c] (c < ncols) = sum_r V[r + c ldv] w[r]  (deterministic two-pass); mode 0 store,
+// mode 1 store sqrt
+hipError_t launch_mdot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n,
+                       double* partial, double* out, int mode, hipStream_t s);
+// w += sign * sum_c V[:, c] h[c]
+hipError_t launch_gemv_acc(const double* V, int64_t ldv, int ncols, const double* h,
+                           double sign, double* w, int64_t n, hipStream_t s);
+// y = x / d[0]  (y = 0 when d[0] == 0)
+hipError_t launch_scale_div(const double* x, const double* d, double* y, int64_t n,
+                            hipStream_t s);
+// a[i] += b[i], i < k
+hipError_t launch_small_add(double* a, const double* b, int k, hipStream_t s);
+// y = x + alpha * z  with alpha = num[0] / den[0] * sgn   (device scalars)
+hipError_t launch_axpy_ratio(const double* x, const double* z, const double* num,
+                             const double* den, double sgn, double* y, int64_t n, hipStream_t s);
+
+}  // namespace rsd

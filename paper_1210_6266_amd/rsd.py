@@ -1,0 +1,312 @@
+"""ctypes binding of the C ABI in include/rsd.h (argument marshalling only).
+
+The functions keep the C names (rsd_setup, rsd_apply, rsd_solve, rsd_spmv,
+rsd_update_values, rsd_get_stats, rsd_destroy, rsd_last_error, rsd_analyze).
+Device arrays are PyTorch tensors on the current HIP device; PyTorch only
+provides the device memory and the stream.  Every step of the method runs in
+librsd.so; when the library is missing, loading raises instead of falling back.
+
+``RSD`` wraps a handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "librsd.so")
+_lib = None
+
+RSD_OK = 0
+STATUS = {0: "RSD_OK", 1: "RSD_ERR_INVALID_ARGUMENT", 2: "RSD_ERR_MAP_NOT_SEPARABLE",
+          3: "RSD_ERR_NOT_SPD", 4: "RSD_ERR_NOT_CONVERGED", 5: "RSD_ERR_BREAKDOWN",
+          6: "RSD_ERR_OUT_OF_MEMORY", 7: "RSD_ERR_DEVICE", 8: "RSD_ERR_UNSUPPORTED"}
+PREC = {"fp64": 0, "fp32": 1}
+SOLVER = {"fgmres": 0, "pcg": 1}
+TIMER_NAMES = ["setup_extract", "leaf_inverse", "sigma", "iface_assembly", "iface_inverse",
+               "leaf_apply", "iface_apply", "coupling", "spmv", "krylov", "permute"]
+
+
+class rsd_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("values", C.c_void_p)]
+
+
+class rsd_hierarchy(C.Structure):
+    _fields_ = [("num_nodes", C.c_int32), ("parent", C.c_void_p), ("dof_node", C.c_void_p)]
+
+
+class rsd_options(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("leaf_prec", C.c_int32), ("sigma_prec", C.c_int32),
+                ("iface_prec", C.c_int32), ("root_prec", C.c_int32),
+                ("host_pointers", C.c_int32), ("timing", C.c_int32)]
+
+
+class rsd_solve_options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
+                ("rtol", C.c_double), ("use_x0", C.c_int32)]
+
+
+class rsd_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("relres", C.c_double), ("status", C.c_int32)]
+
+
+class rsd_analysis(C.Structure):
+    _fields_ = [("num_leaves", C.c_int32), ("num_levels", C.c_int32),
+                ("max_leaf_dofs", C.c_int32), ("max_iface_dofs", C.c_int32),
+                ("max_boundary_dofs", C.c_int32), ("leaf_dofs", C.c_int64),
+                ("skeleton_dofs", C.c_int64), ("sum_leaf_sq", C.c_int64),
+                ("sum_iface_sq", C.c_int64), ("sum_sigma_apply", C.c_int64),
+                ("sum_sigma_sq", C.c_int64), ("leaf_inverse_flops", C.c_double),
+                ("iface_inverse_flops", C.c_double)]
+
+
+class rsd_stats(C.Structure):
+    _fields_ = [("analysis", rsd_analysis), ("time_ms", C.c_double * 11),
+                ("launches", C.c_int64 * 11), ("host_analysis_ms", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+EXPORTS = ["rsd_options_default", "rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv",
+           "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_destroy", "rsd_last_error"]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Loads librsd.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built: run `python -m paper_1210_6266_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library links against)
+    except ImportError:
+        pass
+    lib = C.CDLL(_LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.rsd_options_default.argtypes = [C.POINTER(rsd_options)]
+    lib.rsd_options_default.restype = None
+    lib.rsd_analyze.argtypes = [C.POINTER(rsd_csr), C.POINTER(rsd_hierarchy), C.POINTER(rsd_analysis)]
+    lib.rsd_setup.argtypes = [C.POINTER(rsd_csr), C.POINTER(rsd_hierarchy), C.POINTER(rsd_options),
+                              vp, C.POINTER(vp)]
+    lib.rsd_apply.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    lib.rsd_spmv.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    lib.rsd_solve.argtypes = [vp, i32, vp, i64, vp, i64, C.POINTER(rsd_solve_options),
+                              C.POINTER(rsd_solve_info), vp]
+    lib.rsd_update_values.argtypes = [vp, vp, vp]
+    lib.rsd_get_stats.argtypes = [vp, C.POINTER(rsd_stats), i32, vp]
+    lib.rsd_destroy.argtypes = [vp]
+    lib.rsd_destroy.restype = None
+    lib.rsd_last_error.argtypes = [vp]
+    lib.rsd_last_error.restype = C.c_char_p
+    for f in ["rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv", "rsd_solve",
+              "rsd_update_values", "rsd_get_stats"]:
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class RSDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _check(st: int, handle=None):
+    if st != RSD_OK:
+        raise RSDError(st, rsd_last_error(handle))
+
+
+# ------------------------------------------------------------------ C names
+def rsd_last_error(handle=None) -> str:
+    return load().rsd_last_error(handle).decode()
+
+
+def rsd_options_default() -> rsd_options:
+    o = rsd_options()
+    load().rsd_options_default(C.byref(o))
+    return o
+
+
+def rsd_analyze(row_ptr: np.ndarray, col_idx: np.ndarray, parent: np.ndarray,
+                dof_node: np.ndarray) -> dict:
+    """Host-only analysis (numpy int64 row_ptr, int32 col_idx / parent / dof_node)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    dof_node = np.ascontiguousarray(dof_node, dtype=np.int32)
+    csr = rsd_csr(len(row_ptr) - 1, int(row_ptr[-1]) if len(row_ptr) else 0, _ptr(row_ptr),
+                  _ptr(col_idx), None)
+    hier = rsd_hierarchy(len(parent), _ptr(parent), _ptr(dof_node))
+    out = rsd_analysis()
+    _check(load().rsd_analyze(C.byref(csr), C.byref(hier), C.byref(out)))
+    return {k: getattr(out, k) for k, _ in rsd_analysis._fields_}
+
+
+def rsd_setup(row_ptr, col_idx, values, parent, dof_node, options: rsd_options | None = None,
+              stream=None) -> int:
+    """Arrays: torch tensors on the device (or numpy arrays with options.host_pointers = 1)."""
+    n = int(row_ptr.shape[0]) - 1
+    nnz = int(col_idx.shape[0])
+    csr = rsd_csr(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(values))
+    hier = rsd_hierarchy(int(parent.shape[0]), _ptr(parent), _ptr(dof_node))
+    h = C.c_void_p()
+    opt = C.byref(options) if options is not None else None
+    _check(load().rsd_setup(C.byref(csr), C.byref(hier), opt, _stream(stream), C.byref(h)))
+    return h.value
+
+
+def _cols(t, n):
+    """(nrhs, ld) of a device vector block: 1-D (n,) or 2-D (n, nrhs) column-major."""
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError("vectors must be contiguous")
+        return 1, t.shape[0]
+    if t.stride(0) != 1 or t.stride(1) < n:
+        raise ValueError("2-D blocks must be column-major (stride (1, ld) with ld >= n)")
+    return t.shape[1], t.stride(1)
+
+
+def colmajor(t):
+    """A column-major copy of a 1-D or 2-D tensor (the layout the C ABI takes)."""
+    return t.contiguous() if t.dim() == 1 else t.t().contiguous().t()
+
+
+def rsd_apply(handle, r, z, stream=None):
+    nrhs, ldr = _cols(r, r.shape[0])
+    _, ldz = _cols(z, z.shape[0])
+    _check(load().rsd_apply(handle, nrhs, _ptr(r), ldr, _ptr(z), ldz, _stream(stream)), handle)
+
+
+def rsd_spmv(handle, x, y, stream=None):
+    nrhs, ldx = _cols(x, x.shape[0])
+    _, ldy = _cols(y, y.shape[0])
+    _check(load().rsd_spmv(handle, nrhs, _ptr(x), ldx, _ptr(y), ldy, _stream(stream)), handle)
+
+
+def rsd_solve(handle, b, x, method="fgmres", restart=30, maxit=500, rtol=1e-10, use_x0=False,
+              stream=None):
+    """Returns (status, [info dicts]); x is overwritten.  Does not raise on NOT_CONVERGED
+    or BREAKDOWN (the per-column status says which)."""
+    nrhs, ldb = _cols(b, b.shape[0])
+    _, ldx = _cols(x, x.shape[0])
+    o = rsd_solve_options(SOLVER[method], restart, maxit, rtol, 1 if use_x0 else 0)
+    info = (rsd_solve_info * max(1, nrhs))()
+    st = load().rsd_solve(handle, nrhs, _ptr(b), ldb, _ptr(x), ldx, C.byref(o), info,
+                          _stream(stream))
+    if st not in (RSD_OK, 4, 5):
+        _check(st, handle)
+    return st, [dict(iterations=info[j].iterations, relres=info[j].relres, status=info[j].status)
+                for j in range(nrhs)]
+
+
+def rsd_update_values(handle, values, stream=None):
+    _check(load().rsd_update_values(handle, _ptr(values), _stream(stream)), handle)
+
+
+def rsd_get_stats(handle, reset=False, stream=None) -> dict:
+    s = rsd_stats()
+    _check(load().rsd_get_stats(handle, C.byref(s), 1 if reset else 0, _stream(stream)), handle)
+    out = {k: getattr(s.analysis, k) for k, _ in rsd_analysis._fields_}
+    out["time_ms"] = {TIMER_NAMES[i]: s.time_ms[i] for i in range(11)}
+    out["launches"] = {TIMER_NAMES[i]: s.launches[i] for i in range(11)}
+    out["host_analysis_ms"] = s.host_analysis_ms
+    out["device_bytes"] = s.device_bytes
+    return out
+
+
+def rsd_destroy(handle):
+    if handle:
+        load().rsd_destroy(handle)
+
+
+# ------------------------------------------------------------------ convenience
+def torch_empty_like(t):
+    return t.new_empty(t.shape)
+
+
+class RSD:
+    """One RSD preconditioner handle over a CSR matrix on the current HIP device."""
+
+    def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
+                 sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def dv(a, dt):
+            t = torch.as_tensor(a)
+            return t.to(device=dev, dtype=dt).contiguous()
+
+        self.row_ptr = dv(row_ptr, torch.int64)
+        self.col_idx = dv(col_idx, torch.int32)
+        self.values = dv(values, torch.float64)
+        self.parent = dv(parent, torch.int32)
+        self.dof_node = dv(dof_node, torch.int32)
+        self.n = self.row_ptr.numel() - 1
+        o = rsd_options_default()
+        o.leaf_prec = PREC[leaf_prec]
+        o.sigma_prec = PREC[sigma_prec or leaf_prec]
+        o.iface_prec = PREC[iface_prec or leaf_prec]
+        o.root_prec = PREC[root_prec]
+        o.timing = 1 if timing else 0
+        self.stream = stream
+        self.handle = rsd_setup(self.row_ptr, self.col_idx, self.values, self.parent,
+                                self.dof_node, o, stream)
+
+    def apply(self, r, out=None):
+        r = colmajor(r)
+        z = out if out is not None else colmajor(torch_empty_like(r))
+        rsd_apply(self.handle, r, z, self.stream)
+        return z
+
+    def spmv(self, x, out=None):
+        x = colmajor(x)
+        y = out if out is not None else colmajor(torch_empty_like(x))
+        rsd_spmv(self.handle, x, y, self.stream)
+        return y
+
+    def solve(self, b, x=None, **kw):
+        b = colmajor(b)
+        use_x0 = x is not None
+        x = colmajor(x) if x is not None else colmajor(b.new_zeros(b.shape))
+        st, info = rsd_solve(self.handle, b, x, use_x0=use_x0, stream=self.stream, **kw)
+        return x, st, info
+
+    def update_values(self, values):
+        import torch
+        self.values = torch.as_tensor(values).to(self.values.device, torch.float64).contiguous()
+        rsd_update_values(self.handle, self.values, self.stream)
+
+    def stats(self, reset=False):
+        return rsd_get_stats(self.handle, reset, self.stream)
+
+    def close(self):
+        if self.handle:
+            rsd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

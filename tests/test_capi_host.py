@@ -1,0 +1,147 @@
+"""Host-side tests of the C ABI (no GPU): the library loads, exports every entry
+point declared in include/rsd.h, and its host analysis validates input and
+reproduces the hierarchy counts computed independently from the matrix."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1210_6266_amd import rsd as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "rsd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsd_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(R.library_path()):
+        pytest.fail("librsd.so is not built (run __graft_entry__.build())")
+    return R.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert set(names) == set(R.EXPORTS), names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header(lib):
+    o = R.rsd_options_default()
+    assert o.struct_size == 7 * 4 and o.leaf_prec == 0 and o.timing == 0
+
+
+def _arrays(p):
+    rp, ci, _ = p.csr_arrays()
+    return rp, ci, p.parent.astype(np.int32), p.dof_node.astype(np.int32)
+
+
+def test_analysis_counts(problem_cache, lib):
+    """Counts from the library's planner against counts computed here from K."""
+    p = problem_cache("diffusion", 13, 2, 1.0, 0)
+    rp, ci, par, dn = _arrays(p)
+    a = R.rsd_analyze(rp, ci, par, dn)
+    T = len(par)
+    children = [[] for _ in range(T)]
+    for t in range(1, T):
+        children[par[t]].append(t)
+    leaves = [t for t in range(T) if not children[t]]
+    sizes = np.bincount(dn, minlength=T)
+    K = p.K.tocsr()
+    is_leaf = np.array([not children[t] for t in range(T)])
+    m = []
+    for l in leaves:
+        rows = np.nonzero(dn == l)[0]
+        cols = np.unique(K[rows].indices)
+        m.append(int(np.sum(~is_leaf[dn[cols]])))
+    depth = np.zeros(T, dtype=int)
+    for t in range(1, T):
+        depth[t] = depth[par[t]] + 1
+    inner = [t for t in range(T) if children[t] and sizes[t] > 0]
+    assert a["num_leaves"] == len(leaves)
+    assert a["num_levels"] == len({depth[t] for t in inner})
+    assert a["leaf_dofs"] == int(sizes[leaves].sum())
+    assert a["skeleton_dofs"] == p.n - int(sizes[leaves].sum())
+    assert a["max_leaf_dofs"] == int(sizes[leaves].max())
+    assert a["max_iface_dofs"] == int(sizes[inner].max())
+    assert a["max_boundary_dofs"] == max(m)
+    assert a["sum_sigma_sq"] == sum(x * x for x in m)
+    assert a["sum_leaf_sq"] == int((sizes[leaves].astype(np.int64) ** 2).sum())
+
+
+def test_config_analysis_c2(problem_cache, lib):
+    p = problem_cache("config", "diffusion64")
+    a = R.rsd_analyze(*_arrays(p))
+    assert (a["num_leaves"], a["num_levels"], a["max_leaf_dofs"], a["max_iface_dofs"]) == \
+        (64, 2, 3375, 11719)
+    assert a["leaf_dofs"] == 216000 and a["skeleton_dofs"] == 34047
+    assert a["max_boundary_dofs"] == 1538
+
+
+def _expect(status, fn):
+    with pytest.raises(R.RSDError) as ei:
+        fn()
+    assert ei.value.status == status, (ei.value.status, str(ei.value))
+    return str(ei.value)
+
+
+def test_rejects_non_separable_map(problem_cache, lib):
+    p = problem_cache("diffusion", 8, 2, 0.0, 0)
+    rp, ci, par, dn = _arrays(p)
+    dn = dn.copy()
+    T = len(par)
+    children = [[] for _ in range(T)]
+    for t in range(1, T):
+        children[par[t]].append(t)
+    leaves = [t for t in range(T) if not children[t]]
+    # move one interior dof of leaf A into leaf B, far away: K then couples A and B
+    a_dof = np.nonzero(dn == leaves[0])[0][0]
+    dn[a_dof] = leaves[-1]
+    msg = _expect(2, lambda: R.rsd_analyze(rp, ci, par, dn))
+    assert "root-to-leaf" in msg
+
+
+@pytest.mark.parametrize("case", ["unsorted", "col_range", "row_ptr", "parent", "dof_node",
+                                  "asymmetric"])
+def test_rejects_invalid_input(problem_cache, lib, case):
+    p = problem_cache("diffusion", 6, 1, 0.0, 0)
+    rp, ci, par, dn = [x.copy() for x in _arrays(p)]
+    if case == "unsorted":
+        ci[rp[3]], ci[rp[3] + 1] = ci[rp[3] + 1], ci[rp[3]]
+    elif case == "col_range":
+        ci[5] = p.n
+    elif case == "row_ptr":
+        rp[-1] += 1
+    elif case == "parent":
+        par[3] = 5
+    elif case == "dof_node":
+        dn[0] = len(par)
+    elif case == "asymmetric":
+        # drop one off-diagonal entry of row 0 (keep row 1's mirror)
+        k = rp[0] + 1
+        ci = np.delete(ci, k)
+        rp = rp.copy()
+        rp[1:] -= 1
+    _expect(1, lambda: R.rsd_analyze(rp, ci, par, dn))
+
+
+def test_setup_validates_before_device_work(problem_cache, lib):
+    """With host pointers and an invalid map, rsd_setup fails in the host analysis
+    (no device call is reached) and reports the error thread-locally."""
+    p = problem_cache("diffusion", 6, 1, 0.0, 0)
+    rp, ci, v = p.csr_arrays()
+    par = p.parent.astype(np.int32).copy()
+    par[0] = 0
+    o = R.rsd_options_default()
+    o.host_pointers = 1
+    msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, par, p.dof_node.astype(np.int32), o, stream=0))
+    assert "parent[0]" in msg
+    o.leaf_prec = 7
+    _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
+                                   p.dof_node.astype(np.int32), o, stream=0))
