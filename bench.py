@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSD-preconditioned Krylov solve on one MI355X.
+
+Workload: -div(k grad u) = f on 64^3 trilinear hexahedra of the unit cube,
+k_e = exp(z_e), z_e ~ N(0, 1) per element, f ~ U[-1, 1] per free dof (n = 250,047),
+4 x 4 x 4 box sub-domains (octree of height 2: 64 true sub-domains of 3,375 dofs,
+8 level-1 interfaces of 2,791 dofs, a root interface of 11,719 dofs).
+
+One step = one pass of the whole hot path on inputs already resident in HBM:
+rsd_setup (host analysis of the hierarchy, extraction and exact inversion of the
+sub-domain matrices, Sigma blocks, interface Schur assembly and inversion), then
+rsd_solve (FGMRES(30) preconditioned by RSD to a true relative residual of 1e-10),
+then rsd_destroy.  The headline variant keeps sub-domain, Sigma and non-root
+interface blocks in FP32 and the root interface, the Krylov vectors, dot products,
+orthogonalisation and residuals in FP64; the plain FP64 variant is timed beside it.
+
+value = solves per second of the mixed variant (1 / time-to-1e-10 including set-up).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 residual & solves/s, mixed-batched vs FP64 RSD; GB/s, MFMA %"
+PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
+MIXED = dict(leaf_prec="fp32", sigma_prec="fp32", iface_prec="fp32", root_prec="fp64")
+FP64 = dict(leaf_prec="fp64", sigma_prec="fp64", iface_prec="fp64", root_prec="fp64")
+GROUP_TILES = 2          # pivot tiles per sweep step (default of the library)
+TILE = 64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--reuse-solves", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
+                    help="time one variant only (for profiling runs)")
+    return ap.parse_args()
+
+
+def update_flops(sizes, steps_group=GROUP_TILES):
+    """Algorithmic flops of the MFMA trailing updates of one blocked sweep inversion
+    per matrix of order n: per step with w real pivot columns, the n - w other rows
+    and columns receive a rank-w update of their lower triangle: w (n-w)(n-w+1)."""
+    tot = 0.0
+    for n in sizes:
+        nt = (n + TILE - 1) // TILE
+        for c0 in range(0, nt, steps_group):
+            lo = c0 * TILE
+            w = min(n, (c0 + steps_group) * TILE) - lo
+            if w <= 0:
+                continue
+            r = n - w
+            tot += float(w) * r * (r + 1)
+    return tot
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {a.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1210_6266_amd import RSD
+    from paper_1210_6266_amd.rsd import rsd_analyze
+    from workloads import config_problem
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    p = config_problem("diffusion64", seed=a.seed)
+    rp, ci, v = p.csr_arrays()
+    ana = rsd_analyze(rp, ci, p.parent, p.dof_node)
+    d_rp = torch.as_tensor(rp, device=dev)
+    d_ci = torch.as_tensor(ci, device=dev)
+    d_v = torch.as_tensor(v, device=dev)
+    d_par = torch.as_tensor(p.parent.astype(np.int32), device=dev)
+    d_dn = torch.as_tensor(p.dof_node.astype(np.int32), device=dev)
+    b = torch.as_tensor(np.ascontiguousarray(p.b[:, 0]), device=dev)
+    torch.cuda.synchronize()
+
+    def step(prec, timing):
+        t0 = time.perf_counter()
+        h = RSD(d_rp, d_ci, d_v, d_par, d_dn, timing=timing, **prec)
+        t1 = time.perf_counter()
+        x, st, info = h.solve(b, rtol=1e-10, restart=30, maxit=1000)
+        t2 = time.perf_counter()
+        stats = h.stats() if timing else None
+        h.close()
+        t3 = time.perf_counter()
+        stats["wall_ms"] = [1e3 * (t1 - t0), 1e3 * (t2 - t1), 1e3 * (t3 - t2)]
+        return x, st, info[0], stats
+
+    def timed(prec, k, w):
+        for _ in range(w):
+            step(prec, True)
+        torch.cuda.synchronize()
+        acc_ms, acc_n = {}, {}
+        its = []
+        t0 = time.perf_counter()
+        for _ in range(k):
+            x, st, info, stats = step(prec, True)
+            its.append(info["iterations"])
+            for kk, vv in stats["time_ms"].items():
+                acc_ms[kk] = acc_ms.get(kk, 0.0) + vv
+            for kk, vv in stats["launches"].items():
+                acc_n[kk] = acc_n.get(kk, 0) + vv
+            for i, kk in enumerate(["setup", "solve", "stats+destroy"]):
+                acc_ms["wall_" + kk] = acc_ms.get("wall_" + kk, 0.0) + stats["wall_ms"][i]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if st != 0:
+            raise RuntimeError(f"solve did not converge: status {st}, {info}")
+        return (t1 - t0) / k, x, its, acc_ms, acc_n, stats
+
+    def reuse(prec, r):
+        h = RSD(d_rp, d_ci, d_v, d_par, d_dn, **prec)
+        h.solve(b, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(r):
+            x, st, info = h.solve(b, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h.close()
+        return r / (t1 - t0)
+
+    variants = ["mixed", "fp64"] if a.only is None else [a.only]
+    res = {}
+    for name in variants:
+        prec = MIXED if name == "mixed" else FP64
+        k = a.steps if (name == "mixed" or a.only) else max(1, (a.steps + 1) // 2)
+        sec, x, its, ms, nl, last = timed(prec, k, a.warmup)
+        xh = x.cpu().numpy()
+        bh = p.b[:, 0]
+        relres = float(np.linalg.norm(bh - p.K @ xh) / np.linalg.norm(bh))
+        res[name] = dict(sec=sec, x=xh, its=its, ms={kk: vv / k for kk, vv in ms.items()},
+                         launches={kk: vv / k for kk, vv in nl.items()}, relres=relres,
+                         device_bytes=last["device_bytes"], host_ms=last["host_analysis_ms"],
+                         setup_wall_ms=last["setup_wall_ms"], steps=k)
+    reuse_sps = {}
+    if a.reuse_solves > 0:
+        for name in variants:
+            reuse_sps[name] = reuse(MIXED if name == "mixed" else FP64, a.reuse_solves)
+
+    head = "mixed" if "mixed" in res else variants[0]
+    R0 = res[head]
+    value = 1.0 / R0["sec"]
+
+    # ---- roofline of the dominant kernel class of the headline variant
+    ms = R0["ms"]
+    nlch = R0["launches"]
+    leaf_sizes = [ana["max_leaf_dofs"]] * ana["num_leaves"]   # uniform leaves here
+    fp32_leaf = head == "mixed"
+    cand = {
+        "leaf_update": ms.get("leaf_update", 0.0),
+        "root_update": ms.get("root_update", 0.0),
+        "leaf_apply": ms.get("leaf_apply", 0.0),
+    }
+    dom = max(cand, key=cand.get)
+    if dom == "leaf_update":
+        flops = update_flops(leaf_sizes)
+        per_launch = flops / nlch["leaf_update"]
+        dur = ms["leaf_update"] / nlch["leaf_update"] * 1e-3
+        peak = PEAK["fp32_TFLOPs"] if fp32_leaf else PEAK["fp64_TFLOPs"]
+        roof = dict(kernel="k_sweep_update2 (sub-domain batch)", bound="mfma",
+                    achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s")
+    elif dom == "root_update":
+        flops = update_flops([ana["max_iface_dofs"]])
+        per_launch = flops / nlch["root_update"]
+        dur = ms["root_update"] / nlch["root_update"] * 1e-3
+        roof = dict(kernel="k_sweep_update2<double> (root interface)", bound="mfma",
+                    achieved=per_launch / dur / 1e12, peak=PEAK["fp64_TFLOPs"], unit="TFLOP/s")
+    else:
+        es = 4 if fp32_leaf else 8
+        per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
+        dur = ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3
+        roof = dict(kernel="k_symv1+k_symv2 (sub-domain batch)", bound="hbm",
+                    achieved=per_launch / dur / 1e9, peak=PEAK["hbm_GBps"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["avg_launch_ms"] = dur * 1e3
+    roof["traffic"] = None
+    # secondary figures (not the roofline object): leaf apply bandwidth, root update rate
+    extra = {}
+    if R0["launches"].get("leaf_apply"):
+        es = 4 if fp32_leaf else 8
+        lb = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
+        extra["leaf_apply_GBps"] = lb / (ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3) / 1e9
+    if R0["launches"].get("root_update"):
+        fl = update_flops([ana["max_iface_dofs"]])
+        extra["root_update_TFLOPs_fp64"] = fl / (ms["root_update"] * 1e-3) / 1e12
+    if R0["launches"].get("leaf_update"):
+        fl = update_flops(leaf_sizes)
+        extra["leaf_update_TFLOPs"] = fl / (ms["leaf_update"] * 1e-3) / 1e12
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    cpu = None
+    if not a.no_cpu_baseline and a.only is None:
+        try:
+            from threadpoolctl import threadpool_info
+
+            from oracle import RSDOracle
+            threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+            t0 = time.perf_counter()
+            orc = RSDOracle(p.K, p.parent, p.dof_node)
+            t1 = time.perf_counter()
+            z = orc.apply(p.b[:, 0])
+            t2 = time.perf_counter()
+            _ = p.K @ z
+            t3 = time.perf_counter()
+            beta = float(np.mean(res["fp64"]["its"])) if "fp64" in res else float(np.mean(R0["its"]))
+            sec_solve = (t1 - t0) + beta * ((t2 - t1) + (t3 - t2))
+            cpu = dict(value=1.0 / sec_solve, unit="solves/s", cores=threads, kind="oracle",
+                       sample=(f"FP64 oracle set-up ({t1 - t0:.1f} s) and one RSD apply "
+                               f"({t2 - t1:.2f} s) on the full 64^3 problem; time per solve = "
+                               f"set-up + {beta:.0f} x (apply + SpMV), beta = the FP64 FGMRES "
+                               f"iteration count"))
+        except Exception as e:  # the baseline is a report, not the product
+            cpu = dict(value=None, unit="solves/s", cores=None, kind="oracle",
+                       sample=f"failed: {e!r}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": R0["steps"],
+        "warmup": a.warmup,
+        "ms_per_step": R0["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "diffusion 64^3 Q1 hex, log-normal k (sigma 1), 4x4x4 box "
+                               "sub-domains (octree, 2 interface levels), FGMRES(30) to 1e-10, "
+                               + ("FP32 sub-domain/Sigma/level-1 blocks + FP64 root and Krylov"
+                                  if head == "mixed" else "all FP64"),
+                   "n": int(p.n), "nnz": int(p.K.nnz), "seed": a.seed, "nrhs": 1},
+        "time_to_1e-10_s": {k: r["sec"] for k, r in res.items()},
+        "iterations": {k: r["its"][-1] for k, r in res.items()},
+        "relres": {k: r["relres"] for k, r in res.items()},
+        "solves_per_s_handle_reuse": reuse_sps,
+        "host_analysis_ms": {k: r["host_ms"] for k, r in res.items()},
+        "setup_wall_ms": {k: r["setup_wall_ms"] for k, r in res.items()},
+        "phase_ms_per_step": {k: r["ms"] for k, r in res.items()},
+        "device_bytes": {k: r["device_bytes"] for k, r in res.items()},
+        "roofline": roof,
+        "secondary": extra,
+        "cpu_baseline": cpu,
+    }
+    if "mixed" in res and "fp64" in res:
+        out["mixed_vs_fp64_speedup"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+        xm, xd = res["mixed"]["x"], res["fp64"]["x"]
+        out["mixed_solution_rel_diff_vs_fp64"] = float(np.linalg.norm(xm - xd) / np.linalg.norm(xd))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,17 +182,20 @@ rsd_status rsd_update_values(rsd_handle h, const double* values, void* stream);
 /* Per-handle statistics.  Times are accumulated device times in milliseconds
  * measured with HIP events when the handle was created with timing = 1. */
 enum {
-  RSD_T_SETUP_EXTRACT = 0, /* value gathers, dense block extraction            */
-  RSD_T_LEAF_INVERSE,      /* batched in-place inversion of the K_ll          */
-  RSD_T_SIGMA,             /* Sigma_l blocks                                  */
-  RSD_T_IFACE_ASSEMBLY,    /* S~_t assembly (extend-add)                      */
-  RSD_T_IFACE_INVERSE,     /* batched inversion of the S~_t                   */
-  RSD_T_LEAF_APPLY,        /* batched symmetric products with K_ll^-1         */
-  RSD_T_IFACE_APPLY,       /* batched symmetric products with S~_t^-1         */
-  RSD_T_COUPLING,          /* sparse couplings, Sigma products, g assembly    */
-  RSD_T_SPMV,              /* global SpMV                                     */
-  RSD_T_KRYLOV,            /* dots, orthogonalisation, vector updates         */
-  RSD_T_PERMUTE,           /* user <-> internal dof ordering                  */
+  RSD_T_SETUP_EXTRACT = 0, /* value gathers, dense block extraction                    */
+  RSD_T_LEAF_INVERSE,      /* batched in-place inversion of the K_ll (all kernels)    */
+  RSD_T_LEAF_UPDATE,       /*   of which: the MFMA trailing-update kernels            */
+  RSD_T_SIGMA,             /* Sigma_l blocks                                          */
+  RSD_T_IFACE_ASSEMBLY,    /* S~_t assembly (extend-add)                              */
+  RSD_T_IFACE_INVERSE,     /* batched inversion of the S~_t (all kernels)             */
+  RSD_T_IFACE_UPDATE,      /*   of which: MFMA update kernels, non-root levels        */
+  RSD_T_ROOT_UPDATE,       /*   of which: MFMA update kernels, root level             */
+  RSD_T_LEAF_APPLY,        /* batched symmetric products with K_ll^-1                 */
+  RSD_T_IFACE_APPLY,       /* batched symmetric products with S~_t^-1                 */
+  RSD_T_COUPLING,          /* sparse couplings, Sigma products, g assembly            */
+  RSD_T_SPMV,              /* global SpMV                                             */
+  RSD_T_KRYLOV,            /* dots, orthogonalisation, vector updates                 */
+  RSD_T_PERMUTE,           /* caller <-> internal dof ordering                        */
   RSD_T_COUNT
 };
 typedef struct {
@@ -201,6 +204,11 @@ typedef struct {
   int64_t launches[RSD_T_COUNT];
   double host_analysis_ms; /* wall time of step 1 of rsd_setup                 */
   int64_t device_bytes;    /* device memory held by the handle                */
+  double setup_wall_ms[4]; /* last rsd_setup / rsd_update_values, host wall time:
+                              [0] structure copy to the host and analysis,
+                              [1] device allocation and index upload,
+                              [2] enqueueing the dense set-up,
+                              [3] waiting for it and releasing scratch memory  */
 } rsd_stats;
 
 /* Copies the handle's statistics (synchronises `stream` when timing is on).

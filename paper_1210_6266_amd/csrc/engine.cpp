@@ -9,6 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <type_traits>
 
 namespace rsd {
 
@@ -24,11 +27,38 @@ void hip_check(rsd_ctx* h, hipError_t e, const char* what) {
   throw Fail{e == hipErrorOutOfMemory ? RSD_ERR_OUT_OF_MEMORY : RSD_ERR_DEVICE};
 }
 
+// Device memory comes from one stream-ordered pool per device, owned by the library:
+// memory released by a handle stays in the pool (up to kPoolKeepBytes) and serves the
+// next set-up without new device mappings.
+constexpr uint64_t kPoolKeepBytes = uint64_t(32) << 30;
+
+hipMemPool_t device_pool(rsd_ctx* h, int device) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(device);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  hipMemPool_t pool;
+  hip_check(h, hipMemPoolCreate(&pool, &props), "hipMemPoolCreate");
+  uint64_t keep = kPoolKeepBytes;
+  hip_check(h, hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep),
+            "hipMemPoolSetAttribute");
+  pools[device] = pool;
+  return pool;
+}
+
 template <typename T>
 T* dalloc(rsd_ctx* h, size_t count) {
   if (count == 0) count = 1;
   void* p = nullptr;
-  hip_check(h, hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  hip_check(h, hipMallocFromPoolAsync(&p, count * sizeof(T), h->mempool, h->cur),
+            "hipMallocFromPoolAsync");
   h->allocs.push_back({p, count * sizeof(T)});
   h->device_bytes += int64_t(count * sizeof(T));
   return static_cast<T*>(p);
@@ -42,17 +72,28 @@ void dfree(rsd_ctx* h, void* p) {
       h->allocs.erase(h->allocs.begin() + long(i));
       break;
     }
-  (void)hipFree(p);
+  (void)hipFreeAsync(p, h->cur);
 }
 
-template <typename T>
-T* upload(rsd_ctx* h, const std::vector<T>& v, hipStream_t s) {
-  T* d = dalloc<T>(h, v.size());
-  if (!v.empty())
-    hip_check(h, hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
+// Packs many host arrays into one device allocation and one host-to-device copy:
+// add() records the destination pointer, commit() allocates, copies and patches.
+struct Uploader {
+  std::vector<char> host;
+  std::vector<std::pair<void**, size_t>> fix;
+  template <typename T, typename P>
+  void add(P** dst, const std::vector<T>& v) {
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    fix.push_back({reinterpret_cast<void**>(const_cast<typename std::remove_const<P>::type**>(dst)), off});
+  }
+  void commit(rsd_ctx* h, hipStream_t s) {
+    char* d = dalloc<char>(h, host.size());
+    hip_check(h, hipMemcpyAsync(d, host.data(), host.size(), hipMemcpyHostToDevice, s),
               "hipMemcpyAsync H2D");
-  return d;
-}
+    for (auto& f : fix) *f.first = d + f.second;
+  }
+};
 
 // Times the launches enqueued during its lifetime on stream s (when timing is on).
 struct Timer {
@@ -84,6 +125,10 @@ struct Timer {
   }
 };
 
+double ms_since(std::chrono::steady_clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
+
 void fold_timings(rsd_ctx* h) {
   for (auto& p : h->pending) {
     float ms = 0.f;
@@ -95,32 +140,77 @@ void fold_timings(rsd_ctx* h) {
   h->pending.clear();
 }
 
-DevBatch upload_batch(rsd_ctx* h, const SymBatch& b, bool fp32, hipStream_t s) {
-  DevBatch d;
-  d.count = b.count;
-  d.max_nt = b.max_nt;
-  d.max_tiles = b.max_tiles;
-  d.n = upload(h, b.n, s);
-  d.nt = upload(h, b.nt, s);
-  d.tile_off = upload(h, b.tile_off, s);
-  d.vec_off = upload(h, b.vec_off, s);
-  d.num_items = int32_t(b.item_mat.size());
-  d.item_mat = upload(h, b.item_mat, s);
-  d.item_J = upload(h, b.item_J, s);
-  d.item_I0 = upload(h, b.item_I0, s);
-  d.item_I1 = upload(h, b.item_I1, s);
-  d.item_cslot = upload(h, b.item_cslot, s);
-  d.rslot_off = upload(h, b.rslot_off, s);
-  d.cstrip_ptr = upload(h, b.cstrip_ptr, s);
-  d.cstrip_base = upload(h, b.cstrip_base, s);
-  d.fp32 = fp32 ? 1 : 0;
+void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool fp32) {
+  d->count = b.count;
+  d->max_nt = b.max_nt;
+  d->max_tiles = b.max_tiles;
+  up.add(&d->n, b.n);
+  up.add(&d->nt, b.nt);
+  up.add(&d->tile_off, b.tile_off);
+  up.add(&d->vec_off, b.vec_off);
+  d->num_items = int32_t(b.item_mat.size());
+  up.add(&d->item_mat, b.item_mat);
+  up.add(&d->item_J, b.item_J);
+  up.add(&d->item_I0, b.item_I0);
+  up.add(&d->item_I1, b.item_I1);
+  up.add(&d->item_cslot, b.item_cslot);
+  up.add(&d->rslot_off, b.rslot_off);
+  up.add(&d->cstrip_ptr, b.cstrip_ptr);
+  up.add(&d->cstrip_base, b.cstrip_base);
+  d->fp32 = fp32 ? 1 : 0;
   if (b.total_elems > 0) {
     if (fp32)
-      d.tiles = dalloc<float>(h, size_t(b.total_elems));
+      d->tiles = dalloc<float>(h, size_t(b.total_elems));
     else
-      d.tiles = dalloc<double>(h, size_t(b.total_elems));
+      d->tiles = dalloc<double>(h, size_t(b.total_elems));
   }
-  return d;
+}
+
+// Blocked sweep inversion of a batch; the MFMA update launches are timed as `upd`.
+// With two-tile pivot groups the next step's pivot and panel run on the auxiliary
+// stream as soon as the tiles they read are updated (look-ahead), overlapping the
+// bulk of the current update; the panel buffers alternate between steps.
+void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void* bbuf[2],
+                  int32_t* flags, int upd, hipStream_t s) {
+  const int G = h->group;
+  if (b.count == 0 || b.max_nt == 0) return;
+  if (G != 2) {
+    for (int c0 = 0; c0 < b.max_nt; c0 += G) {
+      hip_check(h, launch_sweep_step(b, c0, 0, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep pivot");
+      hip_check(h, launch_sweep_step(b, c0, 1, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep panel");
+      Timer tm(h, upd, s);
+      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep update");
+    }
+    return;
+  }
+  hipStream_t a = h->aux;
+  hip_check(h, launch_sweep_step(b, 0, 0, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep pivot");
+  hip_check(h, launch_sweep_step(b, 0, 1, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep panel");
+  int k = 0;
+  for (int c0 = 0; c0 < b.max_nt; c0 += G, ++k) {
+    const int cur = k & 1, nxt = cur ^ 1;
+    const bool more = c0 + G < b.max_nt;
+    if (more) {
+      {
+        Timer tm(h, upd, s);
+        hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s, 1),
+                  "sweep update (look-ahead part)");
+      }
+      hip_check(h, hipEventRecord(h->ev_main, s), "hipEventRecord");
+      hip_check(h, hipStreamWaitEvent(a, h->ev_main, 0), "hipStreamWaitEvent");
+      hip_check(h, launch_sweep_step(b, c0 + G, 0, pbuf, cbuf[nxt], bbuf[nxt], flags, G, a),
+                "sweep pivot");
+      hip_check(h, launch_sweep_step(b, c0 + G, 1, pbuf, cbuf[nxt], bbuf[nxt], flags, G, a),
+                "sweep panel");
+      hip_check(h, hipEventRecord(h->ev_aux, a), "hipEventRecord");
+    }
+    {
+      Timer tm(h, upd, s);
+      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s,
+                                     more ? 2 : 0), "sweep update");
+    }
+    if (more) hip_check(h, hipStreamWaitEvent(s, h->ev_aux, 0), "hipStreamWaitEvent");
+  }
 }
 
 int choose_lpr(double avg) {
@@ -157,6 +247,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     } else {
       rsd_options_default(&h->opt);
     }
+    const auto w0 = std::chrono::steady_clock::now();
     const int32_t n = csr->n;
     const int64_t nnz = csr->nnz;
     const int32_t T = hier->num_nodes;
@@ -191,74 +282,107 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       h->err = msg;
       return pe == PlanError::kNotSeparable ? RSD_ERR_MAP_NOT_SEPARABLE : RSD_ERR_INVALID_ARGUMENT;
     }
+    h->setup_wall[0] = ms_since(w0);
+    const auto w1 = std::chrono::steady_clock::now();
     hip_check(h, hipGetDevice(&h->device), "hipGetDevice");
+    h->mempool = device_pool(h, h->device);
+    h->cur = s;
+    // auxiliary stream (default priority) and events of the look-ahead in the inversions
+    hip_check(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
+    hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
     const Plan& P = h->P;
     if (const char* g = std::getenv("RSD_SWEEP_GROUP")) h->group = std::max(1, std::min(2, std::atoi(g)));
     h->lpr = choose_lpr(double(nnz) / double(n));
-    // ---- upload structure
-    h->prow = upload(h, P.prow, s);
-    h->pcol = upload(h, P.pcol, s);
-    h->pmap = upload(h, P.pmap, s);
-    h->segA = upload(h, P.segA, s);
-    h->segB = upload(h, P.segB, s);
-    h->segC = upload(h, P.segC, s);
-    h->perm = upload(h, P.perm, s);
+    // ---- upload structure (one allocation, one copy)
+    Uploader up;
+    up.add(&h->prow, P.prow);
+    up.add(&h->perm, P.perm);
+    up.add(&h->iperm, P.iperm);
+    up.add(&h->skel_lvl_begin, P.skel_lvl_begin);
+    up.add(&h->skel_own_end, P.skel_own_end);
+    h->pcol = dalloc<int32_t>(h, size_t(nnz));
+    h->pmap = dalloc<int64_t>(h, size_t(nnz));
+    h->segA = dalloc<int64_t>(h, size_t(n));
+    h->segB = dalloc<int64_t>(h, size_t(n));
+    h->segC = dalloc<int64_t>(h, size_t(n));
     h->pval = dalloc<double>(h, size_t(nnz));
-    h->B_off = upload(h, P.B_off, s);
-    h->B = upload(h, P.B, s);
-    h->adj_ptr = upload(h, P.adj_ptr, s);
-    h->adj_leaf = upload(h, P.adj_leaf, s);
-    h->adj_pos = upload(h, P.adj_pos, s);
-    h->sig_off_d = upload(h, P.sig_off, s);
+    up.add(&h->B_off, P.B_off);
+    up.add(&h->B, P.B);
+    up.add(&h->adj_ptr, P.adj_ptr);
+    up.add(&h->adj_leaf, P.adj_leaf);
+    up.add(&h->adj_pos, P.adj_pos);
+    up.add(&h->sig_off_d, P.sig_off);
     SigmaArgs& a = h->sig;
     a.num_leaves = int32_t(P.leaf_node.size());
     a.max_m = P.max_m;
-    a.B_off = h->B_off;
-    a.B = h->B;
-    a.shell_off = upload(h, P.shell_off, s);
-    a.shell = upload(h, P.shell, s);
-    a.kcol_ptr = upload(h, P.kcol_ptr, s);
-    a.kcol_row = upload(h, P.kcol_row, s);
-    a.kcol_val = upload(h, P.kcol_val, s);
-    a.krow_ptr = upload(h, P.krow_ptr, s);
-    a.krow_col = upload(h, P.krow_col, s);
-    a.krow_val = upload(h, P.krow_val, s);
-    a.w_off = upload(h, P.w_off, s);
-    a.sig_off = h->sig_off_d;
-    a.pval = h->pval;
+    up.add(&a.shell_off, P.shell_off);
+    up.add(&a.shell, P.shell);
+    up.add(&a.kcol_ptr, P.kcol_ptr);
+    up.add(&a.kcol_row, P.kcol_row);
+    up.add(&h->kcol_pos, P.kcol_val);
+    up.add(&a.krow_ptr, P.krow_ptr);
+    up.add(&a.krow_col, P.krow_col);
+    up.add(&h->krow_pos, P.krow_val);
+    up.add(&a.w_off, P.w_off);
+    h->kcol_v = dalloc<double>(h, P.kcol_val.size());
+    h->krow_v = dalloc<double>(h, P.krow_val.size());
+    a.kcol_v = h->kcol_v;
+    a.krow_v = h->krow_v;
     h->sigma_fp32 = h->opt.sigma_prec == RSD_PREC_FP32;
     if (h->sigma_fp32)
       h->sigma = dalloc<float>(h, size_t(P.sig_total));
     else
       h->sigma = dalloc<double>(h, size_t(P.sig_total));
-    h->leaf = upload_batch(h, P.leaf_batch, h->opt.leaf_prec == RSD_PREC_FP32, s);
+    upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec == RSD_PREC_FP32);
     const int NL = int(P.level_depth.size());
-    h->lev.clear();
-    h->lev_items.clear();
+    h->lev.assign(NL, DevBatch());
+    h->lev_items.assign(NL, SigmaLevelItems());
     int64_t max_c = P.leaf_batch.num_cslots, max_r = P.leaf_batch.num_rslots;
+    std::vector<std::vector<int32_t>> il(NL), ir0(NL), ia0(NL), ia1(NL);
     for (int q = 0; q < NL; ++q) {
       const bool root = P.level_depth[q] == 0;
       const int prec = root ? h->opt.root_prec : h->opt.iface_prec;
-      h->lev.push_back(upload_batch(h, P.level_batch[q], prec == RSD_PREC_FP32, s));
+      upload_batch(h, up, &h->lev[q], P.level_batch[q], prec == RSD_PREC_FP32);
       max_c = std::max(max_c, P.level_batch[q].num_cslots);
       max_r = std::max(max_r, P.level_batch[q].num_rslots);
-      // Sigma products of this level, split into row chunks of 64
-      std::vector<int32_t> il, ir0, ia0, ia1;
+      // Sigma products of this level, split into row chunks of 256
       for (const auto& it : P.level_sigma[q])
-        for (int32_t a0 = it.r0; a0 < it.r1; a0 += 64) {
-          il.push_back(it.leaf);
-          ir0.push_back(it.r0);
-          ia0.push_back(a0);
-          ia1.push_back(std::min(it.r1, a0 + 64));
+        for (int32_t a0 = it.r0; a0 < it.r1; a0 += 256) {
+          il[q].push_back(it.leaf);
+          ir0[q].push_back(it.r0);
+          ia0[q].push_back(a0);
+          ia1[q].push_back(std::min(it.r1, a0 + 256));
         }
-      SigmaLevelItems li;
-      li.count = int32_t(il.size());
-      li.leaf = upload(h, il, s);
-      li.r0 = upload(h, ir0, s);
-      li.a0 = upload(h, ia0, s);
-      li.a1 = upload(h, ia1, s);
-      h->lev_items.push_back(li);
+      SigmaLevelItems& li = h->lev_items[q];
+      li.count = int32_t(il[q].size());
+      up.add(&li.leaf, il[q]);
+      up.add(&li.r0, ir0[q]);
+      up.add(&li.a0, ia0[q]);
+      up.add(&li.a1, ia1[q]);
     }
+    // the caller's CSR structure on the device (copied when given on the host)
+    const int64_t* d_rp = csr->row_ptr;
+    const int32_t* d_ci = csr->col_idx;
+    int64_t* tmp_rp = nullptr;
+    int32_t* tmp_ci = nullptr;
+    if (h->opt.host_pointers) {
+      std::vector<int64_t> vr(csr->row_ptr, csr->row_ptr + n + 1);
+      std::vector<int32_t> vc(csr->col_idx, csr->col_idx + nnz);
+      up.add(&tmp_rp, vr);
+      up.add(&tmp_ci, vc);
+      up.commit(h, s);
+      d_rp = tmp_rp;
+      d_ci = tmp_ci;
+    } else {
+      up.commit(h, s);
+    }
+    hip_check(h, launch_permute_csr(n, P.n_leaf, h->perm, h->iperm, d_rp, d_ci, h->prow,
+                                    h->skel_lvl_begin, h->skel_own_end, h->pcol, h->pmap,
+                                    h->segA, h->segB, h->segC, s), "permute csr");
+    a.B_off = h->B_off;
+    a.B = h->B;
+    a.sig_off = h->sig_off_d;
     const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
     h->flags = dalloc<int32_t>(h, size_t(nflags));
     h->e = dalloc<double>(h, std::max<size_t>(1, P.B.size()));
@@ -268,6 +392,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->cpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_c)) * kTile);
     h->rpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_r)) * kTile);
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    h->setup_wall[1] = ms_since(w1);
     return RSD_OK;
   } catch (const Fail& f) {
     return f.st;
@@ -279,10 +404,16 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
 // operator of Alg. 1 assembled and inverted.
 rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
   try {
+    h->cur = s;
+    const auto w2 = std::chrono::steady_clock::now();
     const Plan& P = h->P;
     {
       Timer tm(h, RSD_T_SETUP_EXTRACT, s);
       hip_check(h, launch_gather(values, h->pmap, P.nnz, h->pval, s), "gather values");
+      hip_check(h, launch_gather(values, h->kcol_pos, int64_t(P.kcol_val.size()), h->kcol_v, s),
+                "gather couplings");
+      hip_check(h, launch_gather(values, h->krow_pos, int64_t(P.krow_val.size()), h->krow_v, s),
+                "gather couplings");
       const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
       hip_check(h, hipMemsetAsync(h->flags, 0, size_t(nflags) * 4, s), "hipMemsetAsync flags");
       hip_check(h, launch_sym_fill(h->leaf, s), "leaf fill");
@@ -300,12 +431,11 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       need_c = std::max(need_c, cb);
     }
     char* pbuf = dalloc<char>(h, need_p);
-    char* cbuf = dalloc<char>(h, need_c);
-    char* bbuf = dalloc<char>(h, need_c);
+    void* cbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
+    void* bbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
     {
       Timer tm(h, RSD_T_LEAF_INVERSE, s);
-      hip_check(h, launch_sym_invert(h->leaf, pbuf, cbuf, bbuf, h->flags, h->group, s),
-                "leaf inversion");
+      invert_batch(h, h->leaf, pbuf, cbuf, bbuf, h->flags, RSD_T_LEAF_UPDATE, s);
     }
     double* W = dalloc<double>(h, size_t(std::max<int64_t>(1, P.w_total)));
     {
@@ -329,11 +459,12 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       }
       {
         Timer tm(h, RSD_T_IFACE_INVERSE, s);
-        hip_check(h, launch_sym_invert(h->lev[q], pbuf, cbuf, bbuf,
-                                       iflags + P.level_iface_begin[q], h->group, s),
-                  "interface inversion");
+        invert_batch(h, h->lev[q], pbuf, cbuf, bbuf, iflags + P.level_iface_begin[q],
+                     P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, s);
       }
     }
+    h->setup_wall[2] = ms_since(w2);
+    const auto w3 = std::chrono::steady_clock::now();
     std::vector<int32_t> fl(P.leaf_node.size() + P.iface_node.size());
     if (!fl.empty())
       hip_check(h, hipMemcpyAsync(fl.data(), h->flags, fl.size() * 4, hipMemcpyDeviceToHost, s),
@@ -341,8 +472,11 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     dfree(h, W);
     dfree(h, pbuf);
-    dfree(h, cbuf);
-    dfree(h, bbuf);
+    for (int i = 0; i < 2; ++i) {
+      dfree(h, cbuf[i]);
+      dfree(h, bbuf[i]);
+    }
+    h->setup_wall[3] = ms_since(w3);
     for (size_t i = 0; i < fl.size(); ++i)
       if (fl[i]) {
         char buf[256];
@@ -691,6 +825,7 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
                         int64_t ldx, const rsd_solve_options* opt, rsd_solve_info* info,
                         hipStream_t s) {
   try {
+    h->cur = s;
     rsd_solve_options o;
     if (opt) {
       o = *opt;
@@ -740,6 +875,7 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
     }
     out->host_analysis_ms = h->host_ms;
     out->device_bytes = h->device_bytes;
+    for (int i = 0; i < 4; ++i) out->setup_wall_ms[i] = h->setup_wall[i];
     if (reset) {
       std::memset(h->time_ms, 0, sizeof(h->time_ms));
       std::memset(h->launches, 0, sizeof(h->launches));
@@ -758,8 +894,14 @@ void engine_free(rsd_ctx* h) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
-  for (auto& p : h->allocs) (void)hipFree(p.first);
+  if (h->ev_main) (void)hipEventDestroy(h->ev_main);
+  if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  h->ev_main = h->ev_aux = nullptr;
+  h->aux = nullptr;
+  for (auto& p : h->allocs) (void)hipFreeAsync(p.first, nullptr);
   h->allocs.clear();
+  (void)hipStreamSynchronize(nullptr);
   if (h->hhost) (void)hipHostFree(h->hhost);
   h->hhost = nullptr;
 }

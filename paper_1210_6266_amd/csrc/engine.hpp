@@ -17,13 +17,18 @@ struct rsd_ctx {
   std::string err;
   int device = 0;
 
+  hipMemPool_t mempool = nullptr;   // library pool of this device
+  hipStream_t cur = nullptr;      // stream of the running call (stream-ordered allocations)
   // every device allocation of the handle
   std::vector<std::pair<void*, size_t>> allocs;
   int64_t device_bytes = 0;
 
   // K in internal order and the index structures of the plan
   int64_t *prow = nullptr, *segA = nullptr, *segB = nullptr, *segC = nullptr, *pmap = nullptr;
-  int32_t *pcol = nullptr, *perm = nullptr;
+  int32_t *pcol = nullptr, *perm = nullptr, *iperm = nullptr;
+  int32_t *skel_lvl_begin = nullptr, *skel_own_end = nullptr;
+  int64_t *kcol_pos = nullptr, *krow_pos = nullptr;   // caller value positions of couplings
+  double *kcol_v = nullptr, *krow_v = nullptr;
   double* pval = nullptr;
   int64_t *B_off = nullptr, *adj_ptr = nullptr, *sig_off_d = nullptr;
   int32_t *B = nullptr, *adj_leaf = nullptr, *adj_pos = nullptr;
@@ -34,6 +39,8 @@ struct rsd_ctx {
   std::vector<rsd::DevBatch> lev;
   std::vector<rsd::SigmaLevelItems> lev_items;
   int32_t* flags = nullptr;  // one per leaf, then one per interface
+  hipStream_t aux = nullptr;          // look-ahead stream of the inversions
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int lpr = 16;
   int group = 2;             // pivot tiles per sweep step
 
@@ -54,6 +61,7 @@ struct rsd_ctx {
   double time_ms[RSD_T_COUNT] = {};
   int64_t launches[RSD_T_COUNT] = {};
   double host_ms = 0.0;
+  double setup_wall[4] = {};
 };
 
 namespace rsd {

@@ -125,6 +125,50 @@ __global__ __launch_bounds__(kBlock) void k_seg_spmv(int64_t row0, int64_t nrows
   if (lane == 0) y[row] = (base ? base[row] : 0.0) + alpha * s;
 }
 
+// Row r of K in internal order: row perm[r] of the caller's CSR with columns renamed by
+// iperm and sorted (insertion sort in place: the renamed row is a few increasing runs),
+// the caller's value position of each entry, and the row segments: first interface
+// column (segA); for interface rows the end of the deeper-level columns (segB) and of
+// the own node's columns (segC).
+__global__ __launch_bounds__(kBlock) void k_permute_csr(
+    int32_t n, int64_t n_leaf, const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const int64_t* __restrict__ prow, const int32_t* __restrict__ skel_lvl_begin,
+    const int32_t* __restrict__ skel_own_end, int32_t* __restrict__ pcol,
+    int64_t* __restrict__ pmap, int64_t* __restrict__ segA, int64_t* __restrict__ segB,
+    int64_t* __restrict__ segC) {
+  const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (r >= n) return;
+  const int32_t o = perm[r];
+  const int64_t k0 = rp[o], len = rp[o + 1] - k0, base = prow[r];
+  int32_t* c = pcol + base;
+  int64_t* v = pmap + base;
+  for (int64_t e = 0; e < len; ++e) {
+    const int32_t nc = iperm[ci[k0 + e]];
+    int64_t w = e;
+    while (w > 0 && c[w - 1] > nc) {
+      c[w] = c[w - 1];
+      v[w] = v[w - 1];
+      --w;
+    }
+    c[w] = nc;
+    v[w] = k0 + e;
+  }
+  int64_t a = 0;
+  while (a < len && c[a] < n_leaf) ++a;
+  segA[r] = base + a;
+  if (r < n_leaf) {
+    segB[r] = segC[r] = base + a;
+    return;
+  }
+  const int32_t lb = skel_lvl_begin[r - n_leaf], oe = skel_own_end[r - n_leaf];
+  int64_t b = a;
+  while (b < len && c[b] < lb) ++b;
+  segB[r] = base + b;
+  while (b < len && c[b] < oe) ++b;
+  segC[r] = base + b;
+}
+
 __global__ void k_fill(double* p, int64_t count, double v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
@@ -178,18 +222,22 @@ __global__ __launch_bounds__(kBlock) void k_sym_extract(T* tiles, const int64_t*
 //   A_ip <- A_ip P,  A_pj <- P A_pj,  A_pp <- -P.
 // After all steps the tiles hold -A^{-1}.
 
-// (1) pivot block: scalar sweeps of the G*64 x G*64 block held in registers
+// (1) pivot block: scalar sweeps of the G*64 x G*64 block held in registers by
+// 1024 threads (a 32 x 32 grid of R x R sub-blocks).  Each pivot p applies the
+// rank-one update to every element (branch-free), then the owners of row p and
+// column p overwrite them with the scaled pivot column and -1/d.
+constexpr int kPivotThreads = 1024;
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_sweep_pivot(T* tiles, const int64_t* tile_off,
-                                                        const int32_t* nt_arr, int c0, T* pbuf,
-                                                        int32_t* flags) {
-  constexpr int PB = G * TS, R = PB / 16;
+__global__ __launch_bounds__(kPivotThreads) void k_sweep_pivot(T* tiles, const int64_t* tile_off,
+                                                               const int32_t* nt_arr, int c0,
+                                                               T* pbuf, int32_t* flags) {
+  constexpr int PB = G * TS, R = PB / 32;
   const int m = blockIdx.x;
   const int nt = nt_arr[m];
   if (c0 >= nt) return;
   const int g = min(G, nt - c0), pbm = g * TS;
   T* base = tiles + tile_off[m];
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  const int ty = threadIdx.x / 32, tx = threadIdx.x % 32;
   T a[R][R];
 #pragma unroll
   for (int i = 0; i < R; ++i)
@@ -205,13 +253,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pivot(T* tiles, const int64_t*
   int fail = 0;
   for (int p = 0; p < pbm; ++p) {
     T* cb = colbuf[p & 1];
-    if (tx == p / R) {   // owner of column p publishes it (select keeps a[][] in VGPRs)
-      const int pj = p % R;
+    const int owner = p / R, pp = p % R;
+    if (tx == owner) {   // owner of column p publishes it (select keeps a[][] in VGPRs)
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         T v = a[i][0];
 #pragma unroll
-        for (int j = 1; j < R; ++j) v = (j == pj) ? a[i][j] : v;
+        for (int j = 1; j < R; ++j) v = (j == pp) ? a[i][j] : v;
         cb[ty * R + i] = v;
       }
     }
@@ -227,19 +275,24 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pivot(T* tiles, const int64_t*
     for (int i = 0; i < R; ++i) ci[i] = cb[ty * R + i];
 #pragma unroll
     for (int j = 0; j < R; ++j) cj[j] = cb[tx * R + j];
+    // (c_i c_j) inv is symmetric in (i, j), so an exactly symmetric block stays so
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const int gi = ty * R + i, gj = tx * R + j;
-        if (gi == p) {
-          a[i][j] = (gj == p) ? -inv : cj[j] * inv;
-        } else if (gj == p) {
-          a[i][j] = ci[i] * inv;
-        } else {
-          a[i][j] -= (ci[i] * cj[j]) * inv;
-        }
-      }
+      for (int j = 0; j < R; ++j) a[i][j] -= (ci[i] * cj[j]) * inv;
+    if (ty == owner) {   // row p: c_j / d
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[i][j] = (i == pp) ? cj[j] * inv : a[i][j];
+    }
+    if (tx == owner) {   // column p: c_i / d, and -1/d on the diagonal
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          a[i][j] = (j == pp) ? ((ty == owner && i == pp) ? -inv : ci[i] * inv) : a[i][j];
+    }
   }
   T* P = pbuf + int64_t(m) * PB * PB;
 #pragma unroll
@@ -360,6 +413,135 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update(T* tiles, const int64_t
       }
 }
 
+// (3') the update for two-tile pivot groups, by 128 x 128 super-tiles: a workgroup
+// of 4 waves owns super-tile (BI, BJ) (tiles 2BI..2BI+1 x 2BJ..2BJ+1), each wave one
+// 64 x 64 tile with 16 MFMA accumulators; the operand panels B_i (128 x 128) and
+// C_j (128 x 128) stream through double-buffered, bank-padded LDS in k-chunks.
+// Super-tile ids are spread so that each XCD (every 8th workgroup) owns a
+// contiguous range, i.e. shares the panels of a few super-rows in its L2.
+template <typename T>
+struct Upd2Cfg;
+template <>
+struct Upd2Cfg<double> { static constexpr int KC = 16, LD = 136; };
+template <>
+struct Upd2Cfg<float> { static constexpr int KC = 16, LD = 144; };
+
+template <typename T>
+__global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int64_t* tile_off,
+                                                          const int32_t* nt_arr, int c0,
+                                                          const T* cbuf, const T* bbuf,
+                                                          int64_t stride, int64_t per_xcd,
+                                                          int part) {
+  constexpr int PB = 2 * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NCH = PB / KC;
+  const int m = blockIdx.y;
+  const int nt = nt_arr[m];
+  if (c0 >= nt) return;
+  const int nsb = (nt + 1) / 2;
+  const int gN = c0 / 2 + 1;                   // super index of the next pivot group
+  int BI, BJ;
+  if (part == 1) {                             // only the next group's row and column
+    const int t = blockIdx.x;
+    if (t >= nsb || gN >= nsb) return;
+    BI = t <= gN ? gN : t;
+    BJ = t <= gN ? t : gN;
+  } else {
+    const int64_t s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (s >= tri(nsb)) return;
+    tile_ij(s, &BI, &BJ);
+    if (part == 2 && (BI == gN || BJ == gN)) return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = 2 * BI + (w >> 1), tj = 2 * BJ + (w & 1);
+  const bool valid = ti < nt && tj <= ti;
+  const T* Bb = bbuf + int64_t(m) * stride;
+  const T* Cb = cbuf + int64_t(m) * stride;
+  T* base = tiles + tile_off[m];
+  const int gB = c0 / 2;
+  if (BI == gB || BJ == gB) {
+    if (BI == gB && BJ == gB) return;          // pivot tiles: written by the pivot kernel
+    if (!valid) return;
+    T* A = base + tile_index(ti, tj) * TT;
+    if (BI == gB) {                            // pivot-group row: A_ij <- (B_j[:, i block])^T
+      const T* Bj = Bb + int64_t(tj) * TS * PB + int64_t(ti - c0) * TS * TS;
+      for (int e = lane; e < TT; e += 64) A[e] = Bj[(e / TS) + (e % TS) * TS];
+    } else {                                   // pivot-group column: A_ij <- B_i[:, j block]
+      const T* Bi = Bb + int64_t(ti) * TS * PB + int64_t(tj - c0) * TS * TS;
+      for (int e = lane; e < TT; e += 64) A[e] = Bi[e];
+    }
+    return;
+  }
+  __shared__ T sA[2][KC * LD], sB[2][KC * LD];
+  constexpr int PER = KC * 128 / kBlock;       // elements per thread per operand and chunk
+  T ra[PER], rb[PER];
+  auto gload = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int r = e % 128, kk = e / 128;
+      const int k = ch * KC + kk;
+      const int i = 2 * BI + r / 64, j = 2 * BJ + r / 64;
+      ra[u] = i < nt ? Bb[int64_t(i) * TS * PB + (r % 64) + k * TS] : T(0);
+      rb[u] = j < nt ? Cb[int64_t(j) * TS * PB + (r % 64) + k * TS] : T(0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      sA[buf][(e / 128) * LD + (e % 128)] = ra[u];
+      sB[buf][(e / 128) * LD + (e % 128)] = rb[u];
+    }
+  };
+  // the accumulators start from A_ij (the MFMA's C operand), with the A operand
+  // negated: D = A_ij - B_i C_j^T; the old tile is read while the panels stream in
+  const int li = lane & 15, lk = lane >> 4, g = lane >> 4;
+  T* At = base + tile_index(valid ? ti : 0, valid ? tj : 0) * TT;
+  typename Mfma<T>::v4 acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
+        acc[bi][bj][v] = valid ? At[r + (16 * bj + li) * TS] : T(0);
+      }
+  const int oa = 64 * (w >> 1) + li, ob = 64 * (w & 1) + li;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (ch + 1 < NCH) gload(ch + 1);
+    const T* A_ = sA[ch & 1];
+    const T* B_ = sB[ch & 1];
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = -A_[(kk + lk) * LD + oa + 16 * q];
+        b[q] = B_[(kk + lk) * LD + ob + 16 * q];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+    }
+    if (ch + 1 < NCH) sstore((ch + 1) & 1);
+    __syncthreads();
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
+        At[r + (16 * bj + li) * TS] = acc[bi][bj][v];
+      }
+}
+
 // ---- symmetric products y = base + alpha A x -------------------------------------------
 // phase 1: one work item = tiles (I, J), I in [I0, I1), of strip J.  Column parts
 // (A_IJ^T x_I, and A_JJ x_J on the diagonal tile) accumulate per item; row parts
@@ -417,24 +599,28 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
   }
 }
 
-__global__ void k_symv2(const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
-                        const int64_t* __restrict__ vec_off,
-                        const int64_t* __restrict__ cstrip_base,
-                        const int64_t* __restrict__ cstrip_ptr,
-                        const int64_t* __restrict__ rslot_off, const double* __restrict__ cpart,
-                        const double* __restrict__ rpart, double alpha,
-                        const double* __restrict__ base, double* __restrict__ y) {
-  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_symv2(
+    const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
+    const int64_t* __restrict__ vec_off, const int64_t* __restrict__ cstrip_base,
+    const int64_t* __restrict__ cstrip_ptr, const int64_t* __restrict__ rslot_off,
+    const double* __restrict__ cpart, const double* __restrict__ rpart, double alpha,
+    const double* __restrict__ base, double* __restrict__ y) {
+  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x & 63, part = threadIdx.x >> 6;
   if (I >= nt_arr[m]) return;
   const int row = I * TS + r;
-  if (row >= n_arr[m]) return;
   double s = 0.0;
   const int64_t sb = cstrip_base[m] + I;
-  for (int64_t c = cstrip_ptr[sb]; c < cstrip_ptr[sb + 1]; ++c) s += cpart[c * TS + r];
+  for (int64_t c = cstrip_ptr[sb] + part; c < cstrip_ptr[sb + 1]; c += 4) s += cpart[c * TS + r];
   const int64_t rb = rslot_off[m] + tri(I - 1);
-  for (int Jc = 0; Jc < I; ++Jc) s += rpart[(rb + Jc) * TS + r];
-  const int64_t o = vec_off[m] + row;
-  y[o] = (base ? base[o] : 0.0) + alpha * s;
+  for (int Jc = part; Jc < I; Jc += 4) s += rpart[(rb + Jc) * TS + r];
+  __shared__ double red[4][TS];
+  red[part][r] = s;
+  __syncthreads();
+  if (part == 0 && row < n_arr[m]) {
+    const int64_t o = vec_off[m] + row;
+    const double t = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    y[o] = (base ? base[o] : 0.0) + alpha * t;
+  }
 }
 
 // ================================================================ Schur complements
@@ -454,26 +640,55 @@ __global__ __launch_bounds__(kBlock) void k_sigma_w(const T* __restrict__ tiles,
     const int i = sh[si];
     double v = 0.0;
     for (int64_t e = a.kcol_ptr[f]; e < a.kcol_ptr[f + 1]; ++e)
-      v -= double(sym_elem(base, i, a.kcol_row[e])) * a.pval[a.kcol_val[e]];  // tiles hold -K^-1
+      v -= double(sym_elem(base, i, a.kcol_row[e])) * a.kcol_v[e];   // tiles hold -K^-1
     Wc[si] = v;
   }
 }
 
+constexpr int kSigmaRow = 32;   // max non-zeros of a row of K_{B_l, l} kept in registers
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_sigma_s(SigmaArgs a, const double* __restrict__ W,
-                                                    S* __restrict__ sigma) {
-  const int l = blockIdx.y, b = blockIdx.x;
+                                                    S* __restrict__ sigma, int col_chunk) {
+  // block (row chunk, column chunk, leaf): Sigma_l[a, b] = sum_e K[B_l[a], i_e] W_l[i_e, b]
+  const int l = blockIdx.z;
   const int64_t m = a.B_off[l + 1] - a.B_off[l];
-  if (b >= m) return;
+  const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t b0 = int64_t(blockIdx.y) * col_chunk;
+  if (b0 >= m) return;
+  const int64_t b1 = min<int64_t>(m, b0 + col_chunk);
   const int64_t s = a.shell_off[l + 1] - a.shell_off[l];
-  const double* Wc = W + a.w_off[l] + int64_t(b) * s;
-  S* out = sigma + a.sig_off[l] + int64_t(b) * m;
-  for (int64_t r = threadIdx.x; r < m; r += kBlock) {
+  int32_t col[kSigmaRow];
+  double val[kSigmaRow];
+  int cnt = 0;
+  if (r < m) {
     const int64_t f = a.B_off[l] + r;
+    const int64_t e0 = a.krow_ptr[f], e1 = a.krow_ptr[f + 1];
+    cnt = int(min<int64_t>(e1 - e0, kSigmaRow));
+#pragma unroll
+    for (int e = 0; e < kSigmaRow; ++e)
+      if (e < cnt) {
+        col[e] = a.krow_col[e0 + e];
+        val[e] = a.krow_v[e0 + e];
+      }
+    // rows with more couplings than fit in registers take the slow path below
+    if (e1 - e0 > kSigmaRow) cnt = -1;
+  }
+  if (r >= m) return;
+  const double* Wl = W + a.w_off[l];
+  S* out = sigma + a.sig_off[l];
+  for (int64_t b = b0; b < b1; ++b) {
+    const double* Wc = Wl + b * s;
     double v = 0.0;
-    for (int64_t e = a.krow_ptr[f]; e < a.krow_ptr[f + 1]; ++e)
-      v += a.pval[a.krow_val[e]] * Wc[a.krow_col[e]];
-    out[r] = S(v);
+    if (cnt >= 0) {
+#pragma unroll
+      for (int e = 0; e < kSigmaRow; ++e)
+        if (e < cnt) v += val[e] * Wc[col[e]];
+    } else {
+      const int64_t f = a.B_off[l] + r;
+      for (int64_t e = a.krow_ptr[f]; e < a.krow_ptr[f + 1]; ++e)
+        v += a.krow_v[e] * Wc[a.krow_col[e]];
+    }
+    out[r + b * m] = S(v);
   }
 }
 
@@ -525,22 +740,31 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
     const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
     const double* __restrict__ z, double* __restrict__ e) {
+  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= 256)
   const int it = blockIdx.x;
   const int l = it_leaf[it], r0 = it_r0[it], a0 = it_a0[it], a1 = it_a1[it];
   const int64_t m = B_off[l + 1] - B_off[l];
   const S* Sg = sigma + sig_off[l];
   const int32_t* Bl = B + B_off[l];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int a = a0 + lane;
-  double s = 0.0;
-  if (a < a1)
-    for (int b = w; b < r0; b += 4) s += double(Sg[a + int64_t(b) * m]) * z[Bl[b]];
-  __shared__ double red[4][64];
-  red[w][lane] = s;
-  __syncthreads();
-  if (threadIdx.x < 64 && a0 + int(threadIdx.x) < a1)
-    e[B_off[l] + a0 + threadIdx.x] =
-        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  __shared__ double ub[kBlock];
+  const int a = a0 + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b0 = 0; b0 < r0; b0 += kBlock) {
+    __syncthreads();
+    if (b0 + int(threadIdx.x) < r0) ub[threadIdx.x] = z[Bl[b0 + threadIdx.x]];
+    __syncthreads();
+    const int nb = min(kBlock, r0 - b0);
+    if (a < a1) {
+      const S* col = Sg + a + int64_t(b0) * m;
+      int b = 0;
+      for (; b + 1 < nb; b += 2) {
+        s0 += double(col[int64_t(b) * m]) * ub[b];
+        s1 += double(col[int64_t(b + 1) * m]) * ub[b + 1];
+      }
+      if (b < nb) s0 += double(col[int64_t(b) * m]) * ub[b];
+    }
+  }
+  if (a < a1) e[B_off[l] + a] = s0 + s1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_level_rhs(
@@ -680,6 +904,18 @@ hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const
   return hipGetLastError();
 }
 
+hipError_t launch_permute_csr(int32_t n, int64_t n_leaf, const int32_t* perm, const int32_t* iperm,
+                              const int64_t* rp, const int32_t* ci, const int64_t* prow,
+                              const int32_t* skel_lvl_begin, const int32_t* skel_own_end,
+                              int32_t* pcol, int64_t* pmap, int64_t* segA, int64_t* segB,
+                              int64_t* segC, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_permute_csr<<<blocks_for(n), kBlock, 0, s>>>(n, n_leaf, perm, iperm, rp, ci, prow,
+                                                 skel_lvl_begin, skel_own_end, pcol, pmap, segA,
+                                                 segB, segC);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   k_fill<<<blocks_for(count), kBlock, 0, s>>>(p, count, v);
@@ -718,31 +954,36 @@ size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, si
   return *pbytes + 2 * *cbytes;
 }
 
-template <typename T, int G>
-static hipError_t sym_invert_t(const DevBatch& b, T* pbuf, T* cbuf, T* bbuf, int32_t* flags,
-                               hipStream_t s) {
-  const int64_t stride = int64_t(b.max_nt) * TS * G * TS;
-  for (int c0 = 0; c0 < b.max_nt; c0 += G) {
-    k_sweep_pivot<T, G><<<b.count, kBlock, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0, pbuf, flags);
-    k_sweep_panel<T, G><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
-        (const T*)b.tiles, b.tile_off, b.nt, c0, pbuf, cbuf, bbuf, stride);
-    k_sweep_update<T, G><<<dim3(unsigned(b.max_tiles), b.count), kBlock, 0, s>>>(
-        (T*)b.tiles, b.tile_off, b.nt, c0, cbuf, bbuf, stride);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_sym_invert(const DevBatch& b, void* pbuf, void* cbuf, void* bbuf,
-                             int32_t* flags, int group, hipStream_t s) {
+hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, void* cbuf,
+                             void* bbuf, int32_t* flags, int group, hipStream_t s, int part) {
   if (b.count == 0 || b.max_nt == 0) return hipSuccess;
+  const int64_t stride = int64_t(b.max_nt) * TS * group * TS;
+#define RSD_STEP(T, G)                                                                          \
+  do {                                                                                          \
+    if (stage == 0)                                                                             \
+      k_sweep_pivot<T, G><<<b.count, kPivotThreads, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,         \
+                                                     (T*)pbuf, flags);                          \
+    else if (stage == 1)                                                                        \
+      k_sweep_panel<T, G><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(                           \
+          (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
+    else if (G == 2) {                                                                          \
+      const int64_t nsb = (b.max_nt + 1) / 2, ns = nsb * (nsb + 1) / 2;                         \
+      const int64_t per_xcd = (ns + 7) / 8;                                                     \
+      const unsigned gx = part == 1 ? unsigned(nsb) : unsigned(8 * per_xcd);                   \
+      k_sweep_update2<T><<<dim3(gx, b.count), kBlock, 0, s>>>(                                  \
+          (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride, per_xcd,   \
+          part);                                                                                \
+    } else                                                                                      \
+      k_sweep_update<T, G><<<dim3(unsigned(b.max_tiles), b.count), kBlock, 0, s>>>(             \
+          (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride);           \
+  } while (0)
   if (b.fp32) {
-    if (group == 2) return sym_invert_t<float, 2>(b, (float*)pbuf, (float*)cbuf, (float*)bbuf, flags, s);
-    return sym_invert_t<float, 1>(b, (float*)pbuf, (float*)cbuf, (float*)bbuf, flags, s);
+    if (group == 2) RSD_STEP(float, 2); else RSD_STEP(float, 1);
+  } else {
+    if (group == 2) RSD_STEP(double, 2); else RSD_STEP(double, 1);
   }
-  if (group == 2) return sym_invert_t<double, 2>(b, (double*)pbuf, (double*)cbuf, (double*)bbuf, flags, s);
-  return sym_invert_t<double, 1>(b, (double*)pbuf, (double*)cbuf, (double*)bbuf, flags, s);
+#undef RSD_STEP
+  return hipGetLastError();
 }
 
 hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
@@ -756,7 +997,7 @@ hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double
     k_symv1<double><<<b.num_items, kBlock, 0, s>>>(
         (const double*)b.tiles, b.tile_off, b.n, b.vec_off, b.item_mat, b.item_J, b.item_I0,
         b.item_I1, b.item_cslot, b.rslot_off, x, cpart, rpart);
-  k_symv2<<<dim3(b.max_nt, b.count), TS, 0, s>>>(b.n, b.nt, b.vec_off, b.cstrip_base,
+  k_symv2<<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(b.n, b.nt, b.vec_off, b.cstrip_base,
                                                   b.cstrip_ptr, b.rslot_off, cpart, rpart,
                                                   alpha, base, y);
   return hipGetLastError();
@@ -775,11 +1016,12 @@ hipError_t launch_sigma_w(const DevBatch& leaf, const SigmaArgs& a, double* W, h
 hipError_t launch_sigma_s(const SigmaArgs& a, const double* W, void* sigma, int sigma_fp32,
                           hipStream_t s) {
   if (a.num_leaves == 0 || a.max_m == 0) return hipSuccess;
-  dim3 grid(a.max_m, a.num_leaves);
+  const int chunk = 64;
+  dim3 grid(blocks_for(a.max_m), unsigned((a.max_m + chunk - 1) / chunk), a.num_leaves);
   if (sigma_fp32)
-    k_sigma_s<float><<<grid, kBlock, 0, s>>>(a, W, (float*)sigma);
+    k_sigma_s<float><<<grid, kBlock, 0, s>>>(a, W, (float*)sigma, chunk);
   else
-    k_sigma_s<double><<<grid, kBlock, 0, s>>>(a, W, (double*)sigma);
+    k_sigma_s<double><<<grid, kBlock, 0, s>>>(a, W, (double*)sigma, chunk);
   return hipGetLastError();
 }
 
@@ -828,7 +1070,7 @@ hipError_t launch_level_rhs(int64_t row0, int64_t nrows, int64_t n_leaf, const i
 }
 
 int mdot_blocks(int64_t n) {
-  int64_t b = (n + 4095) / 4096;
+  int64_t b = (n + 511) / 512;
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return int(b);

@@ -47,6 +47,13 @@ hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const
                            const double* base, double alpha, double* y, int lanes_per_row,
                            hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// K in internal order from the caller's CSR (device arrays): pcol, pmap (caller value
+// position of each entry) and the row segments segA / segB / segC
+hipError_t launch_permute_csr(int32_t n, int64_t n_leaf, const int32_t* perm, const int32_t* iperm,
+                              const int64_t* rp, const int32_t* ci, const int64_t* prow,
+                              const int32_t* skel_lvl_begin, const int32_t* skel_own_end,
+                              int32_t* pcol, int64_t* pmap, int64_t* segA, int64_t* segB,
+                              int64_t* segC, hipStream_t s);
 
 // ---- dense symmetric batches ------------------------------------------------------------
 hipError_t launch_sym_fill(const DevBatch& b, hipStream_t s);
@@ -54,10 +61,16 @@ hipError_t launch_sym_fill(const DevBatch& b, hipStream_t s);
 hipError_t launch_sym_extract(const DevBatch& b, const int64_t* s0, const int64_t* s1,
                               const int32_t* pcol, const double* pval, int32_t max_n,
                               hipStream_t s);
-// in-place inversion by blocked symmetric sweeps; returns -A^{-1} in the tiles;
-// flags[m] != 0 marks a non-positive or non-finite pivot in matrix m
-hipError_t launch_sym_invert(const DevBatch& b, void* pbuf, void* cbuf, void* bbuf,
-                             int32_t* flags, int group, hipStream_t s);
+// In-place inversion by blocked symmetric sweeps, one step over the pivot tile
+// columns [c0, c0 + group): stage 0 inverts the pivot block (scalar sweeps in
+// registers; flags[m] != 0 marks a non-positive or non-finite pivot of matrix m),
+// stage 1 forms the panels C_i = A_ip and B_i = C_i P, stage 2 updates every other
+// lower tile (MFMA).  Steps c0 = 0, group, 2 group, ... < max_nt leave -A^{-1}.
+// For group = 2 the update can be split: part 1 updates only the tiles in the row
+// and column of the next pivot group (what the next pivot and panel read), part 2
+// the others; part 0 updates all.
+hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, void* cbuf,
+                             void* bbuf, int32_t* flags, int group, hipStream_t s, int part = 0);
 size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, size_t* cbytes);
 // y = base + alpha * A x for every matrix of the batch (x, y internal vectors)
 hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
@@ -72,13 +85,12 @@ struct SigmaArgs {
   const int32_t* shell;
   const int64_t* kcol_ptr;
   const int32_t* kcol_row;
-  const int64_t* kcol_val;
+  const double* kcol_v;     // values of K_{l,B_l} by columns
   const int64_t* krow_ptr;
   const int32_t* krow_col;
-  const int64_t* krow_val;
+  const double* krow_v;     // values of K_{B_l,l} by rows
   const int64_t* w_off;
   const int64_t* sig_off;
-  const double* pval;
 };
 // W_l = K_ll^{-1}[shell, :] K_{l,B_l}  (from the leaf batch's -K_ll^{-1} tiles)
 hipError_t launch_sigma_w(const DevBatch& leaf, const SigmaArgs& a, double* W, hipStream_t s);

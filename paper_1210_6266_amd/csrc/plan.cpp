@@ -2,8 +2,11 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
+#include <functional>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 namespace rsd {
@@ -17,6 +20,56 @@ std::string fmt(const char* f, long long a = 0, long long b = 0, long long c = 0
 }
 
 int64_t tiles_of(int64_t nt) { return nt * (nt + 1) / 2; }
+
+int num_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return int(std::max(1u, std::min(16u, hc)));
+}
+
+// Runs fn(lo, hi, worker) over [0, count) split into contiguous chunks, one per worker.
+void parallel_for(int64_t count, const std::function<void(int64_t, int64_t, int)>& fn) {
+  const int nt = int(std::min<int64_t>(num_threads(), std::max<int64_t>(1, count / 4096 + 1)));
+  if (nt <= 1) {
+    fn(0, count, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (count + nt - 1) / nt;
+  for (int w = 0; w < nt; ++w) {
+    const int64_t lo = std::min(count, int64_t(w) * chunk), hi = std::min(count, lo + chunk);
+    th.emplace_back(fn, lo, hi, w);
+  }
+  for (auto& t : th) t.join();
+}
+
+typedef std::vector<std::pair<int64_t, std::pair<PlanError, std::string>>> ErrList;
+
+// Runs a row check in parallel; the error of the lowest failing row is reported, so
+// the message does not depend on the thread schedule.
+PlanError check_rows(int64_t n, const std::function<bool(int64_t, PlanError*, std::string*)>& bad,
+                     std::string* msg) {
+  std::vector<ErrList> per(16);
+  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+    for (int64_t i = lo; i < hi; ++i) {
+      PlanError e;
+      std::string m;
+      if (bad(i, &e, &m)) {
+        per[w].push_back({i, {e, m}});
+        return;
+      }
+    }
+  });
+  int64_t best = INT64_MAX;
+  PlanError code = PlanError::kOk;
+  for (auto& p : per)
+    for (auto& f : p)
+      if (f.first < best) {
+        best = f.first;
+        code = f.second.first;
+        *msg = f.second.second;
+      }
+  return code;
+}
 
 }  // namespace
 
@@ -76,27 +129,41 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     *msg = fmt("row_ptr[0] must be 0 and row_ptr[n] = nnz (%lld), got %lld", nnz, row_ptr[n]);
     return PlanError::kInvalid;
   }
-  for (int32_t i = 0; i < n; ++i) {
-    if (row_ptr[i + 1] < row_ptr[i]) { *msg = fmt("row_ptr decreases at row %lld", i); return PlanError::kInvalid; }
+  for (int32_t i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) {
+      *msg = fmt("row_ptr decreases at row %lld", i);
+      return PlanError::kInvalid;
+    }
+  PlanError e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
     for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
       const int32_t c = col_idx[k];
-      if (c < 0 || c >= n) { *msg = fmt("column index %lld out of range in row %lld", c, i); return PlanError::kInvalid; }
+      if (c < 0 || c >= n) {
+        *code = PlanError::kInvalid;
+        *m = fmt("column index %lld out of range in row %lld", c, i);
+        return true;
+      }
       if (k > row_ptr[i] && c <= col_idx[k - 1]) {
-        *msg = fmt("columns of row %lld not strictly increasing", i);
-        return PlanError::kInvalid;
+        *code = PlanError::kInvalid;
+        *m = fmt("columns of row %lld not strictly increasing", i);
+        return true;
       }
     }
-  }
-  // structural symmetry
-  for (int32_t i = 0; i < n; ++i) {
+    return false;
+  }, msg);
+  if (e != PlanError::kOk) return e;
+  // structural symmetry: (i, j) present => (j, i) present
+  e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
     for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
       const int32_t j = col_idx[k];
-      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
-        *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing", i, j);
-        return PlanError::kInvalid;
+      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
+        *code = PlanError::kInvalid;
+        *m = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing", i, j);
+        return true;
       }
     }
-  }
+    return false;
+  }, msg);
+  if (e != PlanError::kOk) return e;
   // ---- validation of the tree ----------------------------------------------------------
   if (T <= 0 || parent == nullptr || dof_node == nullptr) {
     *msg = "hierarchy needs num_nodes >= 1, parent and dof_node";
@@ -147,28 +214,34 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     return tin[a] <= tin[b] && tout[b] <= tout[a];
   };
   // separability: every coupling joins nodes on one root-to-leaf path
-  for (int32_t i = 0; i < n; ++i) {
+  e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
     const int32_t a = dof_node[i];
     for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
       const int32_t b = dof_node[col_idx[k]];
       if (!anc(a, b) && !anc(b, a)) {
-        *msg = fmt("K couples dof %lld and dof %lld whose tree nodes are not on one root-to-leaf path "
-                   "(node %lld)", i, col_idx[k], a);
-        return PlanError::kNotSeparable;
+        *code = PlanError::kNotSeparable;
+        *m = fmt("K couples dof %lld and dof %lld whose tree nodes are not on one root-to-leaf "
+                 "path (node %lld)", i, col_idx[k], a);
+        return true;
       }
     }
-  }
+    return false;
+  }, msg);
+  if (e != PlanError::kOk) return e;
 
   // ---- orderings ---------------------------------------------------------------------
-  std::vector<std::vector<int32_t>> owned(T);
-  for (int32_t i = 0; i < n; ++i) owned[dof_node[i]].push_back(i);
-  std::vector<int32_t> leaf_index(T, -1);
+  std::vector<int64_t> own_ptr(size_t(T) + 1, 0);
+  std::vector<int32_t> own(n);
+  for (int32_t i = 0; i < n; ++i) own_ptr[dof_node[i] + 1]++;
+  for (int32_t t = 0; t < T; ++t) own_ptr[t + 1] += own_ptr[t];
+  {
+    std::vector<int64_t> fill(own_ptr.begin(), own_ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i) own[fill[dof_node[i]]++] = i;
+  }
+  auto owned_n = [&](int32_t t) { return own_ptr[t + 1] - own_ptr[t]; };
   P->leaf_node.clear();
   for (int32_t t = 0; t < T; ++t)
-    if (P->children[t].empty()) {
-      leaf_index[t] = int32_t(P->leaf_node.size());
-      P->leaf_node.push_back(t);
-    }
+    if (P->children[t].empty()) P->leaf_node.push_back(t);
   const int32_t L = int32_t(P->leaf_node.size());
   P->perm.resize(n);
   P->iperm.resize(n);
@@ -176,14 +249,15 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   P->leaf_off.assign(L, 0);
   P->leaf_n.assign(L, 0);
   for (int32_t l = 0; l < L; ++l) {
+    const int32_t t = P->leaf_node[l];
     P->leaf_off[l] = pos;
-    P->leaf_n[l] = int64_t(owned[P->leaf_node[l]].size());
-    for (int32_t d : owned[P->leaf_node[l]]) P->perm[pos++] = d;
+    P->leaf_n[l] = owned_n(t);
+    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q) P->perm[pos++] = own[q];
   }
   P->n_leaf = pos;
   std::vector<int32_t> inodes;
   for (int32_t t = 0; t < T; ++t)
-    if (!P->children[t].empty() && !owned[t].empty()) inodes.push_back(t);
+    if (!P->children[t].empty() && owned_n(t) > 0) inodes.push_back(t);
   std::stable_sort(inodes.begin(), inodes.end(),
                    [&](int32_t a, int32_t b) { return P->depth[a] > P->depth[b]; });
   P->iface_node = inodes;
@@ -203,8 +277,8 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       P->level_dof_begin.push_back(pos);
     }
     P->iface_off[s] = pos;
-    P->iface_n[s] = int64_t(owned[t].size());
-    for (int32_t d : owned[t]) P->perm[pos++] = d;
+    P->iface_n[s] = owned_n(t);
+    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q) P->perm[pos++] = own[q];
   }
   if (NI > 0) P->level_dof_end.push_back(pos);
   P->level_iface_begin.push_back(NI);
@@ -212,74 +286,155 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   for (int32_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = i;
   const int64_t nB = n - P->n_leaf;
   P->dof_level.assign(nB, 0);
+  P->skel_lvl_begin.assign(nB, 0);
+  P->skel_own_end.assign(nB, 0);
   for (int32_t q = 0; q < NL; ++q)
-    for (int64_t d = P->level_dof_begin[q]; d < P->level_dof_end[q]; ++d)
+    for (int64_t d = P->level_dof_begin[q]; d < P->level_dof_end[q]; ++d) {
       P->dof_level[d - P->n_leaf] = q;
-  std::vector<int32_t> dof_iface(nB, -1);
+      P->skel_lvl_begin[d - P->n_leaf] = int32_t(P->level_dof_begin[q]);
+    }
   for (int32_t s = 0; s < NI; ++s)
     for (int64_t d = P->iface_off[s]; d < P->iface_off[s] + P->iface_n[s]; ++d)
-      dof_iface[d - P->n_leaf] = s;
+      P->skel_own_end[d - P->n_leaf] = int32_t(P->iface_off[s] + P->iface_n[s]);
+  // row pointers of K in internal order
+  P->prow.assign(size_t(n) + 1, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t o = P->perm[r];
+    P->prow[r + 1] = P->prow[r] + (row_ptr[o + 1] - row_ptr[o]);
+  }
 
-  // ---- K in internal order, with segment boundaries -----------------------------------
-  P->prow.assign(n + 1, 0);
-  P->pcol.resize(nnz);
-  P->pmap.resize(nnz);
-  P->segA.assign(n, 0);
-  P->segB.assign(n, 0);
-  P->segC.assign(n, 0);
+  // ---- per leaf: B_l, shell_l, K_{l,B_l} by columns, K_{B_l,l} by rows ----------------
+  // (read from the caller's CSR; value positions are the caller's)
+  struct LeafOut {
+    std::vector<int32_t> B, shell, kcol_row, krow_col;
+    std::vector<int64_t> kcol_ptr, kcol_val, krow_ptr, krow_val;
+  };
+  std::vector<LeafOut> lo_out(L);
   {
-    std::vector<std::pair<int32_t, int64_t>> row;
-    int64_t w = 0;
-    for (int32_t r = 0; r < n; ++r) {
-      const int32_t o = P->perm[r];
-      row.clear();
-      for (int64_t k = row_ptr[o]; k < row_ptr[o + 1]; ++k) row.push_back({P->iperm[col_idx[k]], k});
-      std::sort(row.begin(), row.end());
-      P->prow[r] = w;
-      for (auto& e : row) {
-        P->pcol[w] = e.first;
-        P->pmap[w] = e.second;
-        ++w;
-      }
-    }
-    P->prow[n] = w;
-    for (int32_t r = 0; r < n; ++r) {
-      const int32_t* b = P->pcol.data() + P->prow[r];
-      const int32_t* e = P->pcol.data() + P->prow[r + 1];
-      P->segA[r] = (std::lower_bound(b, e, int32_t(P->n_leaf)) - P->pcol.data());
-      if (r >= P->n_leaf) {
-        const int32_t q = P->dof_level[r - P->n_leaf];
-        const int32_t s = dof_iface[r - P->n_leaf];
-        P->segB[r] = std::lower_bound(b, e, int32_t(P->level_dof_begin[q])) - P->pcol.data();
-        P->segC[r] = std::lower_bound(b, e, int32_t(P->iface_off[s] + P->iface_n[s])) - P->pcol.data();
-      } else {
-        P->segB[r] = P->segC[r] = P->segA[r];
-      }
-    }
+    std::atomic<int32_t> next{0};
+    std::vector<std::thread> th;
+    const int nw = std::min<int>(num_threads(), std::max(1, L));
+    for (int w = 0; w < nw; ++w)
+      th.emplace_back([&]() {
+        std::vector<int32_t> posB(size_t(std::max<int64_t>(1, nB)), -1);
+        std::vector<int32_t> shell_idx;
+        for (;;) {
+          const int32_t l = next++;
+          if (l >= L) break;
+          LeafOut& o = lo_out[l];
+          const int64_t off = P->leaf_off[l], nl = P->leaf_n[l];
+          shell_idx.assign(size_t(nl), -1);
+          // B_l and the shell (posB tags the interface dofs already seen in this leaf)
+          for (int64_t r = 0; r < nl; ++r) {
+            const int32_t orow = P->perm[off + r];
+            bool coupled = false;
+            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+              const int32_t c = P->iperm[col_idx[k]];
+              if (c < P->n_leaf) continue;
+              coupled = true;
+              if (posB[c - P->n_leaf] != -2) {
+                posB[c - P->n_leaf] = -2;
+                o.B.push_back(c);
+              }
+            }
+            if (coupled) {
+              shell_idx[r] = int32_t(o.shell.size());
+              o.shell.push_back(int32_t(r));
+            }
+          }
+          std::sort(o.B.begin(), o.B.end());
+          const int64_t m = int64_t(o.B.size());
+          for (int64_t a = 0; a < m; ++a) posB[o.B[a] - P->n_leaf] = int32_t(a);
+          // columns of K_{l,B}
+          o.kcol_ptr.assign(size_t(m) + 1, 0);
+          for (int64_t r = 0; r < nl; ++r) {
+            const int32_t orow = P->perm[off + r];
+            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+              const int32_t c = P->iperm[col_idx[k]];
+              if (c >= P->n_leaf) o.kcol_ptr[posB[c - P->n_leaf] + 1]++;
+            }
+          }
+          for (int64_t a = 0; a < m; ++a) o.kcol_ptr[a + 1] += o.kcol_ptr[a];
+          o.kcol_row.assign(size_t(o.kcol_ptr[m]), 0);
+          o.kcol_val.assign(size_t(o.kcol_ptr[m]), 0);
+          {
+            std::vector<int64_t> fill(o.kcol_ptr.begin(), o.kcol_ptr.end() - 1);
+            for (int64_t r = 0; r < nl; ++r) {
+              const int32_t orow = P->perm[off + r];
+              for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+                const int32_t c = P->iperm[col_idx[k]];
+                if (c < P->n_leaf) continue;
+                const int64_t f = fill[posB[c - P->n_leaf]]++;
+                o.kcol_row[f] = int32_t(r);
+                o.kcol_val[f] = k;
+              }
+            }
+          }
+          // rows of K_{B,l}
+          o.krow_ptr.assign(size_t(m) + 1, 0);
+          for (int64_t a = 0; a < m; ++a) {
+            const int32_t orow = P->perm[o.B[a]];
+            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+              const int32_t c = P->iperm[col_idx[k]];
+              if (c < off || c >= off + nl) continue;
+              o.krow_col.push_back(shell_idx[c - off]);
+              o.krow_val.push_back(k);
+            }
+            o.krow_ptr[a + 1] = int64_t(o.krow_col.size());
+          }
+          for (int64_t a = 0; a < m; ++a) posB[o.B[a] - P->n_leaf] = -1;
+        }
+      });
+    for (auto& t : th) t.join();
   }
-
-  // ---- leaf boundaries and adjacency ---------------------------------------------------
+  for (int32_t l = 0; l < L; ++l)
+    for (int32_t v : lo_out[l].krow_col)
+      if (v < 0) {
+        *msg = "internal error: interface row couples to a non-shell interior dof";
+        return PlanError::kInvalid;
+      }
+  // concatenate the per-leaf pieces
   P->B_off.assign(L + 1, 0);
-  P->B.clear();
   P->shell_off.assign(L + 1, 0);
-  P->shell.clear();
-  std::vector<int32_t> shell_idx;  // per internal leaf dof: index in its shell or -1
-  shell_idx.assign(P->n_leaf, -1);
+  int64_t nkc = 0, nkr = 0;
   for (int32_t l = 0; l < L; ++l) {
-    std::vector<int32_t> bl;
-    for (int64_t r = P->leaf_off[l]; r < P->leaf_off[l] + P->leaf_n[l]; ++r) {
-      if (P->segA[r] < P->prow[r + 1]) {
-        shell_idx[r] = int32_t(P->shell.size() - P->shell_off[l]);
-        P->shell.push_back(int32_t(r - P->leaf_off[l]));
-      }
-      for (int64_t k = P->segA[r]; k < P->prow[r + 1]; ++k) bl.push_back(P->pcol[k]);
-    }
-    std::sort(bl.begin(), bl.end());
-    bl.erase(std::unique(bl.begin(), bl.end()), bl.end());
-    P->B.insert(P->B.end(), bl.begin(), bl.end());
-    P->B_off[l + 1] = int64_t(P->B.size());
-    P->shell_off[l + 1] = int64_t(P->shell.size());
+    P->B_off[l + 1] = P->B_off[l] + int64_t(lo_out[l].B.size());
+    P->shell_off[l + 1] = P->shell_off[l] + int64_t(lo_out[l].shell.size());
+    nkc += int64_t(lo_out[l].kcol_row.size());
+    nkr += int64_t(lo_out[l].krow_col.size());
   }
+  const int64_t nBflat = P->B_off[L];
+  P->B.clear();
+  P->shell.clear();
+  P->B.reserve(nBflat);
+  P->shell.reserve(P->shell_off[L]);
+  P->kcol_ptr.assign(nBflat + 1, 0);
+  P->krow_ptr.assign(nBflat + 1, 0);
+  P->kcol_row.clear();
+  P->kcol_val.clear();
+  P->krow_col.clear();
+  P->krow_val.clear();
+  P->kcol_row.reserve(nkc);
+  P->kcol_val.reserve(nkc);
+  P->krow_col.reserve(nkr);
+  P->krow_val.reserve(nkr);
+  for (int32_t l = 0; l < L; ++l) {
+    LeafOut& o = lo_out[l];
+    const int64_t base = P->B_off[l];
+    const int64_t kc0 = int64_t(P->kcol_row.size()), kr0 = int64_t(P->krow_col.size());
+    for (size_t a = 0; a < o.B.size(); ++a) {
+      P->kcol_ptr[base + a + 1] = kc0 + o.kcol_ptr[a + 1];
+      P->krow_ptr[base + a + 1] = kr0 + o.krow_ptr[a + 1];
+    }
+    P->B.insert(P->B.end(), o.B.begin(), o.B.end());
+    P->shell.insert(P->shell.end(), o.shell.begin(), o.shell.end());
+    P->kcol_row.insert(P->kcol_row.end(), o.kcol_row.begin(), o.kcol_row.end());
+    P->kcol_val.insert(P->kcol_val.end(), o.kcol_val.begin(), o.kcol_val.end());
+    P->krow_col.insert(P->krow_col.end(), o.krow_col.begin(), o.krow_col.end());
+    P->krow_val.insert(P->krow_val.end(), o.krow_val.begin(), o.krow_val.end());
+    o = LeafOut();
+  }
+  // adjacency of interface dofs: (leaf, position in B_l), sorted by leaf
   P->adj_ptr.assign(nB + 1, 0);
   for (int32_t p : P->B) P->adj_ptr[p - P->n_leaf + 1]++;
   for (int64_t i = 0; i < nB; ++i) P->adj_ptr[i + 1] += P->adj_ptr[i];
@@ -295,7 +450,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
         ++fill[p];
       }
   }
-  // Sigma layouts and the sparse pieces K_{l,B_l}, K_{B_l,l}
+  // Sigma and W layouts
   P->sig_off.assign(L + 1, 0);
   P->w_off.assign(L + 1, 0);
   P->max_m = 0;
@@ -310,66 +465,6 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   }
   P->sig_total = P->sig_off[L];
   P->w_total = P->w_off[L];
-  const int64_t nBflat = int64_t(P->B.size());
-  P->kcol_ptr.assign(nBflat + 1, 0);
-  P->krow_ptr.assign(nBflat + 1, 0);
-  // K_{l,B}: columns of the leaf rows' interface suffix
-  for (int32_t l = 0; l < L; ++l) {
-    const int32_t* Bb = P->B.data() + P->B_off[l];
-    const int32_t* Be = P->B.data() + P->B_off[l + 1];
-    for (int64_t r = P->leaf_off[l]; r < P->leaf_off[l] + P->leaf_n[l]; ++r)
-      for (int64_t k = P->segA[r]; k < P->prow[r + 1]; ++k) {
-        const int64_t b = std::lower_bound(Bb, Be, P->pcol[k]) - Bb;
-        P->kcol_ptr[P->B_off[l] + b + 1]++;
-      }
-  }
-  for (int64_t i = 0; i < nBflat; ++i) P->kcol_ptr[i + 1] += P->kcol_ptr[i];
-  P->kcol_row.assign(P->kcol_ptr[nBflat], 0);
-  P->kcol_val.assign(P->kcol_ptr[nBflat], 0);
-  {
-    std::vector<int64_t> fill(P->kcol_ptr.begin(), P->kcol_ptr.end() - 1);
-    for (int32_t l = 0; l < L; ++l) {
-      const int32_t* Bb = P->B.data() + P->B_off[l];
-      const int32_t* Be = P->B.data() + P->B_off[l + 1];
-      for (int64_t r = P->leaf_off[l]; r < P->leaf_off[l] + P->leaf_n[l]; ++r)
-        for (int64_t k = P->segA[r]; k < P->prow[r + 1]; ++k) {
-          const int64_t f = P->B_off[l] + (std::lower_bound(Bb, Be, P->pcol[k]) - Bb);
-          P->kcol_row[fill[f]] = int32_t(r - P->leaf_off[l]);
-          P->kcol_val[fill[f]] = k;
-          ++fill[f];
-        }
-    }
-  }
-  // K_{B,l}: the entries of interface row B_l[a] that fall in leaf l
-  for (int32_t l = 0; l < L; ++l)
-    for (int64_t a = P->B_off[l]; a < P->B_off[l + 1]; ++a) {
-      const int32_t p = P->B[a];
-      const int32_t* b = P->pcol.data() + P->prow[p];
-      const int32_t* e = P->pcol.data() + P->segA[p];
-      const int64_t lo = std::lower_bound(b, e, int32_t(P->leaf_off[l])) - b;
-      const int64_t hi = std::lower_bound(b, e, int32_t(P->leaf_off[l] + P->leaf_n[l])) - b;
-      P->krow_ptr[a + 1] = hi - lo;
-    }
-  for (int64_t i = 0; i < nBflat; ++i) P->krow_ptr[i + 1] += P->krow_ptr[i];
-  P->krow_col.assign(P->krow_ptr[nBflat], 0);
-  P->krow_val.assign(P->krow_ptr[nBflat], 0);
-  for (int32_t l = 0; l < L; ++l)
-    for (int64_t a = P->B_off[l]; a < P->B_off[l + 1]; ++a) {
-      const int32_t p = P->B[a];
-      int64_t w = P->krow_ptr[a];
-      for (int64_t k = P->prow[p]; k < P->segA[p]; ++k) {
-        const int32_t c = P->pcol[k];
-        if (c < P->leaf_off[l] || c >= P->leaf_off[l] + P->leaf_n[l]) continue;
-        const int32_t si = shell_idx[c];
-        if (si < 0) {
-          *msg = "internal error: interface row couples to a non-shell interior dof";
-          return PlanError::kInvalid;
-        }
-        P->krow_col[w] = si;
-        P->krow_val[w] = k;
-        ++w;
-      }
-    }
 
   // ---- apply schedule: Sigma products per level --------------------------------------
   P->level_sigma.assign(NL, {});

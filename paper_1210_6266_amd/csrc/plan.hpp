@@ -72,14 +72,11 @@ struct Plan {
   // ordering
   std::vector<int32_t> perm, iperm;          // internal -> caller, caller -> internal
 
-  // K in internal order
+  // K in internal order: row pointers here; the columns, the map to the caller's
+  // value positions and the row segments are built on the device from perm/iperm
   std::vector<int64_t> prow;
-  std::vector<int32_t> pcol;
-  std::vector<int64_t> pmap;                 // internal value position -> caller position
-  std::vector<int64_t> segA;                 // leaf row: first interface column
-                                             // interface row: end of leaf columns
-  std::vector<int64_t> segB;                 // interface row: end of deeper-level columns
-  std::vector<int64_t> segC;                 // interface row: end of own-node columns
+  std::vector<int32_t> skel_lvl_begin;       // per interface dof: first dof of its level
+  std::vector<int32_t> skel_own_end;         // per interface dof: end of its node's dofs
 
   // leaf boundaries B_l (internal interface dof indices)
   std::vector<int64_t> B_off;                // per leaf, size num_leaves + 1
@@ -94,11 +91,11 @@ struct Plan {
   //   shell_l = interior rows of l coupled to B_l (local indices)
   std::vector<int64_t> shell_off;
   std::vector<int32_t> shell;
-  //   columns of K_{l B}: per flat column (B_off[l] + b): (local row j, value position)
+  //   columns of K_{l B}: per flat column (B_off[l] + b): (local row j, caller position)
   std::vector<int64_t> kcol_ptr;
   std::vector<int32_t> kcol_row;
   std::vector<int64_t> kcol_val;
-  //   rows of K_{B l}: per flat row (B_off[l] + a): (shell index, value position)
+  //   rows of K_{B l}: per flat row (B_off[l] + a): (shell index, caller position)
   std::vector<int64_t> krow_ptr;
   std::vector<int32_t> krow_col;
   std::vector<int64_t> krow_val;
@@ -119,7 +116,7 @@ struct Plan {
 
 enum class PlanError { kOk = 0, kInvalid = 1, kNotSeparable = 2 };
 
-// Builds the plan from host arrays.  Returns kOk, or an error with *msg set.
+// Builds the plan from host arrays (multithreaded).  Returns kOk, or an error with *msg.
 PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                      int32_t num_nodes, const int32_t* parent, const int32_t* dof_node,
                      Plan* plan, std::string* msg);

@@ -24,8 +24,9 @@ STATUS = {0: "RSD_OK", 1: "RSD_ERR_INVALID_ARGUMENT", 2: "RSD_ERR_MAP_NOT_SEPARA
           6: "RSD_ERR_OUT_OF_MEMORY", 7: "RSD_ERR_DEVICE", 8: "RSD_ERR_UNSUPPORTED"}
 PREC = {"fp64": 0, "fp32": 1}
 SOLVER = {"fgmres": 0, "pcg": 1}
-TIMER_NAMES = ["setup_extract", "leaf_inverse", "sigma", "iface_assembly", "iface_inverse",
-               "leaf_apply", "iface_apply", "coupling", "spmv", "krylov", "permute"]
+TIMER_NAMES = ["setup_extract", "leaf_inverse", "leaf_update", "sigma", "iface_assembly",
+               "iface_inverse", "iface_update", "root_update", "leaf_apply", "iface_apply",
+               "coupling", "spmv", "krylov", "permute"]
 
 
 class rsd_csr(C.Structure):
@@ -63,9 +64,9 @@ class rsd_analysis(C.Structure):
 
 
 class rsd_stats(C.Structure):
-    _fields_ = [("analysis", rsd_analysis), ("time_ms", C.c_double * 11),
-                ("launches", C.c_int64 * 11), ("host_analysis_ms", C.c_double),
-                ("device_bytes", C.c_int64)]
+    _fields_ = [("analysis", rsd_analysis), ("time_ms", C.c_double * 14),
+                ("launches", C.c_int64 * 14), ("host_analysis_ms", C.c_double),
+                ("device_bytes", C.c_int64), ("setup_wall_ms", C.c_double * 4)]
 
 
 EXPORTS = ["rsd_options_default", "rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv",
@@ -228,10 +229,11 @@ def rsd_get_stats(handle, reset=False, stream=None) -> dict:
     s = rsd_stats()
     _check(load().rsd_get_stats(handle, C.byref(s), 1 if reset else 0, _stream(stream)), handle)
     out = {k: getattr(s.analysis, k) for k, _ in rsd_analysis._fields_}
-    out["time_ms"] = {TIMER_NAMES[i]: s.time_ms[i] for i in range(11)}
-    out["launches"] = {TIMER_NAMES[i]: s.launches[i] for i in range(11)}
+    out["time_ms"] = {TIMER_NAMES[i]: s.time_ms[i] for i in range(len(TIMER_NAMES))}
+    out["launches"] = {TIMER_NAMES[i]: s.launches[i] for i in range(len(TIMER_NAMES))}
     out["host_analysis_ms"] = s.host_analysis_ms
     out["device_bytes"] = s.device_bytes
+    out["setup_wall_ms"] = list(s.setup_wall_ms)
     return out
 
 
