@@ -34,8 +34,12 @@ METRIC = "time-to-1e-10 residual & solves/s, mixed-batched vs FP64 RSD; GB/s, MF
 PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
 MIXED = dict(leaf_prec="fp32", sigma_prec="fp32", iface_prec="fp32", root_prec="fp64")
 FP64 = dict(leaf_prec="fp64", sigma_prec="fp64", iface_prec="fp64", root_prec="fp64")
-GROUP_TILES = 2          # pivot tiles per sweep step (default of the library)
 TILE = 64
+
+
+def group_tiles(n):
+    """Pivot tiles per sweep step that the library picks for matrices of order n."""
+    return 4 if (n + TILE - 1) // TILE >= 16 else 2
 
 
 def parse():
@@ -51,12 +55,13 @@ def parse():
     return ap.parse_args()
 
 
-def update_flops(sizes, steps_group=GROUP_TILES):
+def update_flops(sizes):
     """Algorithmic flops of the MFMA trailing updates of one blocked sweep inversion
     per matrix of order n: per step with w real pivot columns, the n - w other rows
     and columns receive a rank-w update of their lower triangle: w (n-w)(n-w+1)."""
     tot = 0.0
     for n in sizes:
+        steps_group = group_tiles(max(sizes))
         nt = (n + TILE - 1) // TILE
         for c0 in range(0, nt, steps_group):
             lo = c0 * TILE

@@ -167,14 +167,21 @@ void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool
 }
 
 // Blocked sweep inversion of a batch; the MFMA update launches are timed as `upd`.
-// With two-tile pivot groups the next step's pivot and panel run on the auxiliary
+// With two- or four-tile pivot groups the next step's pivot and panel run on the auxiliary
 // stream as soon as the tiles they read are updated (look-ahead), overlapping the
 // bulk of the current update; the panel buffers alternate between steps.
+// Pivot tiles per sweep step: four (K = 256 for the MFMA update, half the passes over
+// the matrix) unless the matrices are small; RSD_SWEEP_GROUP overrides.
+int group_for(const rsd_ctx* h, const DevBatch& b) {
+  if (h->group > 0) return h->group;
+  return b.max_nt >= 16 ? 4 : 2;
+}
+
 void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void* bbuf[2],
                   int32_t* flags, int upd, hipStream_t s) {
-  const int G = h->group;
+  const int G = group_for(h, b);
   if (b.count == 0 || b.max_nt == 0) return;
-  if (G != 2) {
+  if (G < 2) {
     for (int c0 = 0; c0 < b.max_nt; c0 += G) {
       hip_check(h, launch_sweep_step(b, c0, 0, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep pivot");
       hip_check(h, launch_sweep_step(b, c0, 1, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep panel");
@@ -292,7 +299,11 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
     const Plan& P = h->P;
-    if (const char* g = std::getenv("RSD_SWEEP_GROUP")) h->group = std::max(1, std::min(2, std::atoi(g)));
+    h->group = 0;
+    if (const char* g = std::getenv("RSD_SWEEP_GROUP")) {
+      const int v = std::atoi(g);
+      h->group = (v == 1 || v == 2 || v == 4) ? v : 0;
+    }
     h->lpr = choose_lpr(double(nnz) / double(n));
     // ---- upload structure (one allocation, one copy)
     Uploader up;
@@ -422,11 +433,11 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     }
     // scratch of the sweeps: sized for the largest batch
     size_t pb = 0, cb = 0, need_p = 0, need_c = 0;
-    sym_invert_scratch_bytes(h->leaf, h->group, &pb, &cb);
+    sym_invert_scratch_bytes(h->leaf, group_for(h, h->leaf), &pb, &cb);
     need_p = pb;
     need_c = cb;
     for (const auto& L : h->lev) {
-      sym_invert_scratch_bytes(L, h->group, &pb, &cb);
+      sym_invert_scratch_bytes(L, group_for(h, L), &pb, &cb);
       need_p = std::max(need_p, pb);
       need_c = std::max(need_c, cb);
     }

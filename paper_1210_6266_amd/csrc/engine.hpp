@@ -42,7 +42,7 @@ struct rsd_ctx {
   hipStream_t aux = nullptr;          // look-ahead stream of the inversions
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int lpr = 16;
-  int group = 2;             // pivot tiles per sweep step
+  int group = 0;             // pivot tiles per sweep step (0: by batch size)
 
   // apply work vectors (internal order)
   double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;

@@ -309,7 +309,207 @@ __global__ __launch_bounds__(kPivotThreads) void k_sweep_pivot(T* tiles, const i
   if (fail && threadIdx.x == 0) flags[m] = c0 + 1;
 }
 
-// (2) panel: C_i = A_{i,p} (64 x PB), B_i = C_i P
+// ---- blocked pivot: the pivot group (G tiles) inverted by one workgroup in 64-wide
+// sub-steps.  Each diagonal 64 x 64 block is swept by a single wave (wave-synchronous:
+// the pivot column is broadcast through LDS without workgroup barriers); the panel and
+// the update inside the group are single-wave 64 x 64 x 64 MFMA products.
+
+// ordering of a wave's LDS writes before its later reads (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 64 scalar sweeps of the symmetric 64 x 64 block at A (column-major, ld 64) by one
+// wave, lanes on an 8 x 8 grid holding 8 x 8 each: A <- -A^{-1}, P <- A^{-1} (ld 64).
+// The inner eight pivots are unrolled so that every register index is static: the
+// owners of row / column p overwrite one row / column of their block directly.
+template <typename T>
+__device__ __forceinline__ void wave_sweep64(T* A, T* P, T* col, int* fail) {
+  const int lane = threadIdx.x & 63, ly = lane >> 3, lx = lane & 7;
+  T a[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[i][j] = A[(ly * 8 + i) + (lx * 8 + j) * TS];
+  int f = 0;
+  for (int ob = 0; ob < 8; ++ob) {
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const int p = ob * 8 + pp;
+      T* cb = col + (pp & 1) * TS;
+      if (lx == ob) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cb[ly * 8 + i] = a[i][pp];
+      }
+      wave_sync();
+      T d = cb[p];
+      if (!(d > T(0)) || !(d < T(INFINITY))) {
+        f = 1;
+        d = T(1);
+      }
+      const T inv = T(1) / d;
+      T ci[8], cs[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ci[i] = cb[ly * 8 + i];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cs[j] = cb[lx * 8 + j] * inv;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[i][j] = fma(-ci[i], cs[j], a[i][j]);
+      if (ly == ob) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[pp][j] = cs[j];           // row p: c_j / d
+      }
+      if (lx == ob) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i][pp] = ci[i] * inv;     // column p: c_i / d
+        if (ly == ob) a[pp][pp] = -inv;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      A[(ly * 8 + i) + (lx * 8 + j) * TS] = a[i][j];
+      P[(ly * 8 + i) + (lx * 8 + j) * TS] = -a[i][j];
+    }
+  if (f) *fail = 1;
+}
+
+// one wave: acc += A(64 x 64) B(64 x 64) on MFMA 16x16x4, acc[bi][bj] at acc_pos64
+template <typename T, typename LA, typename LB>
+__device__ __forceinline__ void wave_gemm64(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < TS; k += 4) {
+    T a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = lda(16 * q + li, k + lk);
+      b[q] = ldb(k + lk, 16 * q + li);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ int acc_row64(int bi, int v) {
+  const int g = (threadIdx.x & 63) >> 4;
+  return 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_pivot_blk(T* tiles, const int64_t* tile_off,
+                                                            const int32_t* nt_arr, int c0,
+                                                            T* pbuf, int32_t* flags) {
+  constexpr int PB = G * TS;
+  const int m = blockIdx.x;
+  const int nt = nt_arr[m];
+  if (c0 >= nt) return;
+  const int g = min(G, nt - c0);
+  T* base = tiles + tile_off[m];
+  __shared__ T Ps[TT];
+  __shared__ T Bs[(G > 1 ? G - 1 : 1) * TT];
+  __shared__ T col[2 * TS];
+  __shared__ int fail;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  auto tl = [&](int r, int c) { return base + tile_index(c0 + r, c0 + c) * TT; };
+  for (int s = 0; s < g; ++s) {
+    if (w == 0) wave_sweep64(tl(s, s), Ps, col, &fail);
+    __syncthreads();
+    // panel of the group: B_r = C_r P_s, C_r = A[r][s] (tile (r,s) or (s,r)^T)
+    if (w < g && w != s) {
+      const int r = w;
+      const T* Cr = r > s ? tl(r, s) : tl(s, r);
+      const bool tr = r < s;
+      typename Mfma<T>::v4 acc[4][4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+      wave_gemm64<T>([&](int row, int k) { return tr ? Cr[k + row * TS] : Cr[row + k * TS]; },
+                     [&](int k, int c) { return Ps[c + k * TS]; }, acc);
+      T* Br = Bs + (r < s ? r : r - 1) * TT;
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Br[acc_row64<T>(bi, v) + (16 * bj + li) * TS] = acc[bi][bj][v];
+    }
+    __syncthreads();
+    // update inside the group: A_rq -= B_r C_q^T for r >= q, r, q != s
+    int item = 0;
+    for (int r = 0; r < g; ++r)
+      for (int q = 0; q <= r; ++q) {
+        if (r == s || q == s) continue;
+        if ((item++ & 3) != w) continue;
+        T* A = tl(r, q);
+        const T* Cq = q > s ? tl(q, s) : tl(s, q);
+        const bool tq = q < s;
+        const T* Br = Bs + (r < s ? r : r - 1) * TT;
+        typename Mfma<T>::v4 acc[4][4];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[acc_row64<T>(bi, v) + (16 * bj + li) * TS];
+        wave_gemm64<T>([&](int row, int k) { return -Br[row + k * TS]; },
+                       [&](int k, int c) { return tq ? Cq[k + c * TS] : Cq[c + k * TS]; }, acc);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[acc_row64<T>(bi, v) + (16 * bj + li) * TS] = acc[bi][bj][v];
+      }
+    __syncthreads();
+    // row and column s of the group: A[r][s] <- B_r (r > s), A[s][q] <- B_q^T (q < s)
+    for (int r = 0; r < g; ++r) {
+      if (r == s) continue;
+      const T* Br = Bs + (r < s ? r : r - 1) * TT;
+      T* A = r > s ? tl(r, s) : tl(s, r);
+      if (r > s)
+        for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Br[e];
+      else
+        for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Br[(e / TS) + (e % TS) * TS];
+    }
+    __syncthreads();
+  }
+  // P = -(swept group block) as a full PB x PB matrix, tile by tile (identity on padding)
+  T* P = pbuf + int64_t(m) * PB * PB;
+  for (int t = w; t < G * G; t += 4) {
+    const int I = t % G, J = t / G;
+    if (I < g && J < g) {
+      const T* src = I >= J ? tl(I, J) : tl(J, I);
+      const bool tr = I < J;
+#pragma unroll 8
+      for (int u = 0; u < TS; ++u) {
+        const int r = lane, c = u;
+        const T v = tr ? src[c + r * TS] : src[r + c * TS];
+        P[(I * TS + r) + int64_t(J * TS + c) * PB] = -v;
+      }
+    } else {
+#pragma unroll 8
+      for (int u = 0; u < TS; ++u)
+        P[(I * TS + lane) + int64_t(J * TS + u) * PB] = (I == J && lane == u) ? T(1) : T(0);
+    }
+  }
+  if (fail && threadIdx.x == 0) flags[m] = c0 + 1;
+}
+
+// (2) panel: C_i = A_{i,p} (64 x PB), B_i = C_i P, with C_i staged through LDS one
+// 64-column chunk at a time (P is symmetric: its columns are read as rows, coalesced)
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_sweep_panel(const T* tiles, const int64_t* tile_off,
                                                         const int32_t* nt_arr, int c0,
@@ -319,34 +519,42 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel(const T* tiles, const in
   const int m = blockIdx.y, i = blockIdx.x;
   const int nt = nt_arr[m];
   if (c0 >= nt || i >= nt) return;
-  const int g = min(G, nt - c0), pbm = g * TS;
+  const int g = min(G, nt - c0);
   if (i >= c0 && i < c0 + g) return;
   const T* base = tiles + tile_off[m];
-  __shared__ T C[TS * PB];
-  for (int e = threadIdx.x; e < TS * PB; e += kBlock) {
-    const int r = e % TS, cc = e / TS;
-    T v = T(0);
-    if (cc < pbm) {
-      const int J = c0 + cc / TS;
-      v = (i > J) ? base[tile_index(i, J) * TT + r + (cc % TS) * TS]
-                  : base[tile_index(J, i) * TT + (cc % TS) + r * TS];
-    }
-    C[e] = v;
-  }
-  __syncthreads();
+  __shared__ T C[TS * TS];
   T* Cout = cbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
-  for (int e = threadIdx.x; e < TS * PB; e += kBlock) Cout[e] = C[e];
-  const T* P = pbuf + int64_t(m) * PB * PB;
   T* Bout = bbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
+  const T* P = pbuf + int64_t(m) * PB * PB;
+  typename Mfma<T>::v4 acc[G][2][2];
 #pragma unroll
-  for (int cb = 0; cb < G; ++cb) {
-    typename Mfma<T>::v4 acc[2][2];
+  for (int cb = 0; cb < G; ++cb)
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
-    mfma_block<T, PB>([&](int r, int k) { return C[r + k * TS]; },
-                      [&](int k, int c) { return P[k + (cb * TS + c) * PB]; }, acc);
+      for (int bj = 0; bj < 2; ++bj) acc[cb][bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+#pragma unroll
+  for (int kc = 0; kc < G; ++kc) {
+    const int J = c0 + kc;
+    for (int e = threadIdx.x; e < TT; e += kBlock) {
+      const int r = e % TS, cc = e / TS;
+      T v = T(0);
+      if (kc < g)
+        v = (i > J) ? base[tile_index(i, J) * TT + r + cc * TS]
+                    : base[tile_index(J, i) * TT + cc + r * TS];
+      C[e] = v;
+      Cout[int64_t(kc) * TT + e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < G; ++cb)
+      mfma_block<T, TS>([&](int r, int k) { return C[r + k * TS]; },
+                        [&](int k, int c) { return P[(cb * TS + c) + (kc * TS + k) * PB]; },
+                        acc[cb]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < G; ++cb)
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -355,9 +563,113 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel(const T* tiles, const in
         for (int v = 0; v < 4; ++v) {
           int r, c;
           acc_pos<T>(bi, bj, v, &r, &c);
-          Bout[r + (cb * TS + c) * TS] = acc[bi][bj][v];
+          Bout[r + (cb * TS + c) * TS] = acc[cb][bi][bj][v];
         }
+}
+
+// (2') panel for two- and four-tile groups: B_i = C_i P with C_i (64 x PB) and the
+// rows of P (= its columns: P is symmetric) streamed through double-buffered LDS in
+// k-chunks; wave w owns output column block w (64 x 64, 16 MFMA accumulators).
+template <typename T>
+struct PanelCfg;
+template <>
+struct PanelCfg<double> { static constexpr int KC = 8; };
+template <>
+struct PanelCfg<float> { static constexpr int KC = 16; };
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const int64_t* tile_off,
+                                                         const int32_t* nt_arr, int c0,
+                                                         const T* pbuf, T* cbuf, T* bbuf,
+                                                         int64_t stride) {
+  constexpr int PB = G * TS, KC = PanelCfg<T>::KC, NCH = PB / KC;
+  constexpr int LDC = TS + 4, LDP = PB + 4;           // padded LDS rows
+  constexpr int NC = KC * TS / kBlock, NP = KC * PB / kBlock;   // loads per thread and chunk
+  const int m = blockIdx.y, i = blockIdx.x;
+  const int nt = nt_arr[m];
+  if (c0 >= nt || i >= nt) return;
+  const int g = min(G, nt - c0);
+  if (i >= c0 && i < c0 + g) return;
+  const T* base = tiles + tile_off[m];
+  T* Cout = cbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
+  T* Bout = bbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
+  const T* P = pbuf + int64_t(m) * PB * PB;
+  __shared__ T sC[2][KC * LDC], sP[2][KC * LDP];
+  T rc[NC], rp[NP];
+  auto gload = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int r = e % TS, kk = e / TS, k = ch * KC + kk;
+      const int J = c0 + k / TS, kl = k % TS;
+      T v = T(0);
+      if (k < g * TS)
+        v = (i > J) ? base[tile_index(i, J) * TT + r + kl * TS]
+                    : base[tile_index(J, i) * TT + kl + r * TS];
+      rc[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int c = e % PB, kk = e / PB;
+      rp[u] = P[c + int64_t(ch * KC + kk) * PB];
+    }
+  };
+  auto sstore = [&](int ch, int buf) {
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int r = e % TS, kk = e / TS;
+      sC[buf][kk * LDC + r] = rc[u];
+      Cout[r + int64_t(ch * KC + kk) * TS] = rc[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      sP[buf][(e / PB) * LDP + (e % PB)] = rp[u];
+    }
+  };
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::v4 acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+  const bool active = w < G;
+  const int ob = 64 * (active ? w : 0);
+  gload(0);
+  sstore(0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (ch + 1 < NCH) gload(ch + 1);
+    const T* C_ = sC[ch & 1];
+    const T* P_ = sP[ch & 1];
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        T a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = C_[(kk + lk) * LDC + 16 * q + li];
+          b[q] = P_[(kk + lk) * LDP + ob + 16 * q + li];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+      }
+    }
+    if (ch + 1 < NCH) sstore(ch + 1, (ch + 1) & 1);
+    __syncthreads();
   }
+  if (!active) return;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Bout[acc_row64<T>(bi, v) + int64_t(ob + 16 * bj + li) * TS] = acc[bi][bj][v];
 }
 
 // (3) update of every lower tile outside the pivot group
@@ -426,29 +738,34 @@ struct Upd2Cfg<double> { static constexpr int KC = 16, LD = 136; };
 template <>
 struct Upd2Cfg<float> { static constexpr int KC = 16, LD = 144; };
 
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int64_t* tile_off,
                                                           const int32_t* nt_arr, int c0,
                                                           const T* cbuf, const T* bbuf,
                                                           int64_t stride, int64_t per_xcd,
                                                           int part) {
-  constexpr int PB = 2 * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NCH = PB / KC;
+  constexpr int PB = G * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NCH = PB / KC;
+  constexpr int GS = G / 2;                    // super-rows per pivot group
   const int m = blockIdx.y;
   const int nt = nt_arr[m];
   if (c0 >= nt) return;
   const int nsb = (nt + 1) / 2;
-  const int gN = c0 / 2 + 1;                   // super index of the next pivot group
+  const int gN = c0 / 2 + GS;                  // first super index of the next pivot group
+  auto in_next = [&](int X) { return X >= gN && X < gN + GS; };
   int BI, BJ;
-  if (part == 1) {                             // only the next group's row and column
-    const int t = blockIdx.x;
-    if (t >= nsb || gN >= nsb) return;
-    BI = t <= gN ? gN : t;
-    BJ = t <= gN ? t : gN;
+  if (part == 1) {                             // only the next group's rows and columns
+    const int t = blockIdx.x / GS, sub = blockIdx.x % GS;
+    const int gx = gN + sub;
+    if (t >= nsb || gx >= nsb) return;
+    BI = t <= gx ? gx : t;
+    BJ = t <= gx ? t : gx;
+    if (t < gx && t >= gN) return;             // (gx, t), t an earlier super of the group:
+                                               // handled as (t', gx) by its own sub-row
   } else {
     const int64_t s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (s >= tri(nsb)) return;
     tile_ij(s, &BI, &BJ);
-    if (part == 2 && (BI == gN || BJ == gN)) return;
+    if (part == 2 && (in_next(BI) || in_next(BJ))) return;
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ti = 2 * BI + (w >> 1), tj = 2 * BJ + (w & 1);
@@ -457,11 +774,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
   const T* Cb = cbuf + int64_t(m) * stride;
   T* base = tiles + tile_off[m];
   const int gB = c0 / 2;
-  if (BI == gB || BJ == gB) {
-    if (BI == gB && BJ == gB) return;          // pivot tiles: written by the pivot kernel
+  auto in_cur = [&](int X) { return X >= gB && X < gB + GS; };
+  if (in_cur(BI) || in_cur(BJ)) {
+    const bool ii = ti >= c0 && ti < c0 + G, jj = tj >= c0 && tj < c0 + G;
+    if (ii && jj) return;                      // pivot tiles: written by the pivot kernel
     if (!valid) return;
     T* A = base + tile_index(ti, tj) * TT;
-    if (BI == gB) {                            // pivot-group row: A_ij <- (B_j[:, i block])^T
+    if (ii) {                                  // pivot-group row: A_ij <- (B_j[:, i block])^T
       const T* Bj = Bb + int64_t(tj) * TS * PB + int64_t(ti - c0) * TS * TS;
       for (int e = lane; e < TT; e += 64) A[e] = Bj[(e / TS) + (e % TS) * TS];
     } else {                                   // pivot-group column: A_ij <- B_i[:, j block]
@@ -960,17 +1279,23 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
   const int64_t stride = int64_t(b.max_nt) * TS * group * TS;
 #define RSD_STEP(T, G)                                                                          \
   do {                                                                                          \
-    if (stage == 0)                                                                             \
-      k_sweep_pivot<T, G><<<b.count, kPivotThreads, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,         \
-                                                     (T*)pbuf, flags);                          \
+    if (stage == 0 && G == 1)                                                                   \
+      k_sweep_pivot<T, G><<<b.count, kPivotThreads, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,   \
+                                                            (T*)pbuf, flags);                   \
+    else if (stage == 0)                                                                        \
+      k_sweep_pivot_blk<T, G><<<b.count, kBlock, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,     \
+                                                         (T*)pbuf, flags);                      \
+    else if (stage == 1 && G >= 2)                                                              \
+      k_sweep_panel2<T, (G >= 2 ? G : 2)><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(           \
+          (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
     else if (stage == 1)                                                                        \
       k_sweep_panel<T, G><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(                           \
           (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
-    else if (G == 2) {                                                                          \
+    else if (G >= 2) {                                                                          \
       const int64_t nsb = (b.max_nt + 1) / 2, ns = nsb * (nsb + 1) / 2;                         \
       const int64_t per_xcd = (ns + 7) / 8;                                                     \
-      const unsigned gx = part == 1 ? unsigned(nsb) : unsigned(8 * per_xcd);                   \
-      k_sweep_update2<T><<<dim3(gx, b.count), kBlock, 0, s>>>(                                  \
+      const unsigned gx = part == 1 ? unsigned(nsb * (G / 2)) : unsigned(8 * per_xcd);         \
+      k_sweep_update2<T, (G >= 2 ? G : 2)><<<dim3(gx, b.count), kBlock, 0, s>>>(                \
           (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride, per_xcd,   \
           part);                                                                                \
     } else                                                                                      \
@@ -978,9 +1303,9 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
           (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride);           \
   } while (0)
   if (b.fp32) {
-    if (group == 2) RSD_STEP(float, 2); else RSD_STEP(float, 1);
+    if (group == 4) RSD_STEP(float, 4); else if (group == 2) RSD_STEP(float, 2); else RSD_STEP(float, 1);
   } else {
-    if (group == 2) RSD_STEP(double, 2); else RSD_STEP(double, 1);
+    if (group == 4) RSD_STEP(double, 4); else if (group == 2) RSD_STEP(double, 2); else RSD_STEP(double, 1);
   }
 #undef RSD_STEP
   return hipGetLastError();

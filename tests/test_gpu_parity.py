@@ -60,7 +60,7 @@ def test_spmv_parity(problem_cache, ne, height, sigma, seed):
     h.close()
 
 
-@pytest.mark.parametrize("group", [1, 2])
+@pytest.mark.parametrize("group", [1, 2, 4])
 @pytest.mark.parametrize("ne,height,sigma,seed", CASES)
 def test_apply_parity_fp64(problem_cache, monkeypatch, ne, height, sigma, seed, group):
     monkeypatch.setenv("RSD_SWEEP_GROUP", str(group))
