@@ -19,6 +19,7 @@ value = solves per second of the mixed variant (1 / time-to-1e-10 including set-
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -71,6 +72,25 @@ def update_flops(sizes):
             r = n - w
             tot += float(w) * r * (r + 1)
     return tot
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of kernel `key` (FETCH_SIZE + WRITE_SIZE, each scaled by
+    what the counter reads for a plain copy of known size), as recorded by the
+    counter runs under profiles/; None unless the kernel source is unchanged since."""
+    rec_path = os.path.join(ROOT, "profiles", "traffic_diffusion64_mixed.json")
+    src_path = os.path.join(ROOT, "paper_1210_6266_amd", "csrc", "kernels.hip")
+    try:
+        with open(rec_path) as f:
+            rec = json.load(f)
+        with open(src_path, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    k = rec.get("kernels", {}).get(key)
+    if rec.get("source_sha256") != sha or k is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def main():
@@ -183,22 +203,26 @@ def main():
         dur = ms["leaf_update"] / nlch["leaf_update"] * 1e-3
         peak = PEAK["fp32_TFLOPs"] if fp32_leaf else PEAK["fp64_TFLOPs"]
         roof = dict(kernel="k_sweep_update2 (sub-domain batch)", bound="mfma",
-                    achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s")
+                    achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s",
+                    profile_key="k_sweep_update2<%s, %d>" % ("float" if fp32_leaf else "double",
+                                                             group_tiles(ana["max_leaf_dofs"])))
     elif dom == "root_update":
         flops = update_flops([ana["max_iface_dofs"]])
         per_launch = flops / nlch["root_update"]
         dur = ms["root_update"] / nlch["root_update"] * 1e-3
         roof = dict(kernel="k_sweep_update2<double> (root interface)", bound="mfma",
-                    achieved=per_launch / dur / 1e12, peak=PEAK["fp64_TFLOPs"], unit="TFLOP/s")
+                    achieved=per_launch / dur / 1e12, peak=PEAK["fp64_TFLOPs"], unit="TFLOP/s",
+                    profile_key="k_sweep_update2<double, %d>" % group_tiles(ana["max_iface_dofs"]))
     else:
         es = 4 if fp32_leaf else 8
         per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
         dur = ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3
         roof = dict(kernel="k_symv1+k_symv2 (sub-domain batch)", bound="hbm",
-                    achieved=per_launch / dur / 1e9, peak=PEAK["hbm_GBps"], unit="GB/s")
+                    achieved=per_launch / dur / 1e9, peak=PEAK["hbm_GBps"], unit="GB/s",
+                    profile_key="k_symv1<%s>" % ("float" if fp32_leaf else "double"))
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["avg_launch_ms"] = dur * 1e3
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(roof.pop("profile_key"))
     # secondary figures (not the roofline object): leaf apply bandwidth, root update rate
     extra = {}
     if R0["launches"].get("leaf_apply"):
