@@ -148,15 +148,11 @@ void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool
   up.add(&d->nt, b.nt);
   up.add(&d->tile_off, b.tile_off);
   up.add(&d->vec_off, b.vec_off);
-  d->num_items = int32_t(b.item_mat.size());
+  d->num_items = int32_t(b.num_items);
   up.add(&d->item_mat, b.item_mat);
-  up.add(&d->item_J, b.item_J);
-  up.add(&d->item_I0, b.item_I0);
-  up.add(&d->item_I1, b.item_I1);
-  up.add(&d->item_cslot, b.item_cslot);
-  up.add(&d->rslot_off, b.rslot_off);
-  up.add(&d->cstrip_ptr, b.cstrip_ptr);
-  up.add(&d->cstrip_base, b.cstrip_base);
+  up.add(&d->item_BI, b.item_BI);
+  up.add(&d->item_BJ, b.item_BJ);
+  up.add(&d->item_base, b.item_base);
   d->fp32 = fp32 ? 1 : 0;
   if (b.total_elems > 0) {
     if (fp32)
@@ -349,21 +345,19 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     const int NL = int(P.level_depth.size());
     h->lev.assign(NL, DevBatch());
     h->lev_items.assign(NL, SigmaLevelItems());
-    int64_t max_c = P.leaf_batch.num_cslots, max_r = P.leaf_batch.num_rslots;
+
     std::vector<std::vector<int32_t>> il(NL), ir0(NL), ia0(NL), ia1(NL);
     for (int q = 0; q < NL; ++q) {
       const bool root = P.level_depth[q] == 0;
       const int prec = root ? h->opt.root_prec : h->opt.iface_prec;
       upload_batch(h, up, &h->lev[q], P.level_batch[q], prec == RSD_PREC_FP32);
-      max_c = std::max(max_c, P.level_batch[q].num_cslots);
-      max_r = std::max(max_r, P.level_batch[q].num_rslots);
-      // Sigma products of this level, split into row chunks of 256
+      // Sigma products of this level, split into row chunks of kSigRows
       for (const auto& it : P.level_sigma[q])
-        for (int32_t a0 = it.r0; a0 < it.r1; a0 += 256) {
+        for (int32_t a0 = it.r0; a0 < it.r1; a0 += kSigRows) {
           il[q].push_back(it.leaf);
           ir0[q].push_back(it.r0);
           ia0[q].push_back(a0);
-          ia1[q].push_back(std::min(it.r1, a0 + 256));
+          ia1[q].push_back(std::min(it.r1, a0 + kSigRows));
         }
       SigmaLevelItems& li = h->lev_items[q];
       li.count = int32_t(il[q].size());
@@ -400,8 +394,9 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->t = dalloc<double>(h, size_t(n));
     h->rin = dalloc<double>(h, size_t(n));
     h->zin = dalloc<double>(h, size_t(n));
-    h->cpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_c)) * kTile);
-    h->rpart = dalloc<double>(h, size_t(std::max<int64_t>(1, max_r)) * kTile);
+    size_t part_bytes = std::max<size_t>(8, symv_part_bytes(h->leaf));
+    for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
+    h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     h->setup_wall[1] = ms_since(w1);
     return RSD_OK;
@@ -522,7 +517,7 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
   const int64_t n = P.n, nl = P.n_leaf;
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, r, h->cpart, h->rpart, -1.0, nullptr, z, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf, r, h->sympart, -1.0, nullptr, z, s), "leaf symv");
   }
   {
     Timer tm(h, RSD_T_COUPLING, s);
@@ -543,7 +538,7 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
     }
     {
       Timer tm(h, RSD_T_IFACE_APPLY, s);
-      hip_check(h, launch_symv(h->lev[q], z, h->cpart, h->rpart, -1.0, nullptr, z, s),
+      hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, s),
                 "interface symv");
     }
   }
@@ -555,7 +550,7 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, h->t, h->cpart, h->rpart, -1.0, nullptr, z, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf, h->t, h->sympart, -1.0, nullptr, z, s), "leaf symv");
   }
 }
 

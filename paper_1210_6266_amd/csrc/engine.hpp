@@ -46,7 +46,7 @@ struct rsd_ctx {
 
   // apply work vectors (internal order)
   double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;
-  double *cpart = nullptr, *rpart = nullptr;
+  double* sympart = nullptr;                // partial sums of the symmetric products
 
   // Krylov work space (grown on demand)
   int kry_m = 0;

@@ -15,16 +15,44 @@ constexpr int TS = 64;            // tile side
 constexpr int TT = TS * TS;       // tile elements
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int64_t tri(int64_t I) { return I * (I + 1) / 2; }
+// partial sums of the symmetric products: FP32 for FP32 factors, FP64 otherwise
+template <typename T>
+struct SymPart { using type = double; };
+template <>
+struct SymPart<float> { using type = float; };
+
+__host__ __device__ __forceinline__ int64_t tri(int64_t I) { return I * (I + 1) / 2; }
 __device__ __forceinline__ int64_t tile_index(int I, int J) { return tri(I) + J; }
 
 // (I, J) of the t-th lower tile in row-major tile order
-__device__ __forceinline__ void tile_ij(int64_t t, int* I, int* J) {
+__host__ __device__ __forceinline__ void tile_ij(int64_t t, int* I, int* J) {
   int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
   while (tri(i) > t) --i;
   while (tri(i + 1) <= t) ++i;
   *I = i;
   *J = int(t - tri(i));
+}
+
+// (I, J) of the s-th lower tile of an n x n tile triangle in band order: bands of
+// kBand tile rows, each band walked kBand x kBand block by block (left to right,
+// the diagonal triangle last).  The lower tiles of any kBand x kBand block are
+// consecutive, so workgroups that run at the same time share kBand row panels and
+// kBand column panels instead of one row panel and many column panels.
+constexpr int kBand = 8;
+__host__ __device__ __forceinline__ void band_ij(int64_t s, int n, int* I, int* J) {
+  int i, j;
+  tile_ij(s, &i, &j);                          // row in plain order picks the band
+  const int r0 = (i / kBand) * kBand, h = min(kBand, n - r0);
+  const int64_t t = s - tri(r0), full = int64_t(r0) * h;
+  if (t < full) {
+    const int64_t cb = t / (int64_t(kBand) * h), u = t % (int64_t(kBand) * h);
+    *I = r0 + int(u % h);
+    *J = int(cb) * kBand + int(u / h);
+  } else {
+    tile_ij(t - full, &i, &j);
+    *I = r0 + i;
+    *J = r0 + j;
+  }
 }
 
 // element (r, c) of the symmetric matrix whose lower tiles start at base
@@ -583,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
                                                          const T* pbuf, T* cbuf, T* bbuf,
                                                          int64_t stride) {
   constexpr int PB = G * TS, KC = PanelCfg<T>::KC, NCH = PB / KC;
-  constexpr int LDC = TS + 4, LDP = PB + 4;           // padded LDS rows
+  constexpr int LDC = TS + 16, LDP = PB + 16;         // padded LDS rows (bank-spread)
   constexpr int NC = KC * TS / kBlock, NP = KC * PB / kBlock;   // loads per thread and chunk
   const int m = blockIdx.y, i = blockIdx.x;
   const int nt = nt_arr[m];
@@ -734,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update(T* tiles, const int64_t
 template <typename T>
 struct Upd2Cfg;
 template <>
-struct Upd2Cfg<double> { static constexpr int KC = 16, LD = 136; };
+struct Upd2Cfg<double> { static constexpr int KC = 16, LD = 144; };
 template <>
 struct Upd2Cfg<float> { static constexpr int KC = 16, LD = 144; };
 
@@ -743,10 +771,24 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
                                                           const int32_t* nt_arr, int c0,
                                                           const T* cbuf, const T* bbuf,
                                                           int64_t stride, int64_t per_xcd,
-                                                          int part) {
+                                                          int part, int count) {
   constexpr int PB = G * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NCH = PB / KC;
   constexpr int GS = G / 2;                    // super-rows per pivot group
-  const int m = blockIdx.y;
+  // Workgroups are dealt to the 8 XCDs round-robin by linear id.  With 8 or more
+  // matrices (part 0 or 2, 1-D grid) each XCD takes whole matrices, one after the
+  // other: matrix 8 q + x on XCD x, its super-tiles at slots s < per_xcd.  Otherwise
+  // (grid y = matrix) XCD x takes the contiguous slot range [x, x + 1) * per_xcd.
+  int m;
+  int64_t s = 0;
+  if (part != 1 && count >= 8) {
+    const int64_t q = blockIdx.x / 8;
+    m = int(8 * (q / per_xcd)) + int(blockIdx.x % 8);
+    s = q % per_xcd;
+    if (m >= count) return;
+  } else {
+    m = blockIdx.y;
+    s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  }
   const int nt = nt_arr[m];
   if (c0 >= nt) return;
   const int nsb = (nt + 1) / 2;
@@ -762,9 +804,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
     if (t < gx && t >= gN) return;             // (gx, t), t an earlier super of the group:
                                                // handled as (t', gx) by its own sub-row
   } else {
-    const int64_t s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (s >= tri(nsb)) return;
-    tile_ij(s, &BI, &BJ);
+    band_ij(s, nsb, &BI, &BJ);
     if (part == 2 && (in_next(BI) || in_next(BJ))) return;
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -862,83 +903,143 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 }
 
 // ---- symmetric products y = base + alpha A x -------------------------------------------
-// phase 1: one work item = tiles (I, J), I in [I0, I1), of strip J.  Column parts
-// (A_IJ^T x_I, and A_JJ x_J on the diagonal tile) accumulate per item; row parts
-// A_IJ x_J (I > J) go to their own slot.  No atomics: phase 2 sums slots in order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_symv1(
-    const T* __restrict__ tiles, const int64_t* __restrict__ tile_off,
-    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off,
-    const int32_t* __restrict__ item_mat, const int32_t* __restrict__ item_J,
-    const int32_t* __restrict__ item_I0, const int32_t* __restrict__ item_I1,
-    const int64_t* __restrict__ item_cslot, const int64_t* __restrict__ rslot_off,
-    const double* __restrict__ x, double* __restrict__ cpart, double* __restrict__ rpart) {
-  const int it = blockIdx.x;
-  const int m = item_mat[it], J = item_J[it], I0 = item_I0[it], I1 = item_I1[it];
-  const int n = n_arr[m];
-  const int64_t xo = vec_off[m];
-  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
-  double xj[16], acc[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = J * TS + cg * 16 + c;
-    xj[c] = col < n ? x[xo + col] : 0.0;
-    acc[c] = 0.0;
-  }
-  __shared__ double rp[2][4][TS];
-  __shared__ double red[TS][TS + 1];
-  const T* base = tiles + tile_off[m];
-  for (int I = I0; I < I1; ++I) {
-    const int row = I * TS + r;
-    const double xi = row < n ? x[xo + row] : 0.0;
-    const T* tl = base + tile_index(I, J) * TT + r + cg * 16 * TS;
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const double a = double(tl[c * TS]);
-      acc[c] += a * xi;
-      s += a * xj[c];
-    }
-    if (I > J) {
-      rp[I & 1][cg][r] = s;
-      __syncthreads();
-      if (threadIdx.x < TS) {
-        const double v = rp[I & 1][0][r] + rp[I & 1][1][r] + rp[I & 1][2][r] + rp[I & 1][3][r];
-        rpart[(rslot_off[m] + tri(I - 1) + J) * TS + r] = v;
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 16; ++c) red[cg * 16 + c][r] = acc[c];
-  __syncthreads();
-  if (threadIdx.x < TS) {
-    double s = 0.0;
-    for (int k = 0; k < TS; ++k) s += red[threadIdx.x][k];
-    cpart[item_cslot[it] * TS + threadIdx.x] = s;
+// Work item = a kSymB x kSymB block of tiles (block row BI, block column BJ <= BI) of
+// one matrix.  Phase 1 streams the block's lower tiles once and keeps, per tile row I
+// of the block, the row part sum_J A_IJ x_J (the full diagonal tile included) and, per
+// tile column J, the column part sum_{I > J} A_IJ^T x_J in registers; they are reduced
+// and written once per item (P = float for FP32 factors, as accurate as the factor).
+// Phase 2 adds, for every tile row, the row parts of its block row and the column parts
+// of its block column, in a fixed order.  No atomics: results are reproducible.
+template <typename P>
+__device__ __forceinline__ void xor_fold(P* a, int n, int lane, int o) {
+  // trade half of a[0..n) with the lane `lane ^ o`; the lane with bit o set keeps the
+  // upper half, so after folds over bits b1 > b2 > ... a lane holds the block of
+  // entries selected by its own bits
+  const bool up = (lane & o) != 0;
+  for (int j = 0; j < n / 2; ++j) {
+    const P give = up ? a[j] : a[j + n / 2];
+    const P keep = up ? a[j + n / 2] : a[j];
+    a[j] = keep + __shfl_xor(give, o, 64);
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_symv1(
+    const T* __restrict__ tiles, const int64_t* __restrict__ tile_off,
+    const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
+    const int64_t* __restrict__ vec_off, const int32_t* __restrict__ item_mat,
+    const int32_t* __restrict__ item_BI, const int32_t* __restrict__ item_BJ,
+    const double* __restrict__ x, typename SymPart<T>::type* __restrict__ part) {
+  using P = typename SymPart<T>::type;
+  constexpr int B = kSymB;
+  constexpr int VEC = 16 / int(sizeof(T));     // elements per 16-byte load
+  constexpr int LPC = 4 / VEC;                 // loads per column (four rows per thread)
+  typedef T V __attribute__((ext_vector_type(VEC)));
+  const int it = blockIdx.x;
+  const int m = item_mat[it], BI = item_BI[it], BJ = item_BJ[it];
+  const int n = n_arr[m], nt = nt_arr[m];
+  const int64_t xo = vec_off[m];
+  // thread t: rows q4(v) of the tile (q = t % 16), columns g + 16 u (g = t / 16, u < 4);
+  // FP32: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1, 32 + 2q,
+  // 33 + 2q (two loads per column, each contiguous over 16 lanes)
+  const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
+  auto q4 = [&](int v) { return sizeof(T) == 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
+  __shared__ double xs[2][B][TS];
+  __shared__ P red[4][B][TS];
+  for (int e = t; e < 2 * B * TS; e += kBlock) {
+    const int sd = e / (B * TS), b = (e / TS) % B, r = e % TS;
+    const int idx = ((sd == 0 ? BI : BJ) * B + b) * TS + r;
+    xs[sd][b][r] = idx < n ? x[xo + idx] : 0.0;
+  }
+  __syncthreads();
+  P racc[B * 4], cacc[B * 4];                  // [block row b][row v], [block column b][column u]
+#pragma unroll
+  for (int i = 0; i < B * 4; ++i) {
+    racc[i] = P(0);
+    cacc[i] = P(0);
+  }
+  const T* base = tiles + tile_off[m] + q4(0) + g * TS;
+#pragma unroll
+  for (int bi = 0; bi < B; ++bi) {
+    const int I = BI * B + bi;
+    if (I >= nt) break;
+    P xi[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xi[v] = P(xs[0][bi][q4(v)]);
+#pragma unroll
+    for (int bj = 0; bj < B; ++bj) {
+      const int J = BJ * B + bj;
+      if (J > I) break;
+      const T* tl = base + tile_index(I, J) * TT;
+      V a[4][LPC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < LPC; ++h) a[u][h] = *(const V*)(tl + 16 * u * TS + 32 * h);
+      P rf[4] = {P(0), P(0), P(0), P(0)};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const P xk = P(xs[1][bj][g + 16 * u]);
+        P cf = P(0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const P av = P(a[u][v / VEC][v % VEC]);
+          cf = fma(av, xi[v], cf);
+          rf[v] = fma(av, xk, rf[v]);
+        }
+        if (J < I) cacc[bj * 4 + u] += cf;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) racc[bi * 4 + v] += rf[v];
+    }
+  }
+  // rows: fold over the wave's four column groups (lane bits 5, 4); lane (q, g) then
+  // holds block row g % 4, rows q4(0..3); the four waves are summed in LDS
+  xor_fold(racc, B * 4, lane, 32);
+  xor_fold(racc, B * 2, lane, 16);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[w][g & 3][q4(v)] = racc[v];
+  // columns: fold over the 16 row lanes (bits 3..0); lane q holds block column q / 4,
+  // column g + 16 (q % 4), summed over the block's rows -- written directly
+  xor_fold(cacc, B * 4, lane, 8);
+  xor_fold(cacc, B * 2, lane, 4);
+  xor_fold(cacc, B, lane, 2);
+  xor_fold(cacc, B / 2, lane, 1);
+  P* rowp = part + int64_t(2 * it) * B * TS;
+  P* colp = rowp + B * TS;
+  colp[(q >> 2) * TS + g + 16 * (q & 3)] = cacc[0];
+  __syncthreads();
+  for (int e = t; e < B * TS; e += kBlock) {
+    const int b = e / TS, r = e % TS;
+    rowp[e] = (red[0][b][r] + red[1][b][r]) + (red[2][b][r] + red[3][b][r]);
+  }
+}
+
+template <typename P>
 __global__ __launch_bounds__(kBlock) void k_symv2(
     const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
-    const int64_t* __restrict__ vec_off, const int64_t* __restrict__ cstrip_base,
-    const int64_t* __restrict__ cstrip_ptr, const int64_t* __restrict__ rslot_off,
-    const double* __restrict__ cpart, const double* __restrict__ rpart, double alpha,
-    const double* __restrict__ base, double* __restrict__ y) {
-  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x & 63, part = threadIdx.x >> 6;
-  if (I >= nt_arr[m]) return;
-  const int row = I * TS + r;
+    const int64_t* __restrict__ vec_off, const int64_t* __restrict__ item_base,
+    const P* __restrict__ part, double alpha, const double* __restrict__ base,
+    double* __restrict__ y) {
+  constexpr int B = kSymB;
+  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x & 63, prt = threadIdx.x >> 6;
+  const int nt = nt_arr[m];
+  if (I >= nt) return;
+  const int nb = (nt + B - 1) / B, BI = I / B, b = I % B;
+  const int64_t ib = item_base[m];
   double s = 0.0;
-  const int64_t sb = cstrip_base[m] + I;
-  for (int64_t c = cstrip_ptr[sb] + part; c < cstrip_ptr[sb + 1]; c += 4) s += cpart[c * TS + r];
-  const int64_t rb = rslot_off[m] + tri(I - 1);
-  for (int Jc = part; Jc < I; Jc += 4) s += rpart[(rb + Jc) * TS + r];
+  for (int BJ = prt; BJ <= BI; BJ += 4)        // row parts of block row BI
+    s += double(part[(2 * (ib + tri(BI) + BJ) * B + b) * TS + r]);
+  for (int B2 = BI + prt; B2 < nb; B2 += 4)    // column parts of block column BI
+    s += double(part[((2 * (ib + tri(B2) + BI) + 1) * B + b) * TS + r]);
   __shared__ double red[4][TS];
-  red[part][r] = s;
+  red[prt][r] = s;
   __syncthreads();
-  if (part == 0 && row < n_arr[m]) {
+  const int row = I * TS + r;
+  if (prt == 0 && row < n_arr[m]) {
     const int64_t o = vec_off[m] + row;
-    const double t = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
-    y[o] = (base ? base[o] : 0.0) + alpha * t;
+    const double v = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    y[o] = (base ? base[o] : 0.0) + alpha * v;
   }
 }
 
@@ -1059,31 +1160,52 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
     const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
     const double* __restrict__ z, double* __restrict__ e) {
-  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= 256)
+  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= kSigRows).
+  // Sigma_l is symmetric: row a is read as column a (contiguous in b), one wave per
+  // row, the gathered u staged in LDS; each row's sum is taken in a fixed order.
   const int it = blockIdx.x;
   const int l = it_leaf[it], r0 = it_r0[it], a0 = it_a0[it], a1 = it_a1[it];
   const int64_t m = B_off[l + 1] - B_off[l];
   const S* Sg = sigma + sig_off[l];
   const int32_t* Bl = B + B_off[l];
-  __shared__ double ub[kBlock];
-  const int a = a0 + threadIdx.x;
-  double s0 = 0.0, s1 = 0.0;
-  for (int b0 = 0; b0 < r0; b0 += kBlock) {
+  constexpr int kSigStage = 2048;              // u values staged per pass (16 KB)
+  __shared__ double ub[kSigStage];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int RW = kSigRows / 4;             // rows per wave
+  double acc[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) acc[q] = 0.0;
+  for (int b0 = 0; b0 < r0; b0 += kSigStage) {
+    const int nb = min(kSigStage, r0 - b0);
     __syncthreads();
-    if (b0 + int(threadIdx.x) < r0) ub[threadIdx.x] = z[Bl[b0 + threadIdx.x]];
+    for (int b = threadIdx.x; b < nb; b += kBlock) ub[b] = z[Bl[b0 + b]];
     __syncthreads();
-    const int nb = min(kBlock, r0 - b0);
-    if (a < a1) {
-      const S* col = Sg + a + int64_t(b0) * m;
-      int b = 0;
-      for (; b + 1 < nb; b += 2) {
-        s0 += double(col[int64_t(b) * m]) * ub[b];
-        s1 += double(col[int64_t(b + 1) * m]) * ub[b + 1];
-      }
-      if (b < nb) s0 += double(col[int64_t(b) * m]) * ub[b];
+    const S* col[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int a = min(a0 + w * RW + q, a1 - 1);   // rows past a1 repeat a valid row
+      col[q] = Sg + int64_t(a) * m + b0;
+    }
+    int b = lane;
+    for (; b + 64 < nb; b += 128) {
+      const double u0 = ub[b], u1 = ub[b + 64];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) acc[q] += double(col[q][b]) * u0 + double(col[q][b + 64]) * u1;
+    }
+    if (b < nb) {
+      const double u0 = ub[b];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) acc[q] += double(col[q][b]) * u0;
     }
   }
-  if (a < a1) e[B_off[l] + a] = s0 + s1;
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int a = a0 + w * RW + q;
+    if (lane == 0 && a < a1) e[B_off[l] + a] = v;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_level_rhs(
@@ -1293,11 +1415,14 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
           (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
     else if (G >= 2) {                                                                          \
       const int64_t nsb = (b.max_nt + 1) / 2, ns = nsb * (nsb + 1) / 2;                         \
-      const int64_t per_xcd = (ns + 7) / 8;                                                     \
-      const unsigned gx = part == 1 ? unsigned(nsb * (G / 2)) : unsigned(8 * per_xcd);         \
-      k_sweep_update2<T, (G >= 2 ? G : 2)><<<dim3(gx, b.count), kBlock, 0, s>>>(                \
+      const bool major = part != 1 && b.count >= 8;                                             \
+      const int64_t per_xcd = major ? ns : (ns + 7) / 8;                                        \
+      const dim3 grid = part == 1 ? dim3(unsigned(nsb * (G / 2)), b.count)                      \
+                        : major   ? dim3(unsigned(8 * ((b.count + 7) / 8) * ns), 1)             \
+                                  : dim3(unsigned(8 * per_xcd), b.count);                       \
+      k_sweep_update2<T, (G >= 2 ? G : 2)><<<grid, kBlock, 0, s>>>(                             \
           (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride, per_xcd,   \
-          part);                                                                                \
+          part, b.count);                                                                       \
     } else                                                                                      \
       k_sweep_update<T, G><<<dim3(unsigned(b.max_tiles), b.count), kBlock, 0, s>>>(             \
           (T*)b.tiles, b.tile_off, b.nt, c0, (const T*)cbuf, (const T*)bbuf, stride);           \
@@ -1311,20 +1436,22 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
   return hipGetLastError();
 }
 
-hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
-                       double alpha, const double* base, double* y, hipStream_t s) {
+hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
+                       const double* base, double* y, hipStream_t s) {
   if (b.count == 0 || b.num_items == 0) return hipSuccess;
-  if (b.fp32)
-    k_symv1<float><<<b.num_items, kBlock, 0, s>>>(
-        (const float*)b.tiles, b.tile_off, b.n, b.vec_off, b.item_mat, b.item_J, b.item_I0,
-        b.item_I1, b.item_cslot, b.rslot_off, x, cpart, rpart);
-  else
-    k_symv1<double><<<b.num_items, kBlock, 0, s>>>(
-        (const double*)b.tiles, b.tile_off, b.n, b.vec_off, b.item_mat, b.item_J, b.item_I0,
-        b.item_I1, b.item_cslot, b.rslot_off, x, cpart, rpart);
-  k_symv2<<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(b.n, b.nt, b.vec_off, b.cstrip_base,
-                                                  b.cstrip_ptr, b.rslot_off, cpart, rpart,
-                                                  alpha, base, y);
+  if (b.fp32) {
+    k_symv1<float><<<b.num_items, kBlock, 0, s>>>((const float*)b.tiles, b.tile_off, b.n, b.nt,
+                                                  b.vec_off, b.item_mat, b.item_BI, b.item_BJ, x,
+                                                  (float*)part);
+    k_symv2<float><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
+        b.n, b.nt, b.vec_off, b.item_base, (const float*)part, alpha, base, y);
+  } else {
+    k_symv1<double><<<b.num_items, kBlock, 0, s>>>((const double*)b.tiles, b.tile_off, b.n, b.nt,
+                                                   b.vec_off, b.item_mat, b.item_BI, b.item_BJ,
+                                                   x, (double*)part);
+    k_symv2<double><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
+        b.n, b.nt, b.vec_off, b.item_base, (const double*)part, alpha, base, y);
+  }
   return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@
 
 #include <cstdint>
 
+#include "plan.hpp"
+
 namespace rsd {
 
 // Device view of a SymBatch (arrays live on the device).
@@ -23,13 +25,9 @@ struct DevBatch {
   const int64_t* vec_off = nullptr;
   int32_t num_items = 0;
   const int32_t* item_mat = nullptr;
-  const int32_t* item_J = nullptr;
-  const int32_t* item_I0 = nullptr;
-  const int32_t* item_I1 = nullptr;
-  const int64_t* item_cslot = nullptr;
-  const int64_t* rslot_off = nullptr;
-  const int64_t* cstrip_ptr = nullptr;
-  const int64_t* cstrip_base = nullptr;
+  const int32_t* item_BI = nullptr;
+  const int32_t* item_BJ = nullptr;
+  const int64_t* item_base = nullptr;
   void* tiles = nullptr;  // double* or float*
   int32_t fp32 = 0;
 };
@@ -73,8 +71,12 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
                              void* bbuf, int32_t* flags, int group, hipStream_t s, int part = 0);
 size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, size_t* cbytes);
 // y = base + alpha * A x for every matrix of the batch (x, y internal vectors)
-hipError_t launch_symv(const DevBatch& b, const double* x, double* cpart, double* rpart,
-                       double alpha, const double* base, double* y, hipStream_t s);
+// (part: symv_part_bytes(b) of scratch for the per-item partial sums)
+hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
+                       const double* base, double* y, hipStream_t s);
+inline size_t symv_part_bytes(const DevBatch& b) {
+  return size_t(b.num_items) * 2 * kSymB * kTile * (b.fp32 ? sizeof(float) : sizeof(double));
+}
 
 // ---- Schur complements --------------------------------------------------------------------
 struct SigmaArgs {
@@ -105,6 +107,9 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
                                  hipStream_t s);
 
 // ---- apply helpers -------------------------------------------------------------------------
+// rows of Sigma_l per work item of the level product (4 waves, kSigRows / 4 rows each)
+constexpr int kSigRows = 16;
+
 struct SigmaLevelItems {
   int32_t count = 0;
   const int32_t* leaf = nullptr;

@@ -73,19 +73,15 @@ PlanError check_rows(int64_t n, const std::function<bool(int64_t, PlanError*, st
 
 }  // namespace
 
-void layout_sym_batch(SymBatch* b, int chunk) {
+void layout_sym_batch(SymBatch* b) {
   const int64_t TT = int64_t(kTile) * kTile;
   b->nt.assign(b->count, 0);
   b->tile_off.assign(b->count, 0);
-  b->rslot_off.assign(b->count, 0);
-  b->cstrip_base.assign(b->count, 0);
+  b->item_base.assign(b->count, 0);
   b->item_mat.clear();
-  b->item_J.clear();
-  b->item_I0.clear();
-  b->item_I1.clear();
-  b->item_cslot.clear();
-  b->cstrip_ptr.clear();
-  int64_t off = 0, rs = 0, cs = 0, strips = 0;
+  b->item_BI.clear();
+  b->item_BJ.clear();
+  int64_t off = 0, items = 0;
   b->max_nt = 0;
   b->max_tiles = 0;
   for (int m = 0; m < b->count; ++m) {
@@ -93,27 +89,20 @@ void layout_sym_batch(SymBatch* b, int chunk) {
     b->nt[m] = nt;
     b->tile_off[m] = off;
     off += tiles_of(nt) * TT;
-    b->rslot_off[m] = rs;
-    rs += int64_t(nt) * (nt - 1) / 2;
-    b->cstrip_base[m] = strips;
     b->max_nt = std::max(b->max_nt, nt);
     b->max_tiles = std::max<int64_t>(b->max_tiles, tiles_of(nt));
-    for (int J = 0; J < nt; ++J) {
-      b->cstrip_ptr.push_back(cs);
-      for (int I0 = J; I0 < nt; I0 += chunk) {
+    b->item_base[m] = items;
+    const int nb = (nt + kSymB - 1) / kSymB;
+    for (int BI = 0; BI < nb; ++BI)
+      for (int BJ = 0; BJ <= BI; ++BJ) {
         b->item_mat.push_back(m);
-        b->item_J.push_back(J);
-        b->item_I0.push_back(I0);
-        b->item_I1.push_back(std::min(nt, I0 + chunk));
-        b->item_cslot.push_back(cs++);
+        b->item_BI.push_back(BI);
+        b->item_BJ.push_back(BJ);
+        ++items;
       }
-    }
-    strips += nt;
   }
-  b->cstrip_ptr.push_back(cs);
   b->total_elems = off;
-  b->num_cslots = cs;
-  b->num_rslots = rs;
+  b->num_items = items;
 }
 
 PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
@@ -496,7 +485,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     P->leaf_flops += double(P->leaf_n[l]) * P->leaf_n[l] * P->leaf_n[l];
     P->max_leaf = std::max<int32_t>(P->max_leaf, int32_t(P->leaf_n[l]));
   }
-  layout_sym_batch(&P->leaf_batch, 8);
+  layout_sym_batch(&P->leaf_batch);
   P->level_batch.assign(NL, SymBatch());
   P->sum_iface_sq = 0;
   P->iface_flops = 0;
@@ -511,7 +500,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       P->iface_flops += double(P->iface_n[s]) * P->iface_n[s] * P->iface_n[s];
       P->max_iface = std::max<int32_t>(P->max_iface, int32_t(P->iface_n[s]));
     }
-    layout_sym_batch(&b, 8);
+    layout_sym_batch(&b);
   }
   return PlanError::kOk;
 }

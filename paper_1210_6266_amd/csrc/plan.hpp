@@ -24,6 +24,7 @@
 namespace rsd {
 
 constexpr int kTile = 64;  // dense blocks are stored as kTile x kTile tiles
+constexpr int kSymB = 4;   // symmetric products work on kSymB x kSymB blocks of tiles
 
 // A batch of symmetric matrices stored as packed lower tiles (tile (I, J) with
 // I >= J; column-major kTile x kTile each; diagonal tiles hold both triangles).
@@ -36,13 +37,11 @@ struct SymBatch {
   int64_t total_elems = 0;
   int32_t max_nt = 0;
   int64_t max_tiles = 0;           // max over matrices of nt (nt + 1) / 2
-  // symmetric product work: item = (matrix, strip J, first tile row, end tile row)
-  std::vector<int32_t> item_mat, item_J, item_I0, item_I1;
-  std::vector<int64_t> item_cslot;   // column-part slot of the item
-  std::vector<int64_t> rslot_off;    // per matrix: base of its row-part slots
-  std::vector<int64_t> cstrip_ptr;   // per (matrix, strip): range of column-part slots
-  std::vector<int64_t> cstrip_base;  // per matrix: index of its first strip in cstrip_ptr
-  int64_t num_cslots = 0, num_rslots = 0;
+  // symmetric product work: item = (matrix, block row BI, block column BJ <= BI) over
+  // kSymB x kSymB tiles; the items of matrix m are item_base[m] + tri(BI) + BJ
+  std::vector<int32_t> item_mat, item_BI, item_BJ;
+  std::vector<int64_t> item_base;
+  int64_t num_items = 0;
 };
 
 struct LevelSigmaItem {            // Sigma_l[rows r0..r1, cols 0..r0] of one leaf
@@ -121,7 +120,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
                      int32_t num_nodes, const int32_t* parent, const int32_t* dof_node,
                      Plan* plan, std::string* msg);
 
-// Work layout of symmetric products over a batch (chunk = max tiles per item).
-void layout_sym_batch(SymBatch* b, int chunk);
+// Tile layout and symmetric-product work items of a batch.
+void layout_sym_batch(SymBatch* b);
 
 }  // namespace rsd
