@@ -852,20 +852,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
       sB[buf][(e / 128) * LD + (e % 128)] = rb[u];
     }
   };
-  // the accumulators start from A_ij (the MFMA's C operand), with the A operand
-  // negated: D = A_ij - B_i C_j^T; the old tile is read while the panels stream in
+  // the accumulators start from A_ij (the MFMA's C operand), with the panel of B_i
+  // negated: D = A_ij - B_i C_j^T.  The MFMA computes the transposed product (the C_j
+  // operand first), so a lane's accumulator holds 16 consecutive rows of a column:
+  // the old tile is read, and the new one written, in whole cache lines.
   const int li = lane & 15, lk = lane >> 4, g = lane >> 4;
   T* At = base + tile_index(valid ? ti : 0, valid ? tj : 0) * TT;
+  auto acc_col = [&](int bj, int v) { return 16 * bj + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v); };
   typename Mfma<T>::v4 acc[4][4];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
-        acc[bi][bj][v] = valid ? At[r + (16 * bj + li) * TS] : T(0);
-      }
+      for (int v = 0; v < 4; ++v)
+        acc[bi][bj][v] = valid ? At[(16 * bi + li) + acc_col(bj, v) * TS] : T(0);
   const int oa = 64 * (w >> 1) + li, ob = 64 * (w & 1) + li;
   gload(0);
   sstore(0);
@@ -885,7 +886,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(b[bj], a[bi], acc[bi][bj]);
     }
     if (ch + 1 < NCH) sstore((ch + 1) & 1);
     __syncthreads();
@@ -896,10 +897,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
-        At[r + (16 * bj + li) * TS] = acc[bi][bj][v];
-      }
+      for (int v = 0; v < 4; ++v) At[(16 * bi + li) + acc_col(bj, v) * TS] = acc[bi][bj][v];
 }
 
 // ---- symmetric products y = base + alpha A x -------------------------------------------
