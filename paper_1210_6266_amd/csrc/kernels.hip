@@ -762,9 +762,34 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update(T* tiles, const int64_t
 template <typename T>
 struct Upd2Cfg;
 template <>
-struct Upd2Cfg<double> { static constexpr int KC = 16, LD = 144; };
+struct Upd2Cfg<double> { static constexpr int KC = 8, LD = 144, NS = 4; };
 template <>
-struct Upd2Cfg<float> { static constexpr int KC = 16, LD = 144; };
+struct Upd2Cfg<float> { static constexpr int KC = 8, LD = 144, NS = 4; };
+
+// s_waitcnt for vmcnt <= N (expcnt and lgkmcnt unconstrained; gfx9 field layout)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+// wait for the oldest chunk of an LDS ring with `younger` chunks (PERW loads per wave
+// each) issued after it
+template <int PERW, int NS>
+__device__ __forceinline__ void wait_ring(int younger) {
+  if constexpr (NS >= 4) {
+    if (younger >= 2) {
+      wait_vmcnt<2 * PERW>();
+      return;
+    }
+  }
+  if constexpr (NS >= 3) {
+    if (younger >= 1) {
+      wait_vmcnt<PERW>();
+      return;
+    }
+  }
+  wait_vmcnt<0>();
+}
 
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int64_t* tile_off,
@@ -772,7 +797,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
                                                           const T* cbuf, const T* bbuf,
                                                           int64_t stride, int64_t per_xcd,
                                                           int part, int count) {
-  constexpr int PB = G * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NCH = PB / KC;
+  constexpr int PB = G * TS, KC = Upd2Cfg<T>::KC, LD = Upd2Cfg<T>::LD, NS = Upd2Cfg<T>::NS;
+  constexpr int NCH = PB / KC;
   constexpr int GS = G / 2;                    // super-rows per pivot group
   // Workgroups are dealt to the 8 XCDs round-robin by linear id.  With 8 or more
   // matrices (part 0 or 2, 1-D grid) each XCD takes whole matrices, one after the
@@ -830,26 +856,35 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
     }
     return;
   }
-  __shared__ T sA[2][KC * LD], sB[2][KC * LD];
-  constexpr int PER = KC * 128 / kBlock;       // elements per thread per operand and chunk
-  T ra[PER], rb[PER];
-  auto gload = [&](int ch) {
+  // Panels B_i, C_j stream straight from global memory into an NS-stage LDS ring
+  // (global_load_lds: each wave instruction fills one padded k-row; FP64 16 bytes per
+  // lane for all 128 rows, FP32 4 bytes per lane for one tile's 64 rows), so NS - 1
+  // chunks are in flight while one is multiplied, with one barrier per chunk.
+  constexpr int IPR = sizeof(T) == 8 ? 1 : 2;  // load instructions per k-row and panel
+  constexpr int PERW = 2 * KC * IPR / 4;       // load instructions per wave and chunk
+  __shared__ __attribute__((aligned(16))) T ring[NS][2][KC * LD];
+  auto issue = [&](int ch) {
+    const int st = ch % NS;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      const int r = e % 128, kk = e / 128;
-      const int k = ch * KC + kk;
-      const int i = 2 * BI + r / 64, j = 2 * BJ + r / 64;
-      ra[u] = i < nt ? Bb[int64_t(i) * TS * PB + (r % 64) + k * TS] : T(0);
-      rb[u] = j < nt ? Cb[int64_t(j) * TS * PB + (r % 64) + k * TS] : T(0);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      sA[buf][(e / 128) * LD + (e % 128)] = ra[u];
-      sB[buf][(e / 128) * LD + (e % 128)] = rb[u];
+    for (int u = 0; u < KC * IPR / 4; ++u) {
+      const int idx = w + 4 * u, kk = idx / IPR, hf = idx % IPR, k = ch * KC + kk;
+      const int r = sizeof(T) == 8 ? 2 * lane : 64 * hf + lane;   // first row of the lane
+      // a row block past the matrix reads its super-row's first tile (finite data that
+      // only reaches accumulators of tiles that are never stored)
+      const int iA = 2 * BI + r / 64 < nt ? 2 * BI + r / 64 : 2 * BI;
+      const int iB = 2 * BJ + r / 64 < nt ? 2 * BJ + r / 64 : 2 * BJ;
+      const int lo = sizeof(T) == 8 ? 0 : 64 * hf;
+      const void* ga = Bb + int64_t(iA) * TS * PB + (r % 64) + int64_t(k) * TS;
+      const void* gb = Cb + int64_t(iB) * TS * PB + (r % 64) + int64_t(k) * TS;
+      auto la = (__attribute__((address_space(3))) void*)&ring[st][0][kk * LD + lo];
+      auto lb = (__attribute__((address_space(3))) void*)&ring[st][1][kk * LD + lo];
+      if constexpr (sizeof(T) == 8) {
+        __builtin_amdgcn_global_load_lds(ga, la, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(gb, lb, 16, 0, 0);
+      } else {
+        __builtin_amdgcn_global_load_lds(ga, la, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(gb, lb, 4, 0, 0);
+      }
     }
   };
   // the accumulators start from A_ij (the MFMA's C operand), with the panel of B_i
@@ -868,13 +903,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
       for (int v = 0; v < 4; ++v)
         acc[bi][bj][v] = valid ? At[(16 * bi + li) + acc_col(bj, v) * TS] : T(0);
   const int oa = 64 * (w >> 1) + li, ob = 64 * (w & 1) + li;
-  gload(0);
-  sstore(0);
-  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NS - 1; ++c)
+    if (c < NCH) issue(c);
   for (int ch = 0; ch < NCH; ++ch) {
-    if (ch + 1 < NCH) gload(ch + 1);
-    const T* A_ = sA[ch & 1];
-    const T* B_ = sB[ch & 1];
+    // chunk ch has landed once at most the younger chunks' loads are outstanding
+    wait_ring<PERW, NS>(min(NS - 2, NCH - 1 - ch));
+    __syncthreads();
+    if (ch + NS - 1 < NCH) issue(ch + NS - 1);   // into the stage freed by chunk ch - 1
+    const T* A_ = ring[ch % NS][0];
+    const T* B_ = ring[ch % NS][1];
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T a[4], b[4];
@@ -888,8 +926,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(b[bj], a[bi], acc[bi][bj]);
     }
-    if (ch + 1 < NCH) sstore((ch + 1) & 1);
-    __syncthreads();
   }
   if (!valid) return;
 #pragma unroll
