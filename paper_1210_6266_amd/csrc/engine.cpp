@@ -27,72 +27,157 @@ void hip_check(rsd_ctx* h, hipError_t e, const char* what) {
   throw Fail{e == hipErrorOutOfMemory ? RSD_ERR_OUT_OF_MEMORY : RSD_ERR_DEVICE};
 }
 
-// Device memory comes from one stream-ordered pool per device, owned by the library:
-// memory released by a handle stays in the pool (up to kPoolKeepBytes) and serves the
-// next set-up without new device mappings.
-constexpr uint64_t kPoolKeepBytes = uint64_t(32) << 30;
+// Memory recycling.  The library releases device memory only at points where the work
+// that used it has completed (after a stream or device synchronization), so released
+// blocks go to a per-device cache and serve the next allocation of a similar size
+// without a call into the allocator; repeated set-ups reuse the same mappings.  Pinned
+// host staging buffers (structure copies) are cached the same way.  Blocks beyond
+// kCacheKeepBytes per device are returned to the runtime.
+constexpr size_t kCacheKeepBytes = size_t(48) << 30;
 
-hipMemPool_t device_pool(rsd_ctx* h, int device) {
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> blocks;   // size -> block
+  size_t bytes = 0;
+};
+
+BlockCache& cache_of(int key) {
   static std::mutex mu;
-  static std::map<int, hipMemPool_t> pools;
+  static std::map<int, BlockCache*> caches;   // device id; -1 - device for pinned host
   std::lock_guard<std::mutex> lock(mu);
-  auto it = pools.find(device);
-  if (it != pools.end()) return it->second;
-  hipMemPoolProps props;
-  std::memset(&props, 0, sizeof(props));
-  props.allocType = hipMemAllocationTypePinned;
-  props.handleTypes = hipMemHandleTypeNone;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = device;
-  hipMemPool_t pool;
-  hip_check(h, hipMemPoolCreate(&pool, &props), "hipMemPoolCreate");
-  uint64_t keep = kPoolKeepBytes;
-  hip_check(h, hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep),
-            "hipMemPoolSetAttribute");
-  pools[device] = pool;
-  return pool;
+  BlockCache*& c = caches[key];
+  if (!c) c = new BlockCache();
+  return *c;
+}
+
+size_t round_block(size_t b) {
+  const size_t g = b <= (size_t(1) << 20) ? size_t(4096) : size_t(2) << 20;
+  return (std::max<size_t>(b, 1) + g - 1) / g * g;
+}
+
+// a cached block of at least `bytes` (and not much larger), or nullptr
+void* cache_take(BlockCache& c, size_t bytes, size_t* got) {
+  std::lock_guard<std::mutex> lock(c.mu);
+  auto it = c.blocks.lower_bound(bytes);
+  if (it == c.blocks.end() || it->first > bytes + bytes / 8 + (size_t(4) << 20)) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  c.bytes -= it->first;
+  c.blocks.erase(it);
+  return p;
+}
+
+void cache_give(BlockCache& c, void* p, size_t bytes, bool pinned) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lock(c.mu);
+    c.blocks.insert({bytes, p});
+    c.bytes += bytes;
+    while (c.bytes > kCacheKeepBytes && !c.blocks.empty()) {
+      auto big = std::prev(c.blocks.end());
+      c.bytes -= big->first;
+      drop.push_back(big->second);
+      c.blocks.erase(big);
+    }
+  }
+  for (void* q : drop) (void)(pinned ? hipHostFree(q) : hipFree(q));
+}
+
+void cache_drain(BlockCache& c, bool pinned) {
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (auto& b : c.blocks) (void)(pinned ? hipHostFree(b.second) : hipFree(b.second));
+  c.blocks.clear();
+  c.bytes = 0;
 }
 
 template <typename T>
 T* dalloc(rsd_ctx* h, size_t count) {
-  if (count == 0) count = 1;
-  void* p = nullptr;
-  hip_check(h, hipMallocFromPoolAsync(&p, count * sizeof(T), h->mempool, h->cur),
-            "hipMallocFromPoolAsync");
-  h->allocs.push_back({p, count * sizeof(T)});
-  h->device_bytes += int64_t(count * sizeof(T));
+  const size_t want = round_block(std::max<size_t>(count, 1) * sizeof(T));
+  BlockCache& c = cache_of(h->device);
+  size_t got = want;
+  void* p = cache_take(c, want, &got);
+  if (!p) {
+    hipError_t st = hipMalloc(&p, want);
+    if (st == hipErrorOutOfMemory) {   // give cached blocks back and retry once
+      (void)hipGetLastError();
+      cache_drain(c, false);
+      st = hipMalloc(&p, want);
+    }
+    hip_check(h, st, "hipMalloc");
+  }
+  h->allocs.push_back({p, got});
+  h->device_bytes += int64_t(got);
   return static_cast<T*>(p);
 }
 
+// Releases p; the caller guarantees that no queued work still uses it.
 void dfree(rsd_ctx* h, void* p) {
   if (!p) return;
   for (size_t i = 0; i < h->allocs.size(); ++i)
     if (h->allocs[i].first == p) {
       h->device_bytes -= int64_t(h->allocs[i].second);
+      cache_give(cache_of(h->device), p, h->allocs[i].second, false);
       h->allocs.erase(h->allocs.begin() + long(i));
-      break;
+      return;
     }
-  (void)hipFreeAsync(p, h->cur);
 }
 
-// Packs many host arrays into one device allocation and one host-to-device copy:
-// add() records the destination pointer, commit() allocates, copies and patches.
+// Pinned host staging buffer (released with pfree once the copy has completed).
+Pinned palloc(rsd_ctx* h, size_t bytes) {
+  Pinned b;
+  const size_t want = round_block(bytes);
+  BlockCache& c = cache_of(-1 - h->device);
+  b.bytes = want;
+  b.p = cache_take(c, want, &b.bytes);
+  if (!b.p) hip_check(h, hipHostMalloc(&b.p, want, hipHostMallocDefault), "hipHostMalloc");
+  return b;
+}
+void pfree(rsd_ctx* h, Pinned& b) {
+  if (b.p) cache_give(cache_of(-1 - h->device), b.p, b.bytes, true);
+  b.p = nullptr;
+}
+
+// The auxiliary (look-ahead) stream of a device, shared by the handles on it (default
+// priority; ordering between streams is carried by each handle's own events).
+hipStream_t aux_stream(rsd_ctx* h) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lock(mu);
+  hipStream_t& s = streams[h->device];
+  if (!s) hip_check(h, hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  return s;
+}
+
+// Packs many host arrays into one device allocation and one host-to-device copy from
+// a pinned staging buffer: add() records source and destination pointer (the source
+// must stay alive until commit), commit() allocates, copies and patches; the staging
+// buffer is released by done() after the stream has been synchronized.
 struct Uploader {
-  std::vector<char> host;
-  std::vector<std::pair<void**, size_t>> fix;
+  struct Item {
+    void** dst;
+    const void* src;
+    size_t bytes, off;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  Pinned stage;
   template <typename T, typename P>
   void add(P** dst, const std::vector<T>& v) {
-    const size_t off = (host.size() + 255) & ~size_t(255);
-    host.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
-    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
-    fix.push_back({reinterpret_cast<void**>(const_cast<typename std::remove_const<P>::type**>(dst)), off});
+    const size_t off = (total + 255) & ~size_t(255);
+    total = off + std::max<size_t>(1, v.size()) * sizeof(T);
+    items.push_back({reinterpret_cast<void**>(const_cast<typename std::remove_const<P>::type**>(dst)),
+                     v.data(), v.size() * sizeof(T), off});
   }
   void commit(rsd_ctx* h, hipStream_t s) {
-    char* d = dalloc<char>(h, host.size());
-    hip_check(h, hipMemcpyAsync(d, host.data(), host.size(), hipMemcpyHostToDevice, s),
-              "hipMemcpyAsync H2D");
-    for (auto& f : fix) *f.first = d + f.second;
+    char* d = dalloc<char>(h, total);
+    stage = palloc(h, total);
+    char* hs = static_cast<char*>(stage.p);
+    for (const Item& it : items)
+      if (it.bytes) std::memcpy(hs + it.off, it.src, it.bytes);
+    hip_check(h, hipMemcpyAsync(d, hs, total, hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
+    for (const Item& it : items) *it.dst = d + it.off;
   }
+  void done(rsd_ctx* h) { pfree(h, stage); }
 };
 
 // Times the launches enqueued during its lifetime on stream s (when timing is on).
@@ -254,33 +339,35 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     const int32_t n = csr->n;
     const int64_t nnz = csr->nnz;
     const int32_t T = hier->num_nodes;
-    // ---- host copies of the structure
-    std::vector<int64_t> rp;
-    std::vector<int32_t> ci, par, dn;
+    h->cur = s;
+    // ---- host copies of the structure (pinned staging when it lives on the device)
     const int64_t* rpp = csr->row_ptr;
     const int32_t* cip = csr->col_idx;
     const int32_t* parp = hier->parent;
     const int32_t* dnp = hier->dof_node;
+    Pinned stage;
     if (!h->opt.host_pointers) {
-      rp.resize(size_t(n) + 1);
-      ci.resize(size_t(nnz));
-      par.resize(size_t(T));
-      dn.resize(size_t(n));
-      hip_check(h, hipMemcpyAsync(rp.data(), csr->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, s), "copy row_ptr");
+      hip_check(h, hipGetDevice(&h->device), "hipGetDevice");
+      const size_t b_rp = size_t(n + 1) * 8, b_ci = size_t(nnz) * 4, b_par = size_t(T) * 4;
+      const size_t o_ci = b_rp, o_par = o_ci + ((b_ci + 7) & ~size_t(7)), o_dn = o_par + ((b_par + 7) & ~size_t(7));
+      stage = palloc(h, o_dn + size_t(n) * 4);
+      char* hs = static_cast<char*>(stage.p);
+      hip_check(h, hipMemcpyAsync(hs, csr->row_ptr, b_rp, hipMemcpyDeviceToHost, s), "copy row_ptr");
       if (nnz > 0)
-        hip_check(h, hipMemcpyAsync(ci.data(), csr->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, s), "copy col_idx");
-      hip_check(h, hipMemcpyAsync(par.data(), hier->parent, par.size() * 4, hipMemcpyDeviceToHost, s), "copy parent");
-      hip_check(h, hipMemcpyAsync(dn.data(), hier->dof_node, dn.size() * 4, hipMemcpyDeviceToHost, s), "copy dof_node");
+        hip_check(h, hipMemcpyAsync(hs + o_ci, csr->col_idx, b_ci, hipMemcpyDeviceToHost, s), "copy col_idx");
+      hip_check(h, hipMemcpyAsync(hs + o_par, hier->parent, b_par, hipMemcpyDeviceToHost, s), "copy parent");
+      hip_check(h, hipMemcpyAsync(hs + o_dn, hier->dof_node, size_t(n) * 4, hipMemcpyDeviceToHost, s), "copy dof_node");
       hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
-      rpp = rp.data();
-      cip = ci.data();
-      parp = par.data();
-      dnp = dn.data();
+      rpp = reinterpret_cast<const int64_t*>(hs);
+      cip = reinterpret_cast<const int32_t*>(hs + o_ci);
+      parp = reinterpret_cast<const int32_t*>(hs + o_par);
+      dnp = reinterpret_cast<const int32_t*>(hs + o_dn);
     }
     const auto t0 = std::chrono::steady_clock::now();
     std::string msg;
     const PlanError pe = build_plan(n, nnz, rpp, cip, T, parp, dnp, &h->P, &msg);
     h->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    pfree(h, stage);
     if (pe != PlanError::kOk) {
       h->err = msg;
       return pe == PlanError::kNotSeparable ? RSD_ERR_MAP_NOT_SEPARABLE : RSD_ERR_INVALID_ARGUMENT;
@@ -288,10 +375,8 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->setup_wall[0] = ms_since(w0);
     const auto w1 = std::chrono::steady_clock::now();
     hip_check(h, hipGetDevice(&h->device), "hipGetDevice");
-    h->mempool = device_pool(h, h->device);
-    h->cur = s;
-    // auxiliary stream (default priority) and events of the look-ahead in the inversions
-    hip_check(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking), "hipStreamCreate");
+    // auxiliary stream (shared, default priority) and events of the inversion look-ahead
+    h->aux = aux_stream(h);
     hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
     const Plan& P = h->P;
@@ -398,6 +483,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
     h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    up.done(h);
     h->setup_wall[1] = ms_since(w1);
     return RSD_OK;
   } catch (const Fail& f) {
@@ -569,9 +655,10 @@ void permute(rsd_ctx* h, const double* x, int64_t ldx, double* y, int64_t ldy, i
 
 void ensure_krylov(rsd_ctx* h, int m) {
   if (h->kry_m >= m && h->V) return;
+  if (h->V) hip_check(h, hipStreamSynchronize(h->cur), "hipStreamSynchronize");  // before reuse
   for (double* p : {h->V, h->Z, h->w, h->hdev, h->tmp, h->part, h->scal, h->bint, h->xint})
     dfree(h, p);
-  if (h->hhost) (void)hipHostFree(h->hhost);
+  pfree(h, h->hhost_block);
   const size_t n = size_t(h->P.n);
   h->V = dalloc<double>(h, n * size_t(m + 1));
   h->Z = dalloc<double>(h, n * size_t(m));
@@ -582,7 +669,8 @@ void ensure_krylov(rsd_ctx* h, int m) {
   h->scal = dalloc<double>(h, 16);
   h->bint = dalloc<double>(h, n);
   h->xint = dalloc<double>(h, n);
-  hip_check(h, hipHostMalloc((void**)&h->hhost, sizeof(double) * size_t(m + 16)), "hipHostMalloc");
+  h->hhost_block = palloc(h, sizeof(double) * size_t(m + 16));
+  h->hhost = static_cast<double*>(h->hhost_block.p);
   h->kry_m = m;
 }
 
@@ -902,13 +990,13 @@ void engine_free(rsd_ctx* h) {
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ev_main) (void)hipEventDestroy(h->ev_main);
   if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
   h->ev_main = h->ev_aux = nullptr;
-  h->aux = nullptr;
-  for (auto& p : h->allocs) (void)hipFreeAsync(p.first, nullptr);
+  h->aux = nullptr;                    // shared by the device's handles: not destroyed
+  BlockCache& c = cache_of(h->device);
+  for (auto& p : h->allocs) cache_give(c, p.first, p.second, false);   // work is complete
   h->allocs.clear();
-  (void)hipStreamSynchronize(nullptr);
-  if (h->hhost) (void)hipHostFree(h->hhost);
+  h->device_bytes = 0;
+  pfree(h, h->hhost_block);
   h->hhost = nullptr;
 }
 

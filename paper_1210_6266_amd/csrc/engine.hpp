@@ -11,15 +11,22 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 
+namespace rsd {
+// a pinned host block of the library's cache
+struct Pinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+}  // namespace rsd
+
 struct rsd_ctx {
   rsd::Plan P;
   rsd_options opt{};
   std::string err;
   int device = 0;
 
-  hipMemPool_t mempool = nullptr;   // library pool of this device
-  hipStream_t cur = nullptr;      // stream of the running call (stream-ordered allocations)
-  // every device allocation of the handle
+  hipStream_t cur = nullptr;      // stream of the running call
+  // every device allocation of the handle (block, size as allocated)
   std::vector<std::pair<void*, size_t>> allocs;
   int64_t device_bytes = 0;
 
@@ -52,7 +59,8 @@ struct rsd_ctx {
   int kry_m = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hdev = nullptr, *tmp = nullptr,
          *part = nullptr, *scal = nullptr, *bint = nullptr, *xint = nullptr;
-  double* hhost = nullptr;   // pinned
+  double* hhost = nullptr;   // pinned (hhost_block)
+  rsd::Pinned hhost_block;
 
   // timing
   struct Pending { int cls; hipEvent_t a, b; };
