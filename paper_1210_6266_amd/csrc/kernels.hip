@@ -427,22 +427,67 @@ __device__ __forceinline__ void wave_gemm64(LA lda, LB ldb, typename Mfma<T>::v4
   }
 }
 
+// wave_gemm64 with one operand read from (global) memory for all 64 k up front: the
+// loads of a 64 x 64 operand are issued together (one memory round trip instead of one
+// per k-step), then the MFMAs consume them with the other operand from LDS.
+template <typename T, typename LA, typename LB>
+__device__ __forceinline__ void wave_gemm64_pa(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  T pa[16][4];
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pa[t][q] = lda(16 * q + li, 4 * t + lk);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    T b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = ldb(4 * t + lk, 16 * q + li);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(pa[t][bi], b[bj], acc[bi][bj]);
+  }
+}
+template <typename T, typename LA, typename LB>
+__device__ __forceinline__ void wave_gemm64_pb(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  T pb[16][4];
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pb[t][q] = ldb(4 * t + lk, 16 * q + li);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    T a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = lda(16 * q + li, 4 * t + lk);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], pb[t][bj], acc[bi][bj]);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ int acc_row64(int bi, int v) {
   const int g = (threadIdx.x & 63) >> 4;
   return 16 * bi + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v);
 }
 
+// threads of the blocked pivot: 8 waves for FP32, 4 for FP64 (register budget)
+template <typename T>
+struct PivCfg { static constexpr int threads = sizeof(T) == 8 ? 256 : 512; };
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_sweep_pivot_blk(T* tiles, const int64_t* tile_off,
-                                                            const int32_t* nt_arr, int c0,
-                                                            T* pbuf, int32_t* flags) {
-  constexpr int PB = G * TS;
+__global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
+    T* tiles, const int64_t* tile_off, const int32_t* nt_arr, int c0, T* pbuf, int32_t* flags) {
+  constexpr int PB = G * TS, NTH = PivCfg<T>::threads, NW = NTH / 64;
   const int m = blockIdx.x;
   const int nt = nt_arr[m];
   if (c0 >= nt) return;
   const int g = min(G, nt - c0);
   T* base = tiles + tile_off[m];
+  T* P = pbuf + int64_t(m) * PB * PB;          // written during the last sub-step
   __shared__ T Ps[TT];
   __shared__ T Bs[(G > 1 ? G - 1 : 1) * TT];
   __shared__ T col[2 * TS];
@@ -451,56 +496,86 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pivot_blk(T* tiles, const int6
   if (threadIdx.x == 0) fail = 0;
   __syncthreads();
   auto tl = [&](int r, int c) { return base + tile_index(c0 + r, c0 + c) * TT; };
+  auto pel = [&](int I, int J, int r, int c) -> T& { return P[(I * TS + r) + int64_t(J * TS + c) * PB]; };
   for (int s = 0; s < g; ++s) {
+    const bool last = s == g - 1;
     if (w == 0) wave_sweep64(tl(s, s), Ps, col, &fail);
     __syncthreads();
-    // panel of the group: B_r = C_r P_s, C_r = A[r][s] (tile (r,s) or (s,r)^T)
-    if (w < g && w != s) {
-      const int r = w;
+    if (last)                                  // P_ss = -(swept diagonal tile) = Ps
+      for (int e = threadIdx.x; e < TT; e += NTH) pel(s, s, e % TS, e / TS) = Ps[e];
+    // panel of the group: B_r = C_r P_s, C_r = A[r][s] (tile (r,s) or (s,r)^T); work
+    // item it: column half it % 2 of the (it / 2)-th row r != s
+    for (int it = w; it < 2 * (g - 1); it += NW) {
+      const int rr = it >> 1, hf = it & 1;
+      const int r = rr < s ? rr : rr + 1;
       const T* Cr = r > s ? tl(r, s) : tl(s, r);
       const bool tr = r < s;
-      typename Mfma<T>::v4 acc[4][4];
+      typename Mfma<T>::v4 acc[4][2];
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
-      wave_gemm64<T>([&](int row, int k) { return tr ? Cr[k + row * TS] : Cr[row + k * TS]; },
-                     [&](int k, int c) { return Ps[c + k * TS]; }, acc);
-      T* Br = Bs + (r < s ? r : r - 1) * TT;
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+      const int lk = lane >> 4;
+#pragma unroll 4
+      for (int k = 0; k < TS; k += 4) {
+        T a[4], b[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * q + li, kk = k + lk;
+          a[q] = tr ? Cr[kk + row * TS] : Cr[row + kk * TS];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) b[q] = Ps[(32 * hf + 16 * q + li) + (k + lk) * TS];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+      }
+      T* Br = Bs + rr * TT;
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Br[acc_row64<T>(bi, v) + (16 * bj + li) * TS] = acc[bi][bj][v];
+          for (int v = 0; v < 4; ++v)
+            Br[acc_row64<T>(bi, v) + (32 * hf + 16 * bj + li) * TS] = acc[bi][bj][v];
     }
     __syncthreads();
     // update inside the group: A_rq -= B_r C_q^T for r >= q, r, q != s
-    int item = 0;
-    for (int r = 0; r < g; ++r)
-      for (int q = 0; q <= r; ++q) {
-        if (r == s || q == s) continue;
-        if ((item++ & 3) != w) continue;
-        T* A = tl(r, q);
-        const T* Cq = q > s ? tl(q, s) : tl(s, q);
-        const bool tq = q < s;
-        const T* Br = Bs + (r < s ? r : r - 1) * TT;
-        typename Mfma<T>::v4 acc[4][4];
+    {
+      int item = 0;
+      for (int r = 0; r < g; ++r)
+        for (int q = 0; q <= r; ++q) {
+          if (r == s || q == s) continue;
+          if ((item++ % NW) != w) continue;
+          T* A = tl(r, q);
+          const T* Cq = q > s ? tl(q, s) : tl(s, q);
+          const bool tq = q < s;
+          const T* Br = Bs + (r < s ? r : r - 1) * TT;
+          typename Mfma<T>::v4 acc[4][4];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
+          for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[acc_row64<T>(bi, v) + (16 * bj + li) * TS];
-        wave_gemm64<T>([&](int row, int k) { return -Br[row + k * TS]; },
-                       [&](int k, int c) { return tq ? Cq[k + c * TS] : Cq[c + k * TS]; }, acc);
+              for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[acc_row64<T>(bi, v) + (16 * bj + li) * TS];
+          wave_gemm64<T>([&](int row, int k) { return -Br[row + k * TS]; },
+                         [&](int k, int c) { return tq ? Cq[k + c * TS] : Cq[c + k * TS]; }, acc);
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
+          for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) A[acc_row64<T>(bi, v) + (16 * bj + li) * TS] = acc[bi][bj][v];
-      }
+              for (int v = 0; v < 4; ++v) {
+                const int rw = acc_row64<T>(bi, v), cl = 16 * bj + li;
+                A[rw + cl * TS] = acc[bi][bj][v];
+                if (last) {
+                  pel(r, q, rw, cl) = -acc[bi][bj][v];
+                  if (r != q) pel(q, r, cl, rw) = -acc[bi][bj][v];
+                }
+              }
+        }
+    }
     __syncthreads();
     // row and column s of the group: A[r][s] <- B_r (r > s), A[s][q] <- B_q^T (q < s)
     for (int r = 0; r < g; ++r) {
@@ -508,30 +583,24 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pivot_blk(T* tiles, const int6
       const T* Br = Bs + (r < s ? r : r - 1) * TT;
       T* A = r > s ? tl(r, s) : tl(s, r);
       if (r > s)
-        for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Br[e];
+        for (int e = threadIdx.x; e < TT; e += NTH) A[e] = Br[e];
       else
-        for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Br[(e / TS) + (e % TS) * TS];
+        for (int e = threadIdx.x; e < TT; e += NTH) A[e] = Br[(e / TS) + (e % TS) * TS];
+      if (last)                                // P_rs = -B_r, P_sr = -B_r^T
+        for (int e = threadIdx.x; e < TT; e += NTH) {
+          const int i = e % TS, j = e / TS;
+          pel(r, s, i, j) = -Br[e];
+          pel(s, r, i, j) = -Br[j + i * TS];
+        }
     }
     __syncthreads();
   }
-  // P = -(swept group block) as a full PB x PB matrix, tile by tile (identity on padding)
-  T* P = pbuf + int64_t(m) * PB * PB;
-  for (int t = w; t < G * G; t += 4) {
+  // P on the padding tiles of a short last group: identity on the diagonal
+  for (int t = w; t < G * G; t += NW) {
     const int I = t % G, J = t / G;
-    if (I < g && J < g) {
-      const T* src = I >= J ? tl(I, J) : tl(J, I);
-      const bool tr = I < J;
+    if (I < g && J < g) continue;
 #pragma unroll 8
-      for (int u = 0; u < TS; ++u) {
-        const int r = lane, c = u;
-        const T v = tr ? src[c + r * TS] : src[r + c * TS];
-        P[(I * TS + r) + int64_t(J * TS + c) * PB] = -v;
-      }
-    } else {
-#pragma unroll 8
-      for (int u = 0; u < TS; ++u)
-        P[(I * TS + lane) + int64_t(J * TS + u) * PB] = (I == J && lane == u) ? T(1) : T(0);
-    }
+    for (int u = 0; u < TS; ++u) pel(I, J, lane, u) = (I == J && lane == u) ? T(1) : T(0);
   }
   if (fail && threadIdx.x == 0) flags[m] = c0 + 1;
 }
@@ -1439,8 +1508,8 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
       k_sweep_pivot<T, G><<<b.count, kPivotThreads, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,   \
                                                             (T*)pbuf, flags);                   \
     else if (stage == 0)                                                                        \
-      k_sweep_pivot_blk<T, G><<<b.count, kBlock, 0, s>>>((T*)b.tiles, b.tile_off, b.nt, c0,     \
-                                                         (T*)pbuf, flags);                      \
+      k_sweep_pivot_blk<T, G><<<b.count, PivCfg<T>::threads, 0, s>>>(                          \
+          (T*)b.tiles, b.tile_off, b.nt, c0, (T*)pbuf, flags);                                  \
     else if (stage == 1 && G >= 2)                                                              \
       k_sweep_panel2<T, (G >= 2 ? G : 2)><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(           \
           (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
