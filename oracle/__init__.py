@@ -5,3 +5,4 @@ benchmark's CPU-baseline leg, never by the library or its Python binding.
 """
 from .rsd import Hierarchy, RSDOracle, exact_block_solve  # noqa: F401
 from .krylov import fgmres, pcg  # noqa: F401
+from . import adjoint  # noqa: F401,E402

@@ -29,6 +29,10 @@ rsd_status check_inputs(const rsd_csr* csr, const rsd_hierarchy* hier) {
 
 }  // namespace
 
+namespace rsd {
+void set_thread_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace rsd
+
 extern "C" {
 
 void rsd_options_default(rsd_options* o) {

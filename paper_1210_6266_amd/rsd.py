@@ -69,8 +69,17 @@ class rsd_stats(C.Structure):
                 ("device_bytes", C.c_int64), ("setup_wall_ms", C.c_double * 4)]
 
 
+class rsd_fe_map(C.Structure):
+    _fields_ = [("num_elements", C.c_int32), ("dofs_per_element", C.c_int32),
+                ("nnz", C.c_int64), ("elem_dofs", C.c_void_p), ("ke", C.c_void_p),
+                ("contrib_ptr", C.c_void_p), ("contrib", C.c_void_p)]
+
+
+COEF = {"linear": 0, "exp": 1}
+
 EXPORTS = ["rsd_options_default", "rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv",
-           "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_destroy", "rsd_last_error"]
+           "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_destroy", "rsd_last_error",
+           "rsd_fe_assemble", "rsd_fe_grad"]
 
 
 def library_path() -> str:
@@ -105,8 +114,10 @@ def load():
     lib.rsd_destroy.restype = None
     lib.rsd_last_error.argtypes = [vp]
     lib.rsd_last_error.restype = C.c_char_p
+    lib.rsd_fe_assemble.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp]
+    lib.rsd_fe_grad.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp, vp, vp]
     for f in ["rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv", "rsd_solve",
-              "rsd_update_values", "rsd_get_stats"]:
+              "rsd_update_values", "rsd_get_stats", "rsd_fe_assemble", "rsd_fe_grad"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -312,3 +323,33 @@ class RSD:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ coefficient maps
+class FEMap:
+    """Device copy of a coefficient map (include/rsd_fe.h) built from numpy arrays
+    (elem_dofs int32 E x d, ke d x d, contrib_ptr int64 nnz+1, contrib int32)."""
+
+    def __init__(self, fe: dict, device=None):
+        import torch
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.elem_dofs = torch.as_tensor(np.ascontiguousarray(fe["elem_dofs"], dtype=np.int32), device=dev)
+        self.ke = torch.as_tensor(np.asfortranarray(fe["ke"], dtype=np.float64).ravel(order="F"), device=dev)
+        self.contrib_ptr = torch.as_tensor(np.ascontiguousarray(fe["contrib_ptr"], dtype=np.int64), device=dev)
+        self.contrib = torch.as_tensor(np.ascontiguousarray(fe["contrib"], dtype=np.int32), device=dev)
+        self.num_elements = int(fe["elem_dofs"].shape[0])
+        self.dofs_per_element = int(fe["elem_dofs"].shape[1])
+        self.nnz = int(fe["contrib_ptr"].shape[0]) - 1
+        self.c = rsd_fe_map(self.num_elements, self.dofs_per_element, self.nnz,
+                            _ptr(self.elem_dofs), _ptr(self.ke), _ptr(self.contrib_ptr),
+                            _ptr(self.contrib))
+
+
+def rsd_fe_assemble(fmap: FEMap, theta, kind: str, values, stream=None):
+    _check(load().rsd_fe_assemble(C.byref(fmap.c), _ptr(theta), COEF[kind], _ptr(values),
+                                  _stream(stream)))
+
+
+def rsd_fe_grad(fmap: FEMap, theta, kind: str, lam, x, grad, stream=None):
+    _check(load().rsd_fe_grad(C.byref(fmap.c), _ptr(theta), COEF[kind], _ptr(lam), _ptr(x),
+                              _ptr(grad), _stream(stream)))

@@ -1,6 +1,7 @@
 """Host-side tests of the C ABI (no GPU): the library loads, exports every entry
 point declared in include/rsd.h, and its host analysis validates input and
 reproduces the hierarchy counts computed independently from the matrix."""
+import glob
 import os
 import re
 
@@ -13,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "rsd.h")).read()
+    src = "".join(open(p).read() for p in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(rsd_[a-z_]+)\s*\(", src)))
 

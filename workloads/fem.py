@@ -212,3 +212,55 @@ def consistent_load_3d(ne: int, f) -> np.ndarray:
     ijk = np.stack(np.unravel_index(np.arange(nn ** 3), (nn, nn, nn), order="F"), axis=1)
     free = np.all((ijk > 0) & (ijk < nn - 1), axis=1)
     return b_full[free]
+
+
+def fe_map_grid(ne: tuple, elem: np.ndarray, K: sp.csr_matrix, ndof: int = 1,
+                dirichlet: str = "all") -> dict:
+    """Coefficient map of ``assemble_grid(ne, elem, coef, ndof, dirichlet)``.
+
+    Returns the element dof lists (E x d, -1 on eliminated dofs), the symmetrised
+    element matrix ``ke`` (d x d) and, for every nonzero of ``K`` (CSR order), the list
+    of element entries (e, a, b) that add to it, packed as e*d*d + a*d + b and sorted.
+    Entries with ke[a, b] == 0 are omitted (they add nothing for any coefficient).
+    """
+    dim = len(ne)
+    nn = tuple(e + 1 for e in ne)
+    conn = _element_connectivity(ne)
+    ijk = np.stack(np.unravel_index(np.arange(int(np.prod(nn))), nn, order="F"), axis=1)
+    if dirichlet == "all":
+        free = np.all((ijk > 0) & (ijk < np.array(nn) - 1), axis=1)
+    elif dirichlet == "x0":
+        free = ijk[:, 0] > 0
+    else:
+        raise ValueError(dirichlet)
+    node_id = -np.ones(ijk.shape[0], dtype=np.int64)
+    node_id[free] = np.arange(int(free.sum()))
+    gdof = np.where(np.repeat(free[conn], ndof, axis=1),
+                    node_id[np.repeat(conn, ndof, axis=1)] * ndof
+                    + np.tile(np.arange(ndof), conn.shape[1])[None, :], -1)
+    E, d = gdof.shape
+    ke = 0.5 * (elem + elem.T)
+    a_idx, b_idx = np.meshgrid(np.arange(d), np.arange(d), indexing="ij")
+    a_idx, b_idx = a_idx.ravel(), b_idx.ravel()
+    rows = gdof[:, a_idx]
+    cols = gdof[:, b_idx]
+    code = np.arange(E, dtype=np.int64)[:, None] * d * d + (a_idx * d + b_idx)[None, :]
+    keep = (rows >= 0) & (cols >= 0) & (ke[a_idx, b_idx] != 0.0)[None, :]
+    rows, cols, code = rows[keep], cols[keep], code[keep]
+    n = K.shape[0]
+    Kc = K.tocsr()
+    row_of_nz = np.repeat(np.arange(n, dtype=np.int64), np.diff(Kc.indptr))
+    kkeys = row_of_nz * n + Kc.indices.astype(np.int64)
+    keys = rows * n + cols
+    pos = np.searchsorted(kkeys, keys)
+    if np.any(pos >= kkeys.size) or np.any(kkeys[np.minimum(pos, kkeys.size - 1)] != keys):
+        raise ValueError("element entry outside the sparsity pattern of K")
+    order = np.lexsort((code, pos))
+    counts = np.bincount(pos, minlength=Kc.nnz)
+    ptr = np.zeros(Kc.nnz + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    if E * d * d >= 2 ** 31:
+        raise ValueError("too many element entries for 32-bit packed codes")
+    return dict(elem_dofs=gdof.astype(np.int32), ke=np.ascontiguousarray(ke),
+                contrib_ptr=ptr, contrib=code[order].astype(np.int32), nnz=int(Kc.nnz),
+                num_elements=E, dofs_per_element=d)

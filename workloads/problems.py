@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .fem import assemble_diffusion_3d, assemble_strip_2d
+from .fem import assemble_diffusion_3d, assemble_strip_2d, fe_map_grid, laplace_element
 from .hierarchy import build_box_tree, dof_node_map
 
 
@@ -59,15 +59,23 @@ def diffusion_problem(ne: int, height: int, sigma: float = 0.0, seed: int = 0,
     """
     rng = np.random.default_rng(seed)
     k = None
+    theta = np.zeros(ne ** 3)
     if sigma > 0.0:
-        k = np.exp(sigma * rng.standard_normal(ne ** 3))
+        theta = sigma * rng.standard_normal(ne ** 3)
+        k = np.exp(theta)
     sysm = assemble_diffusion_3d(ne, k)
     tree = build_box_tree(sysm.shape_nodes, height, cut_fn=cut_fn)
     dof_node = dof_node_map(tree, sysm.free_ijk, 1)
     b = rng.uniform(-1.0, 1.0, size=(sysm.K.shape[0], nrhs))
     return Problem(name or f"diffusion{ne}_h{height}", sysm.K, tree.parent, dof_node, b,
                    meta=dict(ne=ne, height=height, sigma=sigma, seed=seed, k_elem=k,
-                             free_ijk=sysm.free_ijk, tree=tree))
+                             theta=theta, free_ijk=sysm.free_ijk, tree=tree))
+
+
+def diffusion_fe_map(p: Problem) -> dict:
+    """Coefficient map of a diffusion problem: K = sum_e exp(theta_e) h K_ref."""
+    ne = p.meta["ne"]
+    return fe_map_grid((ne, ne, ne), (1.0 / ne) * laplace_element(3), p.K)
 
 
 def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
