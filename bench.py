@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one variant only (for profiling runs)")
+    ap.add_argument("--adjoint-steps", type=int, default=5,
+                    help="forward+backward passes timed on the 32^3 adjoint workload (0: skip)")
     return ap.parse_args()
 
 
@@ -229,12 +231,54 @@ def main():
         es = 4 if fp32_leaf else 8
         lb = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
         extra["leaf_apply_GBps"] = lb / (ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3) / 1e9
+    if R0["launches"].get("spmv"):
+        # K in internal order: values 8 B + column 4 B per nonzero, row pointers 8 B per
+        # row, x (gathered, read once from HBM at best) and y 8 B per row
+        sb = 12 * p.K.nnz + 24 * p.n
+        extra["spmv_GBps"] = sb / (ms["spmv"] / nlch["spmv"] * 1e-3) / 1e9
     if R0["launches"].get("root_update"):
         fl = update_flops([ana["max_iface_dofs"]])
         extra["root_update_TFLOPs_fp64"] = fl / (ms["root_update"] * 1e-3) / 1e12
     if R0["launches"].get("leaf_update"):
         fl = update_flops(leaf_sizes)
         extra["leaf_update_TFLOPs"] = fl / (ms["leaf_update"] * 1e-3) / 1e12
+
+    # ---- differentiable solve (adjoint method) on the 32^3 adjoint workload: one pass
+    # = assembly of K(theta) + set-up refresh + forward solve + adjoint solve + gradient
+    adjoint = None
+    if a.adjoint_steps > 0 and a.only is None:
+        from paper_1210_6266_amd.adjoint import DifferentiableSolve
+        from workloads import diffusion_fe_map
+        pa = config_problem("adjoint32", seed=a.seed)
+        fe = diffusion_fe_map(pa)
+        rpa, cia, _ = pa.csr_arrays()
+        th0 = torch.as_tensor(pa.meta["theta"], device=dev)
+        ba = torch.as_tensor(np.ascontiguousarray(pa.b[:, 0]), device=dev)
+        xt = torch.as_tensor(pa.meta["x_target"], device=dev)
+        adjoint = {}
+        for name, prec in (("mixed", dict(leaf_prec="fp32", sigma_prec="fp32",
+                                          iface_prec="fp32", root_prec="fp64")), ("fp64", {})):
+            sysd = DifferentiableSolve(rpa, cia, pa.parent, pa.dof_node, fe, rtol=1e-10, **prec)
+
+            def one(k):
+                theta = (th0 + 1e-3 * k).requires_grad_(True)   # a new K every pass
+                x = sysd(theta, ba)
+                loss = 0.5 * ((x - xt) ** 2).sum()
+                loss.backward()
+                return theta.grad
+
+            one(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(a.adjoint_steps):
+                one(k + 1)
+            torch.cuda.synchronize()
+            its = [i["iterations"] for i in sysd.last_info[-2 * a.adjoint_steps:]]
+            adjoint[name] = dict(ms_per_fwd_bwd=1e3 * (time.perf_counter() - t0) / a.adjoint_steps,
+                                 krylov_iterations=its[:2])
+            sysd.close()
+        adjoint["workload"] = ("diffusion 32^3 Q1, k = exp(theta), theta ~ N(0, 0.5^2), octree h=2; "
+                               "L = 1/2 ||x - x_t||^2; FGMRES(30) to 1e-10 forward and adjoint")
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -290,6 +334,7 @@ def main():
         "device_bytes": {k: r["device_bytes"] for k, r in res.items()},
         "roofline": roof,
         "secondary": extra,
+        "adjoint32": adjoint,
         "cpu_baseline": cpu,
     }
     if "mixed" in res and "fp64" in res:
