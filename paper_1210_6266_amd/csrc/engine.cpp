@@ -301,13 +301,6 @@ void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void
   }
 }
 
-int choose_lpr(double avg) {
-  if (avg <= 6) return 4;
-  if (avg <= 12) return 8;
-  if (avg <= 40) return 16;
-  return 32;
-}
-
 }  // namespace
 
 void fill_analysis(const Plan& P, rsd_analysis* a) {
@@ -385,7 +378,6 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       const int v = std::atoi(g);
       h->group = (v == 1 || v == 2 || v == 4) ? v : 0;
     }
-    h->lpr = choose_lpr(double(nnz) / double(n));
     // ---- upload structure (one allocation, one copy)
     Uploader up;
     up.add(&h->prow, P.prow);
@@ -393,6 +385,9 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     up.add(&h->iperm, P.iperm);
     up.add(&h->skel_lvl_begin, P.skel_lvl_begin);
     up.add(&h->skel_own_end, P.skel_own_end);
+    up.add(&h->ell_off, P.ell_off);
+    h->ell_col = dalloc<int32_t>(h, size_t(P.ell_off.back()));
+    h->ell_val = dalloc<double>(h, size_t(P.ell_off.back()));
     h->pcol = dalloc<int32_t>(h, size_t(nnz));
     h->pmap = dalloc<int64_t>(h, size_t(nnz));
     h->segA = dalloc<int64_t>(h, size_t(n));
@@ -502,6 +497,8 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     {
       Timer tm(h, RSD_T_SETUP_EXTRACT, s);
       hip_check(h, launch_gather(values, h->pmap, P.nnz, h->pval, s), "gather values");
+      hip_check(h, launch_ell_fill(P.n, h->prow, h->pcol, h->pval, h->ell_off, h->ell_col,
+                                   h->ell_val, s), "ELL fill");
       hip_check(h, launch_gather(values, h->kcol_pos, int64_t(P.kcol_val.size()), h->kcol_v, s),
                 "gather couplings");
       hip_check(h, launch_gather(values, h->krow_pos, int64_t(P.krow_val.size()), h->krow_v, s),
@@ -608,8 +605,8 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
   {
     Timer tm(h, RSD_T_COUPLING, s);
     // interface rows: q_B = r_B - K_{B,leaves} y
-    hip_check(h, launch_seg_spmv(nl, n - nl, h->prow, h->segA, h->pcol, h->pval, z, r, -1.0, z,
-                                 h->lpr, s), "condense");
+    hip_check(h, launch_ell_spmv(nl, n - nl, h->prow, h->segA, h->prow, h->ell_off, h->ell_col,
+                                 h->ell_val, z, r, -1.0, z, s), "condense");
     hip_check(h, launch_fill(h->e, int64_t(P.B.size()), 0.0, s), "fill e");
   }
   for (size_t q = 0; q < h->lev.size(); ++q) {
@@ -631,8 +628,8 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
   {
     Timer tm(h, RSD_T_COUPLING, s);
     // leaf rows: r_l - K_{l,B} u_B
-    hip_check(h, launch_seg_spmv(0, nl, h->segA, h->prow + 1, h->pcol, h->pval, z, r, -1.0, h->t,
-                                 h->lpr, s), "back-substitution rhs");
+    hip_check(h, launch_ell_spmv(0, nl, h->segA, h->prow + 1, h->prow, h->ell_off, h->ell_col,
+                                 h->ell_val, z, r, -1.0, h->t, s), "back-substitution rhs");
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
@@ -643,8 +640,8 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
 void core_spmv(rsd_ctx* h, const double* x, const double* base, double alpha, double* y,
                hipStream_t s) {
   Timer tm(h, RSD_T_SPMV, s);
-  hip_check(h, launch_seg_spmv(0, h->P.n, h->prow, h->prow + 1, h->pcol, h->pval, x, base, alpha,
-                               y, h->lpr, s), "spmv");
+  hip_check(h, launch_ell_spmv(0, h->P.n, h->prow, h->prow + 1, h->prow, h->ell_off, h->ell_col,
+                               h->ell_val, x, base, alpha, y, s), "spmv");
 }
 
 void permute(rsd_ctx* h, const double* x, int64_t ldx, double* y, int64_t ldy, int inverse,

@@ -37,6 +37,9 @@ struct rsd_ctx {
   int64_t *kcol_pos = nullptr, *krow_pos = nullptr;   // caller value positions of couplings
   double *kcol_v = nullptr, *krow_v = nullptr;
   double* pval = nullptr;
+  int64_t* ell_off = nullptr;       // sliced ELL copy of K (SpMVs)
+  int32_t* ell_col = nullptr;
+  double* ell_val = nullptr;
   int64_t *B_off = nullptr, *adj_ptr = nullptr, *sig_off_d = nullptr;
   int32_t *B = nullptr, *adj_leaf = nullptr, *adj_pos = nullptr;
   rsd::SigmaArgs sig{};
@@ -48,7 +51,6 @@ struct rsd_ctx {
   int32_t* flags = nullptr;  // one per leaf, then one per interface
   hipStream_t aux = nullptr;          // look-ahead stream of the inversions
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
-  int lpr = 16;
   int group = 0;             // pivot tiles per sweep step (0: by batch size)
 
   // apply work vectors (internal order)

@@ -131,26 +131,69 @@ __global__ void k_permute(const double* __restrict__ x, int64_t ldx, double* __r
     y[i + j * ldy] = x[int64_t(perm[i]) + j * ldx];   // caller -> internal
 }
 
-template <int LPR>
-__global__ __launch_bounds__(kBlock) void k_seg_spmv(int64_t row0, int64_t nrows,
-                                                     const int64_t* __restrict__ s0,
-                                                     const int64_t* __restrict__ s1,
-                                                     const int32_t* __restrict__ col,
-                                                     const double* __restrict__ val,
-                                                     const double* __restrict__ x,
-                                                     const double* __restrict__ base,
-                                                     double alpha, double* __restrict__ y) {
-  const int64_t gid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t lr = gid / LPR;
-  const int lane = int(gid % LPR);
-  if (lr >= nrows) return;
-  const int64_t row = row0 + lr;
-  double s = 0.0;
-  const int64_t e = s1[row];
-  for (int64_t k = s0[row] + lane; k < e; k += LPR) s += val[k] * x[col[k]];
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-  if (lane == 0) y[row] = (base ? base[row] : 0.0) + alpha * s;
+// ---- sliced ELL copy of K (internal order) for the SpMVs -------------------------------
+// Entry k of row r sits at ell_off[r / 64] + 64 k + r % 64: a wave's 64 rows read each
+// k as one coalesced load, one thread per row, no cross-lane reduction.  Padding
+// entries hold column r and value 0.
+__global__ __launch_bounds__(kEllSlice) void k_ell_fill(int64_t n, const int64_t* __restrict__ prow,
+                                                        const int32_t* __restrict__ pcol,
+                                                        const double* __restrict__ pval,
+                                                        const int64_t* __restrict__ ell_off,
+                                                        int32_t* __restrict__ ell_col,
+                                                        double* __restrict__ ell_val) {
+  // one wave per slice: the slice's CSR entries are contiguous, read coalesced; each
+  // finds its row by bisection over the slice's row starts (LDS) and is written to its
+  // slot; then the padding slots of each row
+  const int64_t sl = blockIdx.x, r0 = sl * kEllSlice;
+  const int rows = int(min<int64_t>(kEllSlice, n - r0)), l = threadIdx.x;
+  __shared__ int64_t rs[kEllSlice + 1];     // row starts of the slice and its end
+  if (l < rows) rs[l] = prow[r0 + l];
+  if (l == 0) rs[rows] = prow[r0 + rows];
+  __syncthreads();
+  const int64_t w = (ell_off[sl + 1] - ell_off[sl]) / kEllSlice;
+  int32_t* col = ell_col + ell_off[sl];
+  double* val = ell_val + ell_off[sl];
+  for (int64_t q = rs[0] + l; q < rs[rows]; q += kEllSlice) {
+    int lo = 0, hi = rows;                     // rs[lo] <= q < rs[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rs[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int64_t k = q - rs[lo];
+    col[k * kEllSlice + lo] = pcol[q];
+    val[k * kEllSlice + lo] = pval[q];
+  }
+  if (l < rows)
+    for (int64_t k = rs[l + 1] - rs[l]; k < w; ++k) {
+      col[k * kEllSlice + l] = int32_t(r0 + l);
+      val[k * kEllSlice + l] = 0.0;
+    }
+}
+
+// y[r] = (base ? base[r] : 0) + alpha * sum over the entries of row r with CSR positions
+// in [s0[r], s1[r]) (contiguous: columns are sorted), rows r in [row0, row0 + nrows)
+__global__ __launch_bounds__(kBlock) void k_ell_spmv(
+    int64_t row0, int64_t nrows, const int64_t* __restrict__ s0, const int64_t* __restrict__ s1,
+    const int64_t* __restrict__ prow, const int64_t* __restrict__ ell_off,
+    const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val,
+    const double* __restrict__ x, const double* __restrict__ base, double alpha,
+    double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  const int64_t r = row0 + i;
+  const int64_t p0 = prow[r];
+  const int64_t k0 = s0[r] - p0, k1 = s1[r] - p0;
+  const int64_t o = ell_off[r / kEllSlice] + r % kEllSlice;
+  const int32_t* c = ell_col + o;
+  const double* v = ell_val + o;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t k = k0;
+  for (; k + 1 < k1; k += 2) {
+    a0 += v[k * kEllSlice] * x[c[k * kEllSlice]];
+    a1 += v[(k + 1) * kEllSlice] * x[c[(k + 1) * kEllSlice]];
+  }
+  if (k < k1) a0 += v[k * kEllSlice] * x[c[k * kEllSlice]];
+  y[r] = (base ? base[r] : 0.0) + alpha * (a0 + a1);
 }
 
 // Row r of K in internal order: row perm[r] of the caller's CSR with columns renamed by
@@ -1433,18 +1476,22 @@ hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
   return hipGetLastError();
 }
 
-hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
-                           const int32_t* col, const double* val, const double* x,
-                           const double* base, double alpha, double* y, int lpr,
-                           hipStream_t s) {
+hipError_t launch_ell_fill(int64_t n, const int64_t* prow, const int32_t* pcol,
+                           const double* pval, const int64_t* ell_off, int32_t* ell_col,
+                           double* ell_val, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t ns = (n + kEllSlice - 1) / kEllSlice;
+  k_ell_fill<<<unsigned(ns), kEllSlice, 0, s>>>(n, prow, pcol, pval, ell_off, ell_col, ell_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
+                           const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
+                           const double* ell_val, const double* x, const double* base,
+                           double alpha, double* y, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  const unsigned nb = blocks_for(nrows * lpr);
-  switch (lpr) {
-    case 4: k_seg_spmv<4><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
-    case 8: k_seg_spmv<8><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
-    case 16: k_seg_spmv<16><<<nb, kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
-    default: k_seg_spmv<32><<<blocks_for(nrows * 32), kBlock, 0, s>>>(row0, nrows, s0, s1, col, val, x, base, alpha, y); break;
-  }
+  k_ell_spmv<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, s0, s1, prow, ell_off, ell_col,
+                                                 ell_val, x, base, alpha, y);
   return hipGetLastError();
 }
 

@@ -38,12 +38,16 @@ hipError_t launch_gather(const double* src, const int64_t* map, int64_t count, d
 hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
                           const int32_t* perm, int64_t n, int32_t nrhs, int32_t inverse,
                           hipStream_t s);
-// y[r] = (base ? base[r] : 0) + alpha * sum_{k in [s0[r], s1[r])} val[k] x[col[k]],
-// rows r in [row0, row0 + nrows); lanes_per_row in {4, 8, 16, 32}
-hipError_t launch_seg_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
-                           const int32_t* col, const double* val, const double* x,
-                           const double* base, double alpha, double* y, int lanes_per_row,
-                           hipStream_t s);
+// sliced ELL copy of K (layout in plan.hpp) and the segmented SpMV on it:
+// y[r] = (base ? base[r] : 0) + alpha * sum over the entries of row r with CSR positions in
+// [s0[r], s1[r]), rows r in [row0, row0 + nrows), entries summed in column order
+hipError_t launch_ell_fill(int64_t n, const int64_t* prow, const int32_t* pcol,
+                           const double* pval, const int64_t* ell_off, int32_t* ell_col,
+                           double* ell_val, hipStream_t s);
+hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
+                           const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
+                           const double* ell_val, const double* x, const double* base,
+                           double alpha, double* y, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // K in internal order from the caller's CSR (device arrays): pcol, pmap (caller value
 // position of each entry) and the row segments segA / segB / segC

@@ -291,6 +291,16 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     const int32_t o = P->perm[r];
     P->prow[r + 1] = P->prow[r] + (row_ptr[o + 1] - row_ptr[o]);
   }
+  {
+    const int64_t ns = (int64_t(n) + kEllSlice - 1) / kEllSlice;
+    P->ell_off.assign(size_t(ns) + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      int64_t w = 0;
+      for (int64_t r = sl * kEllSlice; r < std::min<int64_t>(n, (sl + 1) * kEllSlice); ++r)
+        w = std::max(w, P->prow[r + 1] - P->prow[r]);
+      P->ell_off[sl + 1] = P->ell_off[sl] + w * kEllSlice;
+    }
+  }
 
   // ---- per leaf: B_l, shell_l, K_{l,B_l} by columns, K_{B_l,l} by rows ----------------
   // (read from the caller's CSR; value positions are the caller's)

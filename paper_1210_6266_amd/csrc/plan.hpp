@@ -25,6 +25,7 @@ namespace rsd {
 
 constexpr int kTile = 64;  // dense blocks are stored as kTile x kTile tiles
 constexpr int kSymB = 4;   // symmetric products work on kSymB x kSymB blocks of tiles
+constexpr int kEllSlice = 64;  // rows per ELL slice (one wave)
 
 // A batch of symmetric matrices stored as packed lower tiles (tile (I, J) with
 // I >= J; column-major kTile x kTile each; diagonal tiles hold both triangles).
@@ -74,6 +75,9 @@ struct Plan {
   // K in internal order: row pointers here; the columns, the map to the caller's
   // value positions and the row segments are built on the device from perm/iperm
   std::vector<int64_t> prow;
+  // the same rows as sliced ELL for the SpMV: slices of kEllSlice consecutive rows,
+  // slice s padded to its longest row; entry k of row r at ell_off[s] + k kEllSlice + r % kEllSlice
+  std::vector<int64_t> ell_off;
   std::vector<int32_t> skel_lvl_begin;       // per interface dof: first dof of its level
   std::vector<int32_t> skel_own_end;         // per interface dof: end of its node's dofs
 
