@@ -186,14 +186,22 @@ __global__ __launch_bounds__(kBlock) void k_ell_spmv(
   const int64_t o = ell_off[r / kEllSlice] + r % kEllSlice;
   const int32_t* c = ell_col + o;
   const double* v = ell_val + o;
-  double a0 = 0.0, a1 = 0.0;
-  int64_t k = k0;
-  for (; k + 1 < k1; k += 2) {
-    a0 += v[k * kEllSlice] * x[c[k * kEllSlice]];
-    a1 += v[(k + 1) * kEllSlice] * x[c[(k + 1) * kEllSlice]];
+  // eight slots at a time: their column and value loads are independent, then the
+  // eight gathers of x; out-of-range slots read slot k0 with a zero weight
+  double acc = 0.0;
+  for (int64_t kb = k0; kb < k1; kb += 8) {
+    int32_t ci[8];
+    double vi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t kk = kb + u < k1 ? kb + u : k0;
+      ci[u] = c[kk * kEllSlice];
+      vi[u] = kb + u < k1 ? v[kk * kEllSlice] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += vi[u] * x[ci[u]];
   }
-  if (k < k1) a0 += v[k * kEllSlice] * x[c[k * kEllSlice]];
-  y[r] = (base ? base[r] : 0.0) + alpha * (a0 + a1);
+  y[r] = (base ? base[r] : 0.0) + alpha * acc;
 }
 
 // Row r of K in internal order: row perm[r] of the caller's CSR with columns renamed by
