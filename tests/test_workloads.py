@@ -133,3 +133,47 @@ def test_hierarchy_ownership_rule():
     assert tree.depth[owner[2]] == 1                 # on level-1 planes of octant (0,0,0)
     assert tree.depth[owner[3]] == 2 and tree.depth[owner[5]] == 2
     assert tree.depth[owner[4]] == 1
+
+
+def test_elasticity_element_rigid_body_modes():
+    """The unconstrained element annihilates the 6 rigid-body modes and has rank 18;
+    a single-node stretch has the closed-form energy of the isotropic law."""
+    from workloads.fem import _corners, elasticity_element_3d
+    K = elasticity_element_3d(1.0, 0.3)
+    c = _corners(3).astype(float)
+    modes = []
+    for t in range(3):
+        v = np.zeros(24)
+        v[t::3] = 1.0
+        modes.append(v)
+    for i, j in [(0, 1), (1, 2), (0, 2)]:
+        v = np.zeros(24)
+        v[i::3] = -c[:, j]
+        v[j::3] = c[:, i]
+        modes.append(v)
+    R = np.array(modes).T
+    assert np.abs(K - K.T).max() == 0.0
+    assert np.abs(K @ R).max() < 1e-14
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(ev > 1e-10) == 18 and np.all(ev > -1e-12)
+    # uniform strain u_x = x: energy = 1/2 (lambda + 2 mu) * volume
+    lam, mu = 0.3 / (1.3 * 0.4), 1.0 / 2.6
+    u = np.zeros(24)
+    u[0::3] = c[:, 0]
+    assert abs(0.5 * u @ K @ u - 0.5 * (lam + 2 * mu)) < 1e-14
+
+
+def test_elasticity_workload_sizes():
+    """48^3 clamped at x = 0: n = 3 * 49^2 * 48; octree of height 3 over uneven cuts
+    (leaf interiors 192..882 dofs, root interface 20,880); 8 right-hand sides."""
+    from workloads import config_problem
+    p = config_problem("elasticity48")
+    assert p.n == 3 * 49 * 49 * 48 == 345744
+    assert p.b.shape == (p.n, 8)
+    T = p.parent.size
+    cnt = np.bincount(p.dof_node, minlength=T)
+    isleaf = np.ones(T, bool)
+    isleaf[p.parent[p.parent >= 0]] = False
+    assert isleaf.sum() == 512 and cnt[isleaf].min() == 192 and cnt[isleaf].max() == 882
+    assert cnt[0] == 20880
+    assert abs(p.K - p.K.T).max() == 0.0

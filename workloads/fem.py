@@ -46,6 +46,29 @@ def _shape(dim: int, xi: np.ndarray):
     return val, grad
 
 
+def elasticity_element_3d(E: float, nu: float) -> np.ndarray:
+    """Unit-cell linear-elasticity stiffness  int eps(v) : C : eps(u)  (24 x 24).
+
+    Isotropic C with Lame constants lambda = E nu / ((1 + nu)(1 - 2 nu)) and
+    mu = E / (2 (1 + nu)): sigma = 2 mu eps + lambda tr(eps) I.  Dofs are node-major:
+    (u_x, u_y, u_z) per corner.  For an element of size h the matrix scales by h.
+    """
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    K = np.zeros((24, 24))
+    for q in itertools.product(range(2), repeat=3):
+        xi = np.array([_G2[i] for i in q])
+        w = np.prod([_W2[i] for i in q])
+        _, g = _shape(3, xi)
+        for a in range(8):
+            for b in range(8):
+                # 2 mu eps:eps = mu (grad u : grad v + grad u : grad v^T), plus lambda div div
+                blk = mu * (g[a] @ g[b]) * np.eye(3) + mu * np.outer(g[b], g[a]) \
+                    + lam * np.outer(g[a], g[b])
+                K[3 * a:3 * a + 3, 3 * b:3 * b + 3] += w * blk
+    return K
+
+
 def laplace_element(dim: int) -> np.ndarray:
     """Unit-cell stiffness  int grad(phi_a) . grad(phi_b)  (2^dim x 2^dim)."""
     n = 2 ** dim
@@ -177,6 +200,14 @@ def assemble_diffusion_3d(ne: int, k_elem: np.ndarray | None = None) -> GridSyst
     """
     h = 1.0 / ne
     return assemble_grid((ne, ne, ne), h * laplace_element(3), k_elem, 1, "all", (h, h, h))
+
+
+def assemble_elasticity_3d(ne: int, E: float = 1.0, nu: float = 0.3) -> GridSystem:
+    """Linear elasticity on the unit cube, ne^3 trilinear elements, the face x = 0
+    clamped (its nodes eliminated), 3 dofs per node."""
+    h = 1.0 / ne
+    return assemble_grid((ne, ne, ne), h * elasticity_element_3d(E, nu), None, 3, "x0",
+                         (h, h, h))
 
 
 def assemble_strip_2d(N: int, P: int, problem: str) -> GridSystem:

@@ -25,7 +25,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .fem import assemble_diffusion_3d, assemble_strip_2d, fe_map_grid, laplace_element
+from .fem import (assemble_diffusion_3d, assemble_elasticity_3d, assemble_strip_2d, fe_map_grid,
+                  laplace_element)
 from .hierarchy import build_box_tree, dof_node_map
 
 
@@ -83,6 +84,8 @@ def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
         return diffusion_problem(12, 1, 0.0, seed, nrhs, name)
     if name == "diffusion64":
         return diffusion_problem(64, 2, 1.0, seed, nrhs, name)
+    if name == "elasticity48":
+        return elasticity_problem(48, 3, seed, 8 if nrhs == 1 else nrhs, name)
     if name == "adjoint32":
         p = diffusion_problem(32, 2, 0.5, seed, nrhs, name)
         # draw order continues after b: the adjoint target
@@ -92,6 +95,41 @@ def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
         p.meta["x_target"] = rng.uniform(-1.0, 1.0, size=p.n)
         return p
     raise KeyError(name)
+
+
+def uneven_cuts(seed: int, lo_frac: float = 0.45, hi_frac: float = 0.55):
+    """Random axis-aligned cut planes: each box is cut at a fraction drawn from
+    U[lo_frac, hi_frac] of its extent; over an octree of height 3 the fractions
+    compound (48^3 elasticity: leaf interiors of 192 to 882 dofs).  Drawn in the
+    tree's breadth-first order from their own generator."""
+    rng = np.random.default_rng(seed)
+
+    def cut(depth, axis, lo, hi):
+        m = lo + int(round(rng.uniform(lo_frac, hi_frac) * (hi - lo)))
+        return min(max(m, lo + 1), hi - 1)
+    return cut
+
+
+def elasticity_problem(ne: int, height: int, seed: int = 0, nrhs: int = 8,
+                       name: str | None = None) -> Problem:
+    """3-D linear elasticity (E = 1, nu = 0.3) on ne^3 Q1 hexahedra, the face x = 0
+    clamped, an octree of the given height over random uneven cut planes.
+
+    Right-hand sides: the nodal body load (0, 0, -1) h^3 plus N(0, 0.1^2) h^3 per dof,
+    nrhs columns.  Draw order: the cut planes (their own stream, seed + 1), then the
+    load perturbations (seed).
+    """
+    sysm = assemble_elasticity_3d(ne)
+    tree = build_box_tree(sysm.shape_nodes, height, cut_fn=uneven_cuts(seed + 1))
+    dof_node = dof_node_map(tree, sysm.free_ijk, 3)
+    n = sysm.K.shape[0]
+    h3 = (1.0 / ne) ** 3
+    body = np.tile(np.array([0.0, 0.0, -1.0]), n // 3)
+    rng = np.random.default_rng(seed)
+    b = (body[:, None] + 0.1 * rng.standard_normal((n, nrhs))) * h3
+    return Problem(name or f"elasticity{ne}_h{height}", sysm.K, tree.parent, dof_node, b,
+                   meta=dict(ne=ne, height=height, seed=seed, free_ijk=sysm.free_ijk,
+                             tree=tree))
 
 
 def strip_problem(N: int, P: int, problem: str = "poisson", seed: int = 0) -> Problem:
