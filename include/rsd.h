@@ -151,8 +151,10 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
  * deepest to the root (right-hand side g of eq. (schur), interface solve,
  * back-substitution of eq. (backSub) onto the adjacent sub-domains), then the
  * final sub-domain solves.  r and z are device arrays (n x nrhs, ld >= n) and
- * must not overlap.  nrhs = 0 is a no-op.  Asynchronous on `stream`.
- * Errors: INVALID_ARGUMENT, DEVICE. */
+ * must not overlap.  Up to 8 columns go through each step together (each dense
+ * block and K read once per 4 columns, the SpMV slots once per 8); every column
+ * gets bitwise the result it gets alone.  nrhs = 0 is a no-op.  Asynchronous on
+ * `stream`.  Errors: INVALID_ARGUMENT, DEVICE. */
 rsd_status rsd_apply(rsd_handle h, int32_t nrhs, const double* r, int64_t ldr, double* z,
                      int64_t ldz, void* stream);
 
@@ -166,7 +168,11 @@ rsd_status rsd_spmv(rsd_handle h, int32_t nrhs, const double* x, int64_t ldx, do
  * preconditioned flexible GMRES(m), or PCG), in FP64, to the true relative
  * residual ||b - K x||_2 <= rtol ||b||_2.  b and x are device arrays; info is a
  * HOST array of nrhs entries (may be NULL).  opt may be NULL (FGMRES(30),
- * rtol 1e-10, maxit 500, x0 = 0).  Synchronises `stream` once per iteration.
+ * rtol 1e-10, maxit 500, x0 = 0).  FGMRES advances groups of up to 8 columns
+ * in lockstep (one preconditioner application and one SpMV for the group per
+ * iteration, one host synchronisation of `stream` per iteration); each column
+ * keeps its own Krylov basis, stops on its own criterion and gets bitwise the
+ * iterate and info of a solve alone.  PCG takes the columns one at a time.
  * Returns the worst per-column status: NOT_CONVERGED (x holds the last
  * iterate), BREAKDOWN, or OK. */
 rsd_status rsd_solve(rsd_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,

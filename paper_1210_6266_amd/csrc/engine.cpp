@@ -474,6 +474,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->t = dalloc<double>(h, size_t(n));
     h->rin = dalloc<double>(h, size_t(n));
     h->zin = dalloc<double>(h, size_t(n));
+    h->nvec = 1;
     size_t part_bytes = std::max<size_t>(8, symv_part_bytes(h->leaf));
     for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
     h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
@@ -594,34 +595,39 @@ namespace {
 // every sub-domain solve; per interface level from the deepest: right-hand side g
 // of eq. (schur) -- the interface part of r minus the couplings to the already
 // computed values below it -- and the interface solve; then the back-substitution
-// of eq. (backSub) on every sub-domain at once.
-void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
+// of eq. (backSub) on every sub-domain at once.  nv vectors (r_k = r + k n, likewise
+// z) go through every step together: the factors and K are read once per group of
+// vectors that a kernel holds, and each vector's result is the one it has alone.
+void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   const Plan& P = h->P;
-  const int64_t n = P.n, nl = P.n_leaf;
+  const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, r, h->sympart, -1.0, nullptr, z, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf, r, h->sympart, -1.0, nullptr, z, nv, n, s), "leaf symv");
   }
   {
     Timer tm(h, RSD_T_COUPLING, s);
     // interface rows: q_B = r_B - K_{B,leaves} y
     hip_check(h, launch_ell_spmv(nl, n - nl, h->prow, h->segA, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, z, s), "condense");
-    hip_check(h, launch_fill(h->e, int64_t(P.B.size()), 0.0, s), "fill e");
+                                 h->ell_val, z, r, -1.0, z, nv, n, h->xil, n, s), "condense");
+    hip_check(h, launch_fill(h->e, nB * nv, 0.0, s), "fill e");
   }
   for (size_t q = 0; q < h->lev.size(); ++q) {
     {
       Timer tm(h, RSD_T_COUPLING, s);
       hip_check(h, launch_sigma_level(h->lev_items[q], h->sigma, h->sigma_fp32, h->sig_off_d,
-                                      h->B_off, h->B, z, h->e, s), "sigma level");
+                                      h->B_off, h->B, z, h->e, nv, n, nB, s), "sigma level");
+      // g_t = q_t - K_{t, deeper interfaces} u - sum over adjacent leaves of e_l
       const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
-      hip_check(h, launch_level_rhs(r0, r1 - r0, nl, h->pcol, h->pval, h->segA, h->segB,
-                                    h->adj_ptr, h->adj_leaf, h->adj_pos, h->B_off, h->e, z, s),
+      hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segA, h->segB, h->prow, h->ell_off,
+                                   h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, n, s),
                 "level rhs");
+      hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos,
+                                    h->B_off, h->e, z, nv, n, nB, s), "level adjacency");
     }
     {
       Timer tm(h, RSD_T_IFACE_APPLY, s);
-      hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, s),
+      hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, nv, n, s),
                 "interface symv");
     }
   }
@@ -629,172 +635,275 @@ void core_apply(rsd_ctx* h, const double* r, double* z, hipStream_t s) {
     Timer tm(h, RSD_T_COUPLING, s);
     // leaf rows: r_l - K_{l,B} u_B
     hip_check(h, launch_ell_spmv(0, nl, h->segA, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, h->t, s), "back-substitution rhs");
+                                 h->ell_val, z, r, -1.0, h->t, nv, n, h->xil, n, s),
+              "back-substitution rhs");
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, h->t, h->sympart, -1.0, nullptr, z, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf, h->t, h->sympart, -1.0, nullptr, z, nv, n, s), "leaf symv");
   }
 }
 
-void core_spmv(rsd_ctx* h, const double* x, const double* base, double alpha, double* y,
+// y_k = base_k + alpha K x_k for nv internal-order vectors (stride n)
+void core_spmv(rsd_ctx* h, int nv, const double* x, const double* base, double alpha, double* y,
                hipStream_t s) {
   Timer tm(h, RSD_T_SPMV, s);
   hip_check(h, launch_ell_spmv(0, h->P.n, h->prow, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                               h->ell_val, x, base, alpha, y, s), "spmv");
+                               h->ell_val, x, base, alpha, y, nv, h->P.n, h->xil, h->P.n, s),
+            "spmv");
 }
 
-void permute(rsd_ctx* h, const double* x, int64_t ldx, double* y, int64_t ldy, int inverse,
-             hipStream_t s) {
+void permute(rsd_ctx* h, int nv, const double* x, int64_t ldx, double* y, int64_t ldy,
+             int inverse, hipStream_t s) {
   Timer tm(h, RSD_T_PERMUTE, s);
-  hip_check(h, launch_permute(x, ldx, y, ldy, h->perm, h->P.n, 1, inverse, s), "permute");
+  hip_check(h, launch_permute(x, ldx, y, ldy, h->perm, h->P.n, nv, inverse, s), "permute");
 }
 
-void ensure_krylov(rsd_ctx* h, int m) {
-  if (h->kry_m >= m && h->V) return;
-  if (h->V) hip_check(h, hipStreamSynchronize(h->cur), "hipStreamSynchronize");  // before reuse
+// Right-hand sides handled together by one apply, SpMV or Krylov iteration.
+constexpr int kRhsGroup = 8;
+
+// Apply work vectors (e, t, rin, zin, xil) for nv vectors at once.
+void ensure_vectors(rsd_ctx* h, int nv) {
+  if (h->nvec >= nv) return;
+  hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
+  for (double* p : {h->e, h->t, h->rin, h->zin, h->xil}) dfree(h, p);
+  const size_t n = size_t(h->P.n), nB = std::max<size_t>(1, h->P.B.size());
+  h->xil = dalloc<double>(h, n * size_t(kEllVec));      // interleaved copies for the SpMVs
+  h->e = dalloc<double>(h, nB * size_t(nv));
+  h->t = dalloc<double>(h, n * size_t(nv));
+  h->rin = dalloc<double>(h, n * size_t(nv));
+  h->zin = dalloc<double>(h, n * size_t(nv));
+  h->nvec = nv;
+}
+
+// Krylov work space for restart length m and nr right-hand sides in lockstep.
+void ensure_krylov(rsd_ctx* h, int m, int nr) {
+  if (h->kry_m >= m && h->kry_nr >= nr && h->V) return;
+  if (h->V) hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
   for (double* p : {h->V, h->Z, h->w, h->hdev, h->tmp, h->part, h->scal, h->bint, h->xint})
     dfree(h, p);
   pfree(h, h->hhost_block);
-  const size_t n = size_t(h->P.n);
-  h->V = dalloc<double>(h, n * size_t(m + 1));
-  h->Z = dalloc<double>(h, n * size_t(m));
-  h->w = dalloc<double>(h, n);
-  h->hdev = dalloc<double>(h, size_t(m + 2));
-  h->tmp = dalloc<double>(h, size_t(m + 2));
-  h->part = dalloc<double>(h, size_t(mdot_blocks(h->P.n)) * size_t(m + 2));
-  h->scal = dalloc<double>(h, 16);
-  h->bint = dalloc<double>(h, n);
-  h->xint = dalloc<double>(h, n);
-  h->hhost_block = palloc(h, sizeof(double) * size_t(m + 16));
+  m = std::max(m, h->kry_m);
+  nr = std::max(nr, h->kry_nr);
+  const size_t n = size_t(h->P.n), r = size_t(nr);
+  h->V = dalloc<double>(h, n * size_t(m + 1) * r);
+  h->Z = dalloc<double>(h, n * size_t(m) * r);
+  h->w = dalloc<double>(h, n * r);
+  h->hdev = dalloc<double>(h, size_t(m + 2) * r);
+  h->tmp = dalloc<double>(h, size_t(m + 2) * r);
+  h->part = dalloc<double>(h, size_t(mdot_blocks(h->P.n)) * size_t(m + 2) * r);
+  h->scal = dalloc<double>(h, 16 * r);
+  h->bint = dalloc<double>(h, n * r);
+  h->xint = dalloc<double>(h, n * r);
+  h->hhost_block = palloc(h, sizeof(double) * size_t(m + 16) * r);
   h->hhost = static_cast<double*>(h->hhost_block.p);
   h->kry_m = m;
+  h->kry_nr = nr;
+}
+
+// ||v_k|| for nv vectors (stride ld) into out_dev[k * so]; returned on the host.
+std::vector<double> dev_norms(rsd_ctx* h, int nv, const double* v, int64_t ld, double* out_dev,
+                              int64_t so, hipStream_t s) {
+  {
+    Timer tm(h, RSD_T_KRYLOV, s);
+    hip_check(h, launch_mdot(nv, v, h->P.n, ld, 1, v, ld, h->P.n, h->part, out_dev, so, 1, s),
+              "norm");
+  }
+  for (int k = 0; k < nv; ++k)
+    hip_check(h, hipMemcpyAsync(h->hhost + k, out_dev + k * so, 8, hipMemcpyDeviceToHost, s),
+              "D2H");
+  hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+  return std::vector<double>(h->hhost, h->hhost + nv);
 }
 
 double dev_norm(rsd_ctx* h, const double* v, double* out_dev, hipStream_t s) {
-  {
-    Timer tm(h, RSD_T_KRYLOV, s);
-    hip_check(h, launch_mdot(v, h->P.n, 1, v, h->P.n, h->part, out_dev, 1, s), "norm");
-  }
-  hip_check(h, hipMemcpyAsync(h->hhost, out_dev, 8, hipMemcpyDeviceToHost, s), "D2H");
-  hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
-  return h->hhost[0];
+  return dev_norms(h, 1, v, h->P.n, out_dev, 1, s)[0];
 }
 
-// Right-preconditioned flexible GMRES(m) in internal order; x (internal) holds the
-// initial guess.  Returns the status of this right-hand side.
-rsd_status fgmres_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_options& o,
-                      rsd_solve_info* info, hipStream_t s) {
+// Right-preconditioned flexible GMRES(m) for nr right-hand sides in lockstep, in
+// internal order; x holds the initial guesses.  Right-hand side i keeps its own
+// Arnoldi basis, Hessenberg matrix and Givens rotations; the preconditioner, the SpMV
+// and the Gram-Schmidt kernels take all of them in one launch, and the host waits once
+// per iteration for the whole group.  Column j of right-hand side i is V + (j nr + i) n
+// (likewise Z).  Kernels run over the range [lo, hi) of right-hand sides still
+// iterating; one that has stopped but lies inside the range is carried along, and
+// those extra results are never read.  Each right-hand side's arithmetic is that of
+// its solve alone.
+void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solve_options& o,
+                  rsd_solve_info* info, hipStream_t s) {
   const int64_t n = h->P.n;
   const int m = o.restart;
-  double* beta_d = h->scal;      // scal[0]: ||r||, scal[1]: ||b||
-  const double bnorm = dev_norm(h, b, h->scal + 1, s);
-  if (!(bnorm == bnorm) || std::isinf(bnorm)) {
-    info->iterations = 0;
-    info->relres = NAN;
-    return RSD_ERR_BREAKDOWN;
+  const int64_t ldV = int64_t(nr) * n;   // column stride of one right-hand side's basis
+  const int64_t hs = m + 2;              // per right-hand side stride of hdev / tmp / hhost
+  double* beta_d = h->scal;              // ||r_i||
+  double* bnorm_d = h->scal + nr;        // ||b_i||
+  double* W = h->w;
+  struct Rhs {
+    double bnorm = 0, tol = 0, beta = 0;
+    int its = 0, k = 0;
+    bool done = false, stop = false, bad = false;
+    std::vector<double> H, cs, sn, g, y;
+  };
+  std::vector<Rhs> R(static_cast<size_t>(nr));
+  auto finish = [&](int i, rsd_status st, double relres) {
+    R[i].done = true;
+    info[i].iterations = R[i].its;
+    info[i].relres = relres;
+    info[i].status = st;
+  };
+  auto range = [&](bool inner, int* lo, int* hi) {
+    *lo = nr;
+    *hi = 0;
+    for (int i = 0; i < nr; ++i)
+      if (!R[i].done && !(inner && R[i].stop)) {
+        *lo = std::min(*lo, i);
+        *hi = i + 1;
+      }
+    return *lo < *hi;
+  };
+  {
+    const std::vector<double> bn = dev_norms(h, nr, b, n, bnorm_d, 1, s);
+    for (int i = 0; i < nr; ++i) {
+      Rhs& q = R[i];
+      q.bnorm = bn[i];
+      q.H.assign(size_t(m + 1) * m, 0.0);
+      q.cs.assign(m, 0.0);
+      q.sn.assign(m, 0.0);
+      q.g.assign(m + 1, 0.0);
+      q.y.assign(m, 0.0);
+      if (!(q.bnorm == q.bnorm) || std::isinf(q.bnorm)) {
+        finish(i, RSD_ERR_BREAKDOWN, NAN);
+      } else if (q.bnorm == 0.0) {
+        hip_check(h, launch_fill(x + i * n, n, 0.0, s), "zero x");
+        finish(i, RSD_OK, 0.0);
+      } else {
+        q.tol = o.rtol * q.bnorm;
+      }
+    }
   }
-  if (bnorm == 0.0) {
-    hip_check(h, launch_fill(x, n, 0.0, s), "zero x");
-    info->iterations = 0;
-    info->relres = 0.0;
-    return RSD_OK;
-  }
-  const double tol = o.rtol * bnorm;
-  double* r = h->w;
-  core_spmv(h, x, b, -1.0, r, s);
-  double beta = dev_norm(h, r, beta_d, s);
-  int its = 0;
-  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // true residuals r_i = b_i - K x_i (in W) and their norms
+  auto residuals = [&]() {
+    int lo, hi;
+    if (!range(false, &lo, &hi)) return;
+    core_spmv(h, hi - lo, x + lo * n, b + lo * n, -1.0, W + lo * n, s);
+    const std::vector<double> bt = dev_norms(h, hi - lo, W + lo * n, n, beta_d + lo, 1, s);
+    for (int i = lo; i < hi; ++i) R[i].beta = bt[i - lo];
+  };
+  residuals();
   for (;;) {
-    if (beta <= tol) {
-      info->iterations = its;
-      info->relres = beta / bnorm;
-      return RSD_OK;
+    for (int i = 0; i < nr; ++i) {
+      Rhs& q = R[i];
+      if (q.done) continue;
+      if (q.beta <= q.tol) finish(i, RSD_OK, q.beta / q.bnorm);
+      else if (!(q.beta == q.beta)) finish(i, RSD_ERR_BREAKDOWN, NAN);
+      else if (q.its >= o.maxit) finish(i, RSD_ERR_NOT_CONVERGED, q.beta / q.bnorm);
     }
-    if (!(beta == beta)) {
-      info->iterations = its;
-      info->relres = NAN;
-      return RSD_ERR_BREAKDOWN;
-    }
-    if (its >= o.maxit) {
-      info->iterations = its;
-      info->relres = beta / bnorm;
-      return RSD_ERR_NOT_CONVERGED;
-    }
+    int lo, hi;
+    if (!range(false, &lo, &hi)) return;
     {
       Timer tm(h, RSD_T_KRYLOV, s);
-      hip_check(h, launch_scale_div(r, beta_d, h->V, n, s), "v0");
+      hip_check(h, launch_scale_div(hi - lo, W + lo * n, n, beta_d + lo, 1, h->V + lo * n, n, n, s),
+                "v0");
     }
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    bool bad = false;
+    for (int i = lo; i < hi; ++i) {
+      Rhs& q = R[i];
+      if (q.done) continue;
+      std::fill(q.H.begin(), q.H.end(), 0.0);
+      std::fill(q.g.begin(), q.g.end(), 0.0);
+      q.g[0] = q.beta;
+      q.k = 0;
+      q.stop = q.bad = false;
+    }
     for (int j = 0; j < m; ++j) {
-      double* vj = h->V + size_t(j) * n;
-      double* zj = h->Z + size_t(j) * n;
-      core_apply(h, vj, zj, s);
-      core_spmv(h, zj, nullptr, 1.0, h->w, s);
+      if (!range(true, &lo, &hi)) break;
+      const int nv = hi - lo;
+      const double* Vb = h->V + lo * n;                 // column 0 of right-hand side lo
+      double* Wb = W + lo * n;
+      core_apply(h, nv, h->V + (int64_t(j) * nr + lo) * n, h->Z + (int64_t(j) * nr + lo) * n, s);
+      core_spmv(h, nv, h->Z + (int64_t(j) * nr + lo) * n, nullptr, 1.0, Wb, s);
       {
         Timer tm(h, RSD_T_KRYLOV, s);
+        double* hd = h->hdev + lo * hs;
+        double* td = h->tmp + lo * hs;
         // classical Gram-Schmidt, twice
-        hip_check(h, launch_mdot(h->V, n, j + 1, h->w, n, h->part, h->hdev, 0, s), "cgs dots");
-        hip_check(h, launch_gemv_acc(h->V, n, j + 1, h->hdev, -1.0, h->w, n, s), "cgs update");
-        hip_check(h, launch_mdot(h->V, n, j + 1, h->w, n, h->part, h->tmp, 0, s), "cgs2 dots");
-        hip_check(h, launch_gemv_acc(h->V, n, j + 1, h->tmp, -1.0, h->w, n, s), "cgs2 update");
-        hip_check(h, launch_small_add(h->hdev, h->tmp, j + 1, s), "h add");
-        hip_check(h, launch_mdot(h->w, n, 1, h->w, n, h->part, h->hdev + j + 1, 1, s), "norm");
-        hip_check(h, launch_scale_div(h->w, h->hdev + j + 1, h->V + size_t(j + 1) * n, n, s),
+        hip_check(h, launch_mdot(nv, Vb, ldV, n, j + 1, Wb, n, n, h->part, hd, hs, 0, s),
+                  "cgs dots");
+        hip_check(h, launch_gemv_acc(nv, Vb, ldV, n, j + 1, hd, hs, -1.0, Wb, n, n, s),
+                  "cgs update");
+        hip_check(h, launch_mdot(nv, Vb, ldV, n, j + 1, Wb, n, n, h->part, td, hs, 0, s),
+                  "cgs2 dots");
+        hip_check(h, launch_gemv_acc(nv, Vb, ldV, n, j + 1, td, hs, -1.0, Wb, n, n, s),
+                  "cgs2 update");
+        hip_check(h, launch_small_add(nv, hd, hs, td, hs, j + 1, s), "h add");
+        hip_check(h, launch_mdot(nv, Wb, n, n, 1, Wb, n, n, h->part, hd + j + 1, hs, 1, s),
+                  "norm");
+        hip_check(h, launch_scale_div(nv, Wb, n, hd + j + 1, hs,
+                                      h->V + (int64_t(j + 1) * nr + lo) * n, n, n, s),
                   "normalise");
       }
-      hip_check(h, hipMemcpyAsync(h->hhost, h->hdev, sizeof(double) * size_t(j + 2),
+      hip_check(h, hipMemcpyAsync(h->hhost, h->hdev + lo * hs, sizeof(double) * size_t(nv * hs),
                                   hipMemcpyDeviceToHost, s), "h D2H");
       hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
-      double* hc = &H[size_t(j) * (m + 1)];
-      for (int i = 0; i <= j + 1; ++i) {
-        hc[i] = h->hhost[i];
-        if (!(hc[i] == hc[i]) || std::isinf(hc[i])) bad = true;
+      for (int i = lo; i < hi; ++i) {
+        Rhs& q = R[i];
+        if (q.done || q.stop) continue;
+        double* hc = &q.H[size_t(j) * (m + 1)];
+        const double* src = h->hhost + (i - lo) * hs;
+        for (int t = 0; t <= j + 1; ++t) {
+          hc[t] = src[t];
+          if (!(hc[t] == hc[t]) || std::isinf(hc[t])) q.bad = true;
+        }
+        if (q.bad) {
+          q.stop = true;
+          continue;
+        }
+        const double hnext = hc[j + 1];
+        for (int t = 0; t < j; ++t) {
+          const double t0 = q.cs[t] * hc[t] + q.sn[t] * hc[t + 1];
+          hc[t + 1] = -q.sn[t] * hc[t] + q.cs[t] * hc[t + 1];
+          hc[t] = t0;
+        }
+        const double den = std::hypot(hc[j], hc[j + 1]);
+        q.cs[j] = den > 0 ? hc[j] / den : 1.0;
+        q.sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
+        hc[j] = den;
+        hc[j + 1] = 0.0;
+        q.g[j + 1] = -q.sn[j] * q.g[j];
+        q.g[j] = q.cs[j] * q.g[j];
+        ++q.its;
+        q.k = j + 1;
+        if (std::fabs(q.g[j + 1]) <= q.tol || q.its >= o.maxit || hnext == 0.0) q.stop = true;
       }
-      if (bad) break;
-      const double hnext = hc[j + 1];
-      for (int i = 0; i < j; ++i) {
-        const double t0 = cs[i] * hc[i] + sn[i] * hc[i + 1];
-        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-        hc[i] = t0;
+    }
+    // x_i += Z_i y_i with y_i = R_i^{-1} g_i (upper triangular k x k)
+    bool any = false;
+    for (int i = 0; i < nr; ++i) {
+      Rhs& q = R[i];
+      if (q.done) continue;
+      if (q.bad) {
+        finish(i, RSD_ERR_BREAKDOWN, NAN);
+        continue;
       }
-      const double den = std::hypot(hc[j], hc[j + 1]);
-      cs[j] = den > 0 ? hc[j] / den : 1.0;
-      sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
-      hc[j] = den;
-      hc[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++its;
-      k = j + 1;
-      if (std::fabs(g[j + 1]) <= tol || its >= o.maxit || hnext == 0.0) break;
+      for (int t = q.k - 1; t >= 0; --t) {
+        double v = q.g[t];
+        for (int c = t + 1; c < q.k; ++c) v -= q.H[size_t(c) * (m + 1) + t] * q.y[c];
+        const double d = q.H[size_t(t) * (m + 1) + t];
+        q.y[t] = d != 0.0 ? v / d : 0.0;
+      }
+      for (int t = 0; t < q.k; ++t) h->hhost[i * hs + t] = q.y[t];
+      any = true;
     }
-    if (bad) {
-      info->iterations = its;
-      info->relres = NAN;
-      return RSD_ERR_BREAKDOWN;
-    }
-    // y = R^{-1} g (upper triangular k x k)
-    for (int i = k - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int c = i + 1; c < k; ++c) v -= H[size_t(c) * (m + 1) + i] * y[c];
-      const double d = H[size_t(i) * (m + 1) + i];
-      y[i] = d != 0.0 ? v / d : 0.0;
-    }
-    for (int i = 0; i < k; ++i) h->hhost[i] = y[i];
-    hip_check(h, hipMemcpyAsync(h->tmp, h->hhost, sizeof(double) * size_t(k),
+    if (!any) return;
+    hip_check(h, hipMemcpyAsync(h->tmp, h->hhost, sizeof(double) * size_t(nr * hs),
                                 hipMemcpyHostToDevice, s), "y H2D");
     {
       Timer tm(h, RSD_T_KRYLOV, s);
-      hip_check(h, launch_gemv_acc(h->Z, n, k, h->tmp, 1.0, x, n, s), "x update");
+      for (int i = 0; i < nr; ++i)
+        if (!R[i].done)
+          hip_check(h, launch_gemv_acc(1, h->Z + i * n, ldV, 0, R[i].k, h->tmp + i * hs, 0, 1.0,
+                                       x + i * n, 0, n, s), "x update");
     }
-    core_spmv(h, x, b, -1.0, r, s);
-    beta = dev_norm(h, r, beta_d, s);
+    residuals();
   }
 }
 
@@ -820,7 +929,7 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
     return RSD_OK;
   }
   const double tol = o.rtol * bnorm;
-  core_spmv(h, x, b, -1.0, r, s);
+  core_spmv(h, 1, x, b, -1.0, r, s);
   double rn = dev_norm(h, r, h->scal + 3, s);
   int its = 0;
   int cur = 0;
@@ -829,21 +938,21 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
     info->relres = rn / bnorm;
     return RSD_OK;
   }
-  core_apply(h, r, z, s);
+  core_apply(h, 1, r, z, s);
   {
     Timer tm(h, RSD_T_KRYLOV, s);
-    hip_check(h, launch_mdot(r, n, 1, z, n, h->part, h->scal + cur, 0, s), "rz");
+    hip_check(h, launch_mdot(1, r, n, 0, 1, z, 0, n, h->part, h->scal + cur, 0, 0, s), "rz");
     hip_check(h, hipMemcpyAsync(p, z, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, s),
               "p = z");
   }
   for (;;) {
-    core_spmv(h, p, nullptr, 1.0, q, s);
+    core_spmv(h, 1, p, nullptr, 1.0, q, s);
     {
       Timer tm(h, RSD_T_KRYLOV, s);
-      hip_check(h, launch_mdot(p, n, 1, q, n, h->part, h->scal + 2, 0, s), "pq");
+      hip_check(h, launch_mdot(1, p, n, 0, 1, q, 0, n, h->part, h->scal + 2, 0, 0, s), "pq");
       hip_check(h, launch_axpy_ratio(x, p, h->scal + cur, h->scal + 2, 1.0, x, n, s), "x");
       hip_check(h, launch_axpy_ratio(r, q, h->scal + cur, h->scal + 2, -1.0, r, n, s), "r");
-      hip_check(h, launch_mdot(r, n, 1, r, n, h->part, h->scal + 3, 1, s), "|r|");
+      hip_check(h, launch_mdot(1, r, n, 0, 1, r, 0, n, h->part, h->scal + 3, 0, 1, s), "|r|");
     }
     hip_check(h, hipMemcpyAsync(h->hhost, h->scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s),
               "D2H");
@@ -857,7 +966,7 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
       return RSD_ERR_BREAKDOWN;
     }
     if (rn <= tol) {
-      core_spmv(h, x, b, -1.0, r, s);
+      core_spmv(h, 1, x, b, -1.0, r, s);
       const double rt = dev_norm(h, r, h->scal + 3, s);
       if (rt <= tol) {
         info->iterations = its;
@@ -866,16 +975,16 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
       }
     }
     if (its >= o.maxit) {
-      core_spmv(h, x, b, -1.0, h->w, s);
+      core_spmv(h, 1, x, b, -1.0, h->w, s);
       info->iterations = its;
       info->relres = dev_norm(h, h->w, h->scal + 5, s) / bnorm;
       return RSD_ERR_NOT_CONVERGED;
     }
-    core_apply(h, r, z, s);
+    core_apply(h, 1, r, z, s);
     {
       Timer tm(h, RSD_T_KRYLOV, s);
       const int nxt = 1 - cur;
-      hip_check(h, launch_mdot(r, n, 1, z, n, h->part, h->scal + nxt, 0, s), "rz");
+      hip_check(h, launch_mdot(1, r, n, 0, 1, z, 0, n, h->part, h->scal + nxt, 0, 0, s), "rz");
       hip_check(h, launch_axpy_ratio(z, p, h->scal + nxt, h->scal + cur, 1.0, p, n, s), "p");
       cur = nxt;
     }
@@ -887,10 +996,13 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
 rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, double* z,
                         int64_t ldz, hipStream_t s) {
   try {
-    for (int j = 0; j < nrhs; ++j) {
-      permute(h, r + size_t(j) * ldr, h->P.n, h->rin, h->P.n, 0, s);
-      core_apply(h, h->rin, h->zin, s);
-      permute(h, h->zin, h->P.n, z + size_t(j) * ldz, h->P.n, 1, s);
+    const int64_t n = h->P.n;
+    for (int j0 = 0; j0 < nrhs; j0 += kRhsGroup) {
+      const int c = std::min(kRhsGroup, nrhs - j0);
+      ensure_vectors(h, c);
+      permute(h, c, r + size_t(j0) * ldr, ldr, h->rin, n, 0, s);
+      core_apply(h, c, h->rin, h->zin, s);
+      permute(h, c, h->zin, n, z + size_t(j0) * ldz, ldz, 1, s);
     }
     return RSD_OK;
   } catch (const Fail& f) {
@@ -901,10 +1013,13 @@ rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, doub
 rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, double* y,
                        int64_t ldy, hipStream_t s) {
   try {
-    for (int j = 0; j < nrhs; ++j) {
-      permute(h, x + size_t(j) * ldx, h->P.n, h->rin, h->P.n, 0, s);
-      core_spmv(h, h->rin, nullptr, 1.0, h->zin, s);
-      permute(h, h->zin, h->P.n, y + size_t(j) * ldy, h->P.n, 1, s);
+    const int64_t n = h->P.n;
+    for (int j0 = 0; j0 < nrhs; j0 += kRhsGroup) {
+      const int c = std::min(kRhsGroup, nrhs - j0);
+      ensure_vectors(h, c);
+      permute(h, c, x + size_t(j0) * ldx, ldx, h->rin, n, 0, s);
+      core_spmv(h, c, h->rin, nullptr, 1.0, h->zin, s);
+      permute(h, c, h->zin, n, y + size_t(j0) * ldy, ldy, 1, s);
     }
     return RSD_OK;
   } catch (const Fail& f) {
@@ -927,21 +1042,30 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
       o.rtol = 1e-10;
       o.use_x0 = 0;
     }
-    ensure_krylov(h, o.method == RSD_SOLVER_PCG ? 4 : o.restart);
+    const bool pcg = o.method == RSD_SOLVER_PCG;
+    const int group = pcg ? 1 : std::min(kRhsGroup, std::max(nrhs, 1));
+    ensure_krylov(h, pcg ? 4 : o.restart, group);
+    ensure_vectors(h, group);
+    const int64_t n = h->P.n;
     rsd_status worst = RSD_OK;
-    for (int j = 0; j < nrhs; ++j) {
-      rsd_solve_info inf{0, 0.0, RSD_OK};
-      permute(h, b + size_t(j) * ldb, h->P.n, h->bint, h->P.n, 0, s);
+    std::vector<rsd_solve_info> inf(static_cast<size_t>(group));
+    for (int j0 = 0; j0 < nrhs; j0 += group) {
+      const int c = std::min(group, nrhs - j0);
+      permute(h, c, b + size_t(j0) * ldb, ldb, h->bint, n, 0, s);
       if (o.use_x0)
-        permute(h, x + size_t(j) * ldx, h->P.n, h->xint, h->P.n, 0, s);
+        permute(h, c, x + size_t(j0) * ldx, ldx, h->xint, n, 0, s);
       else
-        hip_check(h, launch_fill(h->xint, h->P.n, 0.0, s), "x0");
-      const rsd_status st = o.method == RSD_SOLVER_PCG ? pcg_one(h, h->bint, h->xint, o, &inf, s)
-                                                       : fgmres_one(h, h->bint, h->xint, o, &inf, s);
-      permute(h, h->xint, h->P.n, x + size_t(j) * ldx, h->P.n, 1, s);
-      inf.status = st;
-      if (info) info[j] = inf;
-      if (st == RSD_ERR_BREAKDOWN || (st != RSD_OK && worst == RSD_OK)) worst = st;
+        hip_check(h, launch_fill(h->xint, n * c, 0.0, s), "x0");
+      if (pcg)
+        inf[0].status = pcg_one(h, h->bint, h->xint, o, &inf[0], s);
+      else
+        fgmres_group(h, c, h->bint, h->xint, o, inf.data(), s);
+      permute(h, c, h->xint, n, x + size_t(j0) * ldx, ldx, 1, s);
+      for (int k = 0; k < c; ++k) {
+        const rsd_status st = static_cast<rsd_status>(inf[k].status);
+        if (info) info[j0 + k] = inf[k];
+        if (st == RSD_ERR_BREAKDOWN || (st != RSD_OK && worst == RSD_OK)) worst = st;
+      }
     }
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     if (worst == RSD_ERR_NOT_CONVERGED) h->err = "Krylov iteration reached maxit";

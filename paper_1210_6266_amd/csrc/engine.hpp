@@ -54,11 +54,13 @@ struct rsd_ctx {
   int group = 0;             // pivot tiles per sweep step (0: by batch size)
 
   // apply work vectors (internal order)
-  double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;
+  double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;   // nvec vectors each
+  double* xil = nullptr;     // n * kEllVec: interleaved SpMV operand (null while nvec == 1)
+  int nvec = 0;
   double* sympart = nullptr;                // partial sums of the symmetric products
 
   // Krylov work space (grown on demand)
-  int kry_m = 0;
+  int kry_m = 0, kry_nr = 0;   // restart length, right-hand sides in lockstep
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hdev = nullptr, *tmp = nullptr,
          *part = nullptr, *scal = nullptr, *bint = nullptr, *xint = nullptr;
   double* hhost = nullptr;   // pinned (hhost_block)

@@ -170,14 +170,37 @@ __global__ __launch_bounds__(kEllSlice) void k_ell_fill(int64_t n, const int64_t
     }
 }
 
-// y[r] = (base ? base[r] : 0) + alpha * sum over the entries of row r with CSR positions
-// in [s0[r], s1[r]) (contiguous: columns are sorted), rows r in [row0, row0 + nrows)
+// xil[i KV + k] = x_k[i] (k < nv), 0 for nv <= k < KV: the vectors of a column side by
+// side, so that one lane's gather for all of them is KV contiguous doubles.
+template <int KV>
+__global__ __launch_bounds__(kBlock) void k_interleave(const double* __restrict__ x, int nv,
+                                                       int64_t ld, int64_t ncols,
+                                                       double* __restrict__ xil) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= ncols) return;
+  typedef double D2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int k = 0; k < KV; k += 2) {
+    D2 v;
+    v.x = k < nv ? x[k * ld + i] : 0.0;
+    v.y = k + 1 < nv ? x[(k + 1) * ld + i] : 0.0;
+    *(D2*)(xil + i * KV + k) = v;
+  }
+}
+
+// y_k[r] = (base ? base_k[r] : 0) + alpha * sum over the entries of row r with CSR
+// positions in [s0[r], s1[r]) (contiguous: columns are sorted), rows r in
+// [row0, row0 + nrows), for the nv <= KV vectors x_k = x + k ld (likewise base, y).
+// The slots are read once for all vectors; with IL the gathers read the interleaved
+// copy xil of x.  Each vector's sum has the same order whatever KV is.  x, base and y
+// may be the same vectors when the columns read are not the rows written.
+template <int KV, bool IL>
 __global__ __launch_bounds__(kBlock) void k_ell_spmv(
     int64_t row0, int64_t nrows, const int64_t* __restrict__ s0, const int64_t* __restrict__ s1,
     const int64_t* __restrict__ prow, const int64_t* __restrict__ ell_off,
     const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val,
-    const double* __restrict__ x, const double* __restrict__ base, double alpha,
-    double* __restrict__ y) {
+    const double* x, const double* __restrict__ xil, const double* base, double alpha,
+    double* y, int nv, int64_t ld) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= nrows) return;
   const int64_t r = row0 + i;
@@ -188,7 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_ell_spmv(
   const double* v = ell_val + o;
   // eight slots at a time: their column and value loads are independent, then the
   // eight gathers of x; out-of-range slots read slot k0 with a zero weight
-  double acc = 0.0;
+  double acc[KV];
+#pragma unroll
+  for (int k = 0; k < KV; ++k) acc[k] = 0.0;
   for (int64_t kb = k0; kb < k1; kb += 8) {
     int32_t ci[8];
     double vi[8];
@@ -198,10 +223,29 @@ __global__ __launch_bounds__(kBlock) void k_ell_spmv(
       ci[u] = c[kk * kEllSlice];
       vi[u] = kb + u < k1 ? v[kk * kEllSlice] : 0.0;
     }
+    if constexpr (IL) {
+      typedef double D2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += vi[u] * x[ci[u]];
+      for (int u = 0; u < 8; ++u) {
+        const D2* xp = (const D2*)(xil + int64_t(ci[u]) * KV);
+#pragma unroll
+        for (int k = 0; k < KV; k += 2) {
+          const D2 xv = xp[k / 2];
+          acc[k] += vi[u] * xv.x;
+          acc[k + 1] += vi[u] * xv.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int k = 0; k < KV; ++k)
+          if (KV == 1 || k < nv) acc[k] += vi[u] * x[k * ld + ci[u]];
+    }
   }
-  y[r] = (base ? base[r] : 0.0) + alpha * acc;
+#pragma unroll
+  for (int k = 0; k < KV; ++k)
+    if (KV == 1 || k < nv) y[k * ld + r] = (base ? base[k * ld + r] : 0.0) + alpha * acc[k];
 }
 
 // Row r of K in internal order: row perm[r] of the caller's CSR with columns renamed by
@@ -1058,32 +1102,40 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 
 // ---- symmetric products y = base + alpha A x -------------------------------------------
 // Work item = a kSymB x kSymB block of tiles (block row BI, block column BJ <= BI) of
-// one matrix.  Phase 1 streams the block's lower tiles once and keeps, per tile row I
-// of the block, the row part sum_J A_IJ x_J (the full diagonal tile included) and, per
-// tile column J, the column part sum_{I > J} A_IJ^T x_J in registers; they are reduced
-// and written once per item (P = float for FP32 factors, as accurate as the factor).
+// one matrix.  Phase 1 streams the block's lower tiles once, row by row of tiles.  The
+// row part sum_J A_IJ x_J of tile row I (the full diagonal tile included) is folded
+// across the wave and parked in LDS when its row is done.  The column parts
+// sum_{I > J} A_IJ^T x_I of the block's tile columns either stay in registers until
+// the end of the item (FP32 tiles), or (FP64 tiles, whose 16-byte loads hold half as
+// many entries) are folded across the row lanes after every tile and added into LDS
+// by the one lane that owns the column, which frees the registers for four vectors
+// per pass.  P = float for FP32 factors, as accurate as the factor.
 // Phase 2 adds, for every tile row, the row parts of its block row and the column parts
-// of its block column, in a fixed order.  No atomics: results are reproducible.
-template <typename P>
-__device__ __forceinline__ void xor_fold(P* a, int n, int lane, int o) {
-  // trade half of a[0..n) with the lane `lane ^ o`; the lane with bit o set keeps the
+// of its block column, in a fixed order.  No atomics: results are reproducible.  With
+// several vectors (KV per launch, x_k = x + k ld) the tiles are read once for all of
+// them; each vector's sums have the same order whatever KV is.
+template <int N, typename P>
+__device__ __forceinline__ void xor_fold(P* a, int lane, int o) {
+  // trade half of a[0..N) with the lane `lane ^ o`; the lane with bit o set keeps the
   // upper half, so after folds over bits b1 > b2 > ... a lane holds the block of
-  // entries selected by its own bits
+  // entries selected by its own bits (N is a constant so that a[] stays in registers)
   const bool up = (lane & o) != 0;
-  for (int j = 0; j < n / 2; ++j) {
-    const P give = up ? a[j] : a[j + n / 2];
-    const P keep = up ? a[j + n / 2] : a[j];
+#pragma unroll
+  for (int j = 0; j < N / 2; ++j) {
+    const P give = up ? a[j] : a[j + N / 2];
+    const P keep = up ? a[j + N / 2] : a[j];
     a[j] = keep + __shfl_xor(give, o, 64);
   }
 }
 
-template <typename T>
+template <typename T, int KV>
 __global__ __launch_bounds__(kBlock) void k_symv1(
     const T* __restrict__ tiles, const int64_t* __restrict__ tile_off,
     const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
     const int64_t* __restrict__ vec_off, const int32_t* __restrict__ item_mat,
     const int32_t* __restrict__ item_BI, const int32_t* __restrict__ item_BJ,
-    const double* __restrict__ x, typename SymPart<T>::type* __restrict__ part) {
+    const double* __restrict__ x, int64_t ldx, int nv,
+    typename SymPart<T>::type* __restrict__ part) {
   using P = typename SymPart<T>::type;
   constexpr int B = kSymB;
   constexpr int VEC = 16 / int(sizeof(T));     // elements per 16-byte load
@@ -1098,74 +1150,113 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
   // 33 + 2q (two loads per column, each contiguous over 16 lanes)
   const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
   auto q4 = [&](int v) { return sizeof(T) == 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
-  __shared__ double xs[2][B][TS];
-  __shared__ P red[4][B][TS];
-  for (int e = t; e < 2 * B * TS; e += kBlock) {
-    const int sd = e / (B * TS), b = (e / TS) % B, r = e % TS;
+  constexpr bool kColLds = sizeof(T) == 8;
+  __shared__ double xs[KV][2][B][TS];
+  __shared__ P red[KV][4][B][TS];
+  __shared__ P colr[kColLds ? KV : 1][B][TS];
+  for (int e = t; e < KV * 2 * B * TS; e += kBlock) {
+    const int k = e / (2 * B * TS), sd = (e / (B * TS)) % 2, b = (e / TS) % B, r = e % TS;
     const int idx = ((sd == 0 ? BI : BJ) * B + b) * TS + r;
-    xs[sd][b][r] = idx < n ? x[xo + idx] : 0.0;
+    xs[k][sd][b][r] = idx < n && k < nv ? x[k * ldx + xo + idx] : 0.0;
   }
+  if (kColLds)
+    for (int e = t; e < KV * B * TS; e += kBlock) (&colr[0][0][0])[e] = P(0);
   __syncthreads();
-  P racc[B * 4], cacc[B * 4];                  // [block row b][row v], [block column b][column u]
+  P cacc[kColLds ? 1 : KV][B * 4];             // [vector][block column b][column u]
 #pragma unroll
-  for (int i = 0; i < B * 4; ++i) {
-    racc[i] = P(0);
-    cacc[i] = P(0);
-  }
+  for (int k = 0; k < (kColLds ? 1 : KV); ++k)
+#pragma unroll
+    for (int i = 0; i < B * 4; ++i) cacc[k][i] = P(0);
+  const int usel = (q >> 2) & 3;               // LDS columns: column g + 16 usel after the fold
   const T* base = tiles + tile_off[m] + q4(0) + g * TS;
 #pragma unroll
   for (int bi = 0; bi < B; ++bi) {
     const int I = BI * B + bi;
-    if (I >= nt) break;
-    P xi[4];
+    P ra[KV][4];                               // row part of tile row I, rows q4(v)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) xi[v] = P(xs[0][bi][q4(v)]);
+    for (int k = 0; k < KV; ++k)
 #pragma unroll
-    for (int bj = 0; bj < B; ++bj) {
-      const int J = BJ * B + bj;
-      if (J > I) break;
-      const T* tl = base + tile_index(I, J) * TT;
-      V a[4][LPC];
+      for (int v = 0; v < 4; ++v) ra[k][v] = P(0);
+    if (I < nt) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int bj = 0; bj < B; ++bj) {
+        const int J = BJ * B + bj;
+        if (J > I) break;
+        const T* tl = base + tile_index(I, J) * TT;
+        V a[4][LPC];
 #pragma unroll
-        for (int h = 0; h < LPC; ++h) a[u][h] = *(const V*)(tl + 16 * u * TS + 32 * h);
-      P rf[4] = {P(0), P(0), P(0), P(0)};
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const P xk = P(xs[1][bj][g + 16 * u]);
-        P cf = P(0);
+          for (int h = 0; h < LPC; ++h) a[u][h] = *(const V*)(tl + 16 * u * TS + 32 * h);
+        P cf[KV][4];                           // column parts of this tile, columns g + 16 u
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const P av = P(a[u][v / VEC][v % VEC]);
-          cf = fma(av, xi[v], cf);
-          rf[v] = fma(av, xk, rf[v]);
+        for (int u = 0; u < 4; ++u) {
+          P xk[KV];
+#pragma unroll
+          for (int k = 0; k < KV; ++k) {
+            xk[k] = P(xs[k][1][bj][g + 16 * u]);
+            cf[k][u] = P(0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const P av = P(a[u][v / VEC][v % VEC]);
+#pragma unroll
+            for (int k = 0; k < KV; ++k) {   // x_I is read from LDS: fewer live registers
+              cf[k][u] = fma(av, P(xs[k][0][bi][q4(v)]), cf[k][u]);
+              ra[k][v] = fma(av, xk[k], ra[k][v]);
+            }
+          }
+          if (!kColLds && J < I)
+#pragma unroll
+            for (int k = 0; k < KV; ++k) cacc[kColLds ? 0 : k][bj * 4 + u] += cf[k][u];
         }
-        if (J < I) cacc[bj * 4 + u] += cf;
-      }
+        if (J < I) {
+          if constexpr (kColLds) {
+            // fold over the 16 row lanes (bits 3..0): lanes q with q % 4 == 0 then hold
+            // column g + 16 usel of this tile, which only they update
 #pragma unroll
-      for (int v = 0; v < 4; ++v) racc[bi * 4 + v] += rf[v];
+            for (int k = 0; k < KV; ++k) {
+              xor_fold<4>(cf[k], lane, 8);
+              xor_fold<2>(cf[k], lane, 4);
+              P c = cf[k][0];
+              c += __shfl_xor(c, 2, 64);
+              c += __shfl_xor(c, 1, 64);
+              if ((q & 3) == 0) colr[k][bj][g + 16 * usel] += c;
+            }
+          }
+        }
+      }
+    }
+    // fold over the wave's four column groups (lane bits 5, 4): lane (q, g) then holds
+    // row q4(g % 4) of tile row I; the four waves are summed in LDS at the end
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+      xor_fold<4>(ra[k], lane, 32);
+      xor_fold<2>(ra[k], lane, 16);
+      red[k][w][bi][q4(g & 3)] = ra[k][0];
     }
   }
-  // rows: fold over the wave's four column groups (lane bits 5, 4); lane (q, g) then
-  // holds block row g % 4, rows q4(0..3); the four waves are summed in LDS
-  xor_fold(racc, B * 4, lane, 32);
-  xor_fold(racc, B * 2, lane, 16);
+  // part of item it, side sd (0 rows, 1 columns), vector k
+  auto partp = [&](int sd, int k) { return part + ((int64_t(2 * it + sd) * KV + k) * B) * TS; };
+  if constexpr (!kColLds) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) red[w][g & 3][q4(v)] = racc[v];
-  // columns: fold over the 16 row lanes (bits 3..0); lane q holds block column q / 4,
-  // column g + 16 (q % 4), summed over the block's rows -- written directly
-  xor_fold(cacc, B * 4, lane, 8);
-  xor_fold(cacc, B * 2, lane, 4);
-  xor_fold(cacc, B, lane, 2);
-  xor_fold(cacc, B / 2, lane, 1);
-  P* rowp = part + int64_t(2 * it) * B * TS;
-  P* colp = rowp + B * TS;
-  colp[(q >> 2) * TS + g + 16 * (q & 3)] = cacc[0];
+    for (int k = 0; k < KV; ++k) {
+      // columns: fold over the 16 row lanes (bits 3..0); lane q holds block column q / 4,
+      // column g + 16 (q % 4), summed over the block's rows -- written directly
+      xor_fold<B * 4>(cacc[k], lane, 8);
+      xor_fold<B * 2>(cacc[k], lane, 4);
+      xor_fold<B>(cacc[k], lane, 2);
+      xor_fold<B / 2>(cacc[k], lane, 1);
+      if (k < nv) partp(1, k)[(q >> 2) * TS + g + 16 * (q & 3)] = cacc[k][0];
+    }
+  }
   __syncthreads();
-  for (int e = t; e < B * TS; e += kBlock) {
-    const int b = e / TS, r = e % TS;
-    rowp[e] = (red[0][b][r] + red[1][b][r]) + (red[2][b][r] + red[3][b][r]);
+  for (int e = t; e < KV * B * TS; e += kBlock) {
+    const int k = e / (B * TS), b = (e / TS) % B, r = e % TS;
+    if (k < nv) {
+      partp(0, k)[b * TS + r] = (red[k][0][b][r] + red[k][1][b][r]) + (red[k][2][b][r] + red[k][3][b][r]);
+      if constexpr (kColLds) partp(1, k)[b * TS + r] = colr[k][b][r];
+    }
   }
 }
 
@@ -1173,25 +1264,27 @@ template <typename P>
 __global__ __launch_bounds__(kBlock) void k_symv2(
     const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
     const int64_t* __restrict__ vec_off, const int64_t* __restrict__ item_base,
-    const P* __restrict__ part, double alpha, const double* __restrict__ base,
-    double* __restrict__ y) {
+    const P* __restrict__ part, int kv, double alpha, const double* __restrict__ base,
+    double* __restrict__ y, int64_t ld) {
+  // block (tile row I, matrix m, vector k); the parts of phase 1 hold kv vectors
   constexpr int B = kSymB;
-  const int m = blockIdx.y, I = blockIdx.x, r = threadIdx.x & 63, prt = threadIdx.x >> 6;
+  const int m = blockIdx.y, I = blockIdx.x, k = blockIdx.z, r = threadIdx.x & 63,
+            prt = threadIdx.x >> 6;
   const int nt = nt_arr[m];
   if (I >= nt) return;
   const int nb = (nt + B - 1) / B, BI = I / B, b = I % B;
   const int64_t ib = item_base[m];
   double s = 0.0;
   for (int BJ = prt; BJ <= BI; BJ += 4)        // row parts of block row BI
-    s += double(part[(2 * (ib + tri(BI) + BJ) * B + b) * TS + r]);
+    s += double(part[((2 * (ib + tri(BI) + BJ) * kv + k) * B + b) * TS + r]);
   for (int B2 = BI + prt; B2 < nb; B2 += 4)    // column parts of block column BI
-    s += double(part[((2 * (ib + tri(B2) + BI) + 1) * B + b) * TS + r]);
+    s += double(part[(((2 * (ib + tri(B2) + BI) + 1) * kv + k) * B + b) * TS + r]);
   __shared__ double red[4][TS];
   red[prt][r] = s;
   __syncthreads();
   const int row = I * TS + r;
   if (prt == 0 && row < n_arr[m]) {
-    const int64_t o = vec_off[m] + row;
+    const int64_t o = k * ld + vec_off[m] + row;
     const double v = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
     y[o] = (base ? base[o] : 0.0) + alpha * v;
   }
@@ -1307,32 +1400,39 @@ __global__ __launch_bounds__(kBlock) void k_schur_assemble(
 }
 
 // ================================================================ apply helpers
-template <typename S>
+template <typename S, int KV>
 __global__ __launch_bounds__(kBlock) void k_sigma_level(
     const int32_t* __restrict__ it_leaf, const int32_t* __restrict__ it_r0,
     const int32_t* __restrict__ it_a0, const int32_t* __restrict__ it_a1,
     const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
     const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
-    const double* __restrict__ z, double* __restrict__ e) {
-  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= kSigRows).
-  // Sigma_l is symmetric: row a is read as column a (contiguous in b), one wave per
-  // row, the gathered u staged in LDS; each row's sum is taken in a fixed order.
+    const double* __restrict__ z, double* __restrict__ e, int nv, int64_t ldz, int64_t lde) {
+  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= kSigRows),
+  // for nv <= KV vectors (u_k = z + k ldz, e_k = e + k lde).  Sigma_l is symmetric: row
+  // a is read as column a (contiguous in b), one wave per row, the gathered u staged in
+  // LDS; each row's sum is taken in a fixed order that does not depend on KV.
   const int it = blockIdx.x;
   const int l = it_leaf[it], r0 = it_r0[it], a0 = it_a0[it], a1 = it_a1[it];
   const int64_t m = B_off[l + 1] - B_off[l];
   const S* Sg = sigma + sig_off[l];
   const int32_t* Bl = B + B_off[l];
-  constexpr int kSigStage = 2048;              // u values staged per pass (16 KB)
-  __shared__ double ub[kSigStage];
+  constexpr int kSigStage = 1024;              // u values staged per pass and vector (8 KB)
+  __shared__ double ub[KV][kSigStage];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int RW = kSigRows / 4;             // rows per wave
-  double acc[RW];
+  double acc[RW][KV];
 #pragma unroll
-  for (int q = 0; q < RW; ++q) acc[q] = 0.0;
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int k = 0; k < KV; ++k) acc[q][k] = 0.0;
   for (int b0 = 0; b0 < r0; b0 += kSigStage) {
     const int nb = min(kSigStage, r0 - b0);
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kBlock) ub[b] = z[Bl[b0 + b]];
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+      const int32_t gi = Bl[b0 + b];
+#pragma unroll
+      for (int k = 0; k < KV; ++k) ub[k][b] = k < nv ? z[k * ldz + gi] : 0.0;
+    }
     __syncthreads();
     const S* col[RW];
 #pragma unroll
@@ -1342,40 +1442,51 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     }
     int b = lane;
     for (; b + 64 < nb; b += 128) {
-      const double u0 = ub[b], u1 = ub[b + 64];
 #pragma unroll
-      for (int q = 0; q < RW; ++q) acc[q] += double(col[q][b]) * u0 + double(col[q][b + 64]) * u1;
+      for (int q = 0; q < RW; ++q) {
+        const double s0 = double(col[q][b]), s1 = double(col[q][b + 64]);
+#pragma unroll
+        for (int k = 0; k < KV; ++k) acc[q][k] += s0 * ub[k][b] + s1 * ub[k][b + 64];
+      }
     }
     if (b < nb) {
-      const double u0 = ub[b];
 #pragma unroll
-      for (int q = 0; q < RW; ++q) acc[q] += double(col[q][b]) * u0;
+      for (int q = 0; q < RW; ++q) {
+        const double s0 = double(col[q][b]);
+#pragma unroll
+        for (int k = 0; k < KV; ++k) acc[q][k] += s0 * ub[k][b];
+      }
     }
   }
 #pragma unroll
-  for (int q = 0; q < RW; ++q) {
-    double v = acc[q];
+  for (int q = 0; q < RW; ++q)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int a = a0 + w * RW + q;
-    if (lane == 0 && a < a1) e[B_off[l] + a] = v;
-  }
+    for (int k = 0; k < KV; ++k) {
+      double v = acc[q][k];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      const int a = a0 + w * RW + q;
+      if (lane == 0 && a < a1 && k < nv) e[k * lde + B_off[l] + a] = v;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_level_rhs(
-    int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* __restrict__ pcol,
-    const double* __restrict__ pval, const int64_t* __restrict__ segA,
-    const int64_t* __restrict__ segB, const int64_t* __restrict__ adj_ptr,
+// z_v[r] += sum over the leaves l adjacent to interface dof r of e_l[position of r in
+// B_l], rows r in [row0, row0 + nrows), for nv vectors (z_v = z + v ldz, e_v = e + v lde)
+__global__ __launch_bounds__(kBlock) void k_level_adj(
+    int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* __restrict__ adj_ptr,
     const int32_t* __restrict__ adj_leaf, const int32_t* __restrict__ adj_pos,
-    const int64_t* __restrict__ B_off, const double* __restrict__ e, double* z) {
+    const int64_t* __restrict__ B_off, const double* __restrict__ e, double* __restrict__ z,
+    int nv, int64_t ldz, int64_t lde) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= nrows) return;
   const int64_t r = row0 + i;
-  double s = z[r];
-  for (int64_t k = segA[r]; k < segB[r]; ++k) s -= pval[k] * z[pcol[k]];
   const int64_t p = r - n_leaf;
-  for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += e[B_off[adj_leaf[k]] + adj_pos[k]];
-  z[r] = s;
+  for (int v = 0; v < nv; ++v) {
+    const double* ev = e + v * lde;
+    double s = z[v * ldz + r];
+    for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += ev[B_off[adj_leaf[k]] + adj_pos[k]];
+    z[v * ldz + r] = s;
+  }
 }
 
 // ================================================================ Krylov
@@ -1392,11 +1503,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// The Krylov kernels below act on a batch of right-hand sides, one per grid row
+// (blockIdx.y): operand i is the base pointer plus i times its batch stride.
 __global__ __launch_bounds__(kBlock) void k_mdot_partial(const double* __restrict__ V,
-                                                         int64_t ldv, int ncols,
+                                                         int64_t ldv, int64_t sV, int ncols,
                                                          const double* __restrict__ w,
-                                                         int64_t n, double* __restrict__ part) {
+                                                         int64_t sw, int64_t n,
+                                                         double* __restrict__ part) {
   __shared__ double sh[4];
+  V += blockIdx.y * sV;
+  w += blockIdx.y * sw;
+  part += int64_t(blockIdx.y) * gridDim.x * ncols;
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int64_t hi = min(n, lo + chunk);
@@ -1421,9 +1538,12 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(const double* __restric
 
 __global__ __launch_bounds__(kBlock) void k_mdot_final(const double* __restrict__ part,
                                                        int nblocks, int ncols,
-                                                       double* __restrict__ out, int mode) {
+                                                       double* __restrict__ out, int64_t so,
+                                                       int mode) {
   __shared__ double sh[4];
   const int c = blockIdx.x;
+  part += int64_t(blockIdx.y) * nblocks * ncols;
+  out += blockIdx.y * so;
   double v = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += kBlock) v += part[int64_t(b) * ncols + c];
   const double t = block_sum(v, sh);
@@ -1431,27 +1551,34 @@ __global__ __launch_bounds__(kBlock) void k_mdot_final(const double* __restrict_
 }
 
 __global__ __launch_bounds__(kBlock) void k_gemv_acc(const double* __restrict__ V, int64_t ldv,
-                                                     int ncols, const double* __restrict__ h,
+                                                     int64_t sV, int ncols,
+                                                     const double* __restrict__ h, int64_t sh,
                                                      double sign, double* __restrict__ w,
-                                                     int64_t n) {
+                                                     int64_t sw, int64_t n) {
   const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (r >= n) return;
+  V += blockIdx.y * sV;
+  h += blockIdx.y * sh;
+  w += blockIdx.y * sw;
   double s = 0.0;
   for (int c = 0; c < ncols; ++c) s += V[r + c * ldv] * h[c];
   w[r] += sign * s;
 }
 
-__global__ void k_scale_div(const double* __restrict__ x, const double* __restrict__ d,
-                            double* __restrict__ y, int64_t n) {
+__global__ void k_scale_div(const double* __restrict__ x, int64_t sx,
+                            const double* __restrict__ d, int64_t sd, double* __restrict__ y,
+                            int64_t sy, int64_t n) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const double dv = d[0];
+  x += blockIdx.y * sx;
+  y += blockIdx.y * sy;
+  const double dv = d[blockIdx.y * sd];
   y[r] = dv != 0.0 ? x[r] / dv : 0.0;
 }
 
-__global__ void k_small_add(double* a, const double* b, int k) {
+__global__ void k_small_add(double* a, int64_t sa, const double* b, int64_t sb, int k) {
   const int i = threadIdx.x;
-  if (i < k) a[i] += b[i];
+  if (i < k) a[blockIdx.y * sa + i] += b[blockIdx.y * sb + i];
 }
 
 __global__ void k_axpy_ratio(const double* __restrict__ x, const double* __restrict__ z,
@@ -1496,10 +1623,39 @@ hipError_t launch_ell_fill(int64_t n, const int64_t* prow, const int32_t* pcol,
 hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
                            const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
                            const double* ell_val, const double* x, const double* base,
-                           double alpha, double* y, hipStream_t s) {
-  if (nrows <= 0) return hipSuccess;
-  k_ell_spmv<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, s0, s1, prow, ell_off, ell_col,
-                                                 ell_val, x, base, alpha, y);
+                           double alpha, double* y, int nv, int64_t ld, double* xil,
+                           int64_t ncols, hipStream_t s) {
+  if (nrows <= 0 || nv <= 0) return hipSuccess;
+  for (int v0 = 0; v0 < nv; v0 += kEllVec) {
+    const int c = nv - v0 < kEllVec ? nv - v0 : kEllVec;
+    const int kv = c == 1 ? 1 : c == 2 ? 2 : c <= 4 ? 4 : 8;
+    const double* xb = x + v0 * ld;
+    const double* bb = base ? base + v0 * ld : nullptr;
+    double* yb = y + v0 * ld;
+    const bool il = kv > 1 && xil != nullptr;
+#define RSD_ELL(KV, IL)                                                                        \
+  k_ell_spmv<KV, IL><<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, s0, s1, prow, ell_off, \
+                                                          ell_col, ell_val, xb, xil, bb, alpha, \
+                                                          yb, c, ld)
+#define RSD_IL(KV) \
+  k_interleave<KV><<<blocks_for(ncols), kBlock, 0, s>>>(xb, c, ld, ncols, xil)
+    if (kv == 1) {
+      RSD_ELL(1, false);
+    } else if (!il) {
+      if (kv == 2) RSD_ELL(2, false); else if (kv == 4) RSD_ELL(4, false); else RSD_ELL(8, false);
+    } else if (kv == 2) {
+      RSD_IL(2);
+      RSD_ELL(2, true);
+    } else if (kv == 4) {
+      RSD_IL(4);
+      RSD_ELL(4, true);
+    } else {
+      RSD_IL(8);
+      RSD_ELL(8, true);
+    }
+#undef RSD_IL
+#undef RSD_ELL
+  }
   return hipGetLastError();
 }
 
@@ -1595,20 +1751,29 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
 }
 
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
-                       const double* base, double* y, hipStream_t s) {
-  if (b.count == 0 || b.num_items == 0) return hipSuccess;
-  if (b.fp32) {
-    k_symv1<float><<<b.num_items, kBlock, 0, s>>>((const float*)b.tiles, b.tile_off, b.n, b.nt,
-                                                  b.vec_off, b.item_mat, b.item_BI, b.item_BJ, x,
-                                                  (float*)part);
-    k_symv2<float><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
-        b.n, b.nt, b.vec_off, b.item_base, (const float*)part, alpha, base, y);
-  } else {
-    k_symv1<double><<<b.num_items, kBlock, 0, s>>>((const double*)b.tiles, b.tile_off, b.n, b.nt,
-                                                   b.vec_off, b.item_mat, b.item_BI, b.item_BJ,
-                                                   x, (double*)part);
-    k_symv2<double><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(
-        b.n, b.nt, b.vec_off, b.item_base, (const double*)part, alpha, base, y);
+                       const double* base, double* y, int nv, int64_t ld, hipStream_t s) {
+  if (b.count == 0 || b.num_items == 0 || nv <= 0) return hipSuccess;
+  const int kmax = symv_vectors(b);
+  for (int v0 = 0; v0 < nv; v0 += kmax) {
+    const int c = nv - v0 < kmax ? nv - v0 : kmax;
+    const int kv = c == 1 ? 1 : c == 2 ? 2 : 4;
+    const double* xb = x + v0 * ld;
+    const double* bb = base ? base + v0 * ld : nullptr;
+    double* yb = y + v0 * ld;
+#define RSD_SYMV(T, KV)                                                                         \
+  k_symv1<T, KV><<<b.num_items, kBlock, 0, s>>>((const T*)b.tiles, b.tile_off, b.n, b.nt,       \
+                                                b.vec_off, b.item_mat, b.item_BI, b.item_BJ, xb, \
+                                                ld, c, (typename SymPart<T>::type*)part)
+    if (b.fp32) {
+      if (kv == 1) RSD_SYMV(float, 1); else if (kv == 2) RSD_SYMV(float, 2); else RSD_SYMV(float, 4);
+      k_symv2<float><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
+          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld);
+    } else {
+      if (kv == 1) RSD_SYMV(double, 1); else if (kv == 2) RSD_SYMV(double, 2); else RSD_SYMV(double, 4);
+      k_symv2<double><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
+          b.n, b.nt, b.vec_off, b.item_base, (const double*)part, kv, alpha, bb, yb, ld);
+    }
+#undef RSD_SYMV
   }
   return hipGetLastError();
 }
@@ -1657,25 +1822,35 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
 
 hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int sigma_fp32,
                               const int64_t* sig_off, const int64_t* B_off, const int32_t* B,
-                              const double* z, double* e, hipStream_t s) {
-  if (it.count == 0) return hipSuccess;
-  if (sigma_fp32)
-    k_sigma_level<float><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,
-                                                      (const float*)sigma, sig_off, B_off, B, z, e);
-  else
-    k_sigma_level<double><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,
-                                                       (const double*)sigma, sig_off, B_off, B, z, e);
+                              const double* z, double* e, int nv, int64_t ldz, int64_t lde,
+                              hipStream_t s) {
+  if (it.count == 0 || nv <= 0) return hipSuccess;
+  constexpr int kmax = 4;
+  for (int v0 = 0; v0 < nv; v0 += kmax) {
+    const int c = nv - v0 < kmax ? nv - v0 : kmax;
+    const double* zb = z + v0 * ldz;
+    double* eb = e + v0 * lde;
+#define RSD_SIGL(S, KV)                                                                     \
+  k_sigma_level<S, KV><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,         \
+                                                   (const S*)sigma, sig_off, B_off, B, zb, eb, \
+                                                   c, ldz, lde)
+    if (sigma_fp32) {
+      if (c == 1) RSD_SIGL(float, 1); else if (c == 2) RSD_SIGL(float, 2); else RSD_SIGL(float, 4);
+    } else {
+      if (c == 1) RSD_SIGL(double, 1); else if (c == 2) RSD_SIGL(double, 2); else RSD_SIGL(double, 4);
+    }
+#undef RSD_SIGL
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_level_rhs(int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* pcol,
-                            const double* pval, const int64_t* segA, const int64_t* segB,
-                            const int64_t* adj_ptr, const int32_t* adj_leaf,
-                            const int32_t* adj_pos, const int64_t* B_off, const double* e,
-                            double* z, hipStream_t s) {
-  if (nrows <= 0) return hipSuccess;
-  k_level_rhs<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, n_leaf, pcol, pval, segA, segB,
-                                                   adj_ptr, adj_leaf, adj_pos, B_off, e, z);
+hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* adj_ptr,
+                            const int32_t* adj_leaf, const int32_t* adj_pos, const int64_t* B_off,
+                            const double* e, double* z, int nv, int64_t ldz, int64_t lde,
+                            hipStream_t s) {
+  if (nrows <= 0 || nv <= 0) return hipSuccess;
+  k_level_adj<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, n_leaf, adj_ptr, adj_leaf, adj_pos,
+                                                   B_off, e, z, nv, ldz, lde);
   return hipGetLastError();
 }
 
@@ -1686,32 +1861,36 @@ int mdot_blocks(int64_t n) {
   return int(b);
 }
 
-hipError_t launch_mdot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n,
-                       double* partial, double* out, int mode, hipStream_t s) {
-  if (ncols <= 0) return hipSuccess;
+hipError_t launch_mdot(int nb_rhs, const double* V, int64_t ldv, int64_t sV, int ncols,
+                       const double* w, int64_t sw, int64_t n, double* partial, double* out,
+                       int64_t so, int mode, hipStream_t s) {
+  if (ncols <= 0 || nb_rhs <= 0) return hipSuccess;
   const int nb = mdot_blocks(n);
-  k_mdot_partial<<<nb, kBlock, 0, s>>>(V, ldv, ncols, w, n, partial);
-  k_mdot_final<<<ncols, kBlock, 0, s>>>(partial, nb, ncols, out, mode);
+  k_mdot_partial<<<dim3(nb, nb_rhs), kBlock, 0, s>>>(V, ldv, sV, ncols, w, sw, n, partial);
+  k_mdot_final<<<dim3(ncols, nb_rhs), kBlock, 0, s>>>(partial, nb, ncols, out, so, mode);
   return hipGetLastError();
 }
 
-hipError_t launch_gemv_acc(const double* V, int64_t ldv, int ncols, const double* h,
-                           double sign, double* w, int64_t n, hipStream_t s) {
-  if (ncols <= 0 || n <= 0) return hipSuccess;
-  k_gemv_acc<<<blocks_for(n), kBlock, 0, s>>>(V, ldv, ncols, h, sign, w, n);
+hipError_t launch_gemv_acc(int nb_rhs, const double* V, int64_t ldv, int64_t sV, int ncols,
+                           const double* h, int64_t sh, double sign, double* w, int64_t sw,
+                           int64_t n, hipStream_t s) {
+  if (ncols <= 0 || n <= 0 || nb_rhs <= 0) return hipSuccess;
+  k_gemv_acc<<<dim3(blocks_for(n), nb_rhs), kBlock, 0, s>>>(V, ldv, sV, ncols, h, sh, sign, w,
+                                                            sw, n);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_div(const double* x, const double* d, double* y, int64_t n,
-                            hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_scale_div<<<blocks_for(n), kBlock, 0, s>>>(x, d, y, n);
+hipError_t launch_scale_div(int nb_rhs, const double* x, int64_t sx, const double* d,
+                            int64_t sd, double* y, int64_t sy, int64_t n, hipStream_t s) {
+  if (n <= 0 || nb_rhs <= 0) return hipSuccess;
+  k_scale_div<<<dim3(blocks_for(n), nb_rhs), kBlock, 0, s>>>(x, sx, d, sd, y, sy, n);
   return hipGetLastError();
 }
 
-hipError_t launch_small_add(double* a, const double* b, int k, hipStream_t s) {
-  if (k <= 0) return hipSuccess;
-  k_small_add<<<1, 512, 0, s>>>(a, b, k);
+hipError_t launch_small_add(int nb_rhs, double* a, int64_t sa, const double* b, int64_t sb,
+                            int k, hipStream_t s) {
+  if (k <= 0 || nb_rhs <= 0) return hipSuccess;
+  k_small_add<<<dim3(1, nb_rhs), 512, 0, s>>>(a, sa, b, sb, k);
   return hipGetLastError();
 }
 

@@ -40,14 +40,20 @@ hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
                           hipStream_t s);
 // sliced ELL copy of K (layout in plan.hpp) and the segmented SpMV on it:
 // y[r] = (base ? base[r] : 0) + alpha * sum over the entries of row r with CSR positions in
-// [s0[r], s1[r]), rows r in [row0, row0 + nrows), entries summed in column order
+// [s0[r], s1[r]), rows r in [row0, row0 + nrows), entries summed in column order; for
+// nv vectors x_k = x + k ld (likewise base, y) the slots are read once per kEllVec vectors,
+// and when xil (ncols * kEllVec doubles of scratch, or null) is given the vectors are first
+// interleaved there so that the gathers of a column are contiguous.  x, base and y may be
+// the same vectors when the columns read are not the rows written.
+constexpr int kEllVec = 8;
 hipError_t launch_ell_fill(int64_t n, const int64_t* prow, const int32_t* pcol,
                            const double* pval, const int64_t* ell_off, int32_t* ell_col,
                            double* ell_val, hipStream_t s);
 hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const int64_t* s1,
                            const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
                            const double* ell_val, const double* x, const double* base,
-                           double alpha, double* y, hipStream_t s);
+                           double alpha, double* y, int nv, int64_t ld, double* xil,
+                           int64_t ncols, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // K in internal order from the caller's CSR (device arrays): pcol, pmap (caller value
 // position of each entry) and the row segments segA / segB / segC
@@ -74,12 +80,16 @@ hipError_t launch_sym_extract(const DevBatch& b, const int64_t* s0, const int64_
 hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, void* cbuf,
                              void* bbuf, int32_t* flags, int group, hipStream_t s, int part = 0);
 size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, size_t* cbytes);
-// y = base + alpha * A x for every matrix of the batch (x, y internal vectors)
+// y_k = base_k + alpha * A x_k for every matrix of the batch and the nv vectors
+// x_k = x + k ld (likewise base, y; internal order), read in groups of up to
+// symv_vectors(b) vectors per pass over the tiles
 // (part: symv_part_bytes(b) of scratch for the per-item partial sums)
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
-                       const double* base, double* y, hipStream_t s);
+                       const double* base, double* y, int nv, int64_t ld, hipStream_t s);
+inline int symv_vectors(const DevBatch&) { return 4; }
 inline size_t symv_part_bytes(const DevBatch& b) {
-  return size_t(b.num_items) * 2 * kSymB * kTile * (b.fp32 ? sizeof(float) : sizeof(double));
+  return size_t(b.num_items) * 2 * kSymB * kTile * size_t(symv_vectors(b)) *
+         (b.fp32 ? sizeof(float) : sizeof(double));
 }
 
 // ---- Schur complements --------------------------------------------------------------------
@@ -121,29 +131,36 @@ struct SigmaLevelItems {
   const int32_t* a0 = nullptr;
   const int32_t* a1 = nullptr;
 };
+// (nv vectors: z_k = z + k ldz, e_k = e + k lde)
 hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int sigma_fp32,
                               const int64_t* sig_off, const int64_t* B_off, const int32_t* B,
-                              const double* z, double* e, hipStream_t s);
-hipError_t launch_level_rhs(int64_t row0, int64_t nrows, int64_t n_leaf, const int32_t* pcol,
-                            const double* pval, const int64_t* segA, const int64_t* segB,
-                            const int64_t* adj_ptr, const int32_t* adj_leaf,
-                            const int32_t* adj_pos, const int64_t* B_off, const double* e,
-                            double* z, hipStream_t s);
+                              const double* z, double* e, int nv, int64_t ldz, int64_t lde,
+                              hipStream_t s);
+// z[r] += sum of e over the leaves adjacent to interface dof r (rows [row0, row0 + nrows))
+hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* adj_ptr,
+                            const int32_t* adj_leaf, const int32_t* adj_pos, const int64_t* B_off,
+                            const double* e, double* z, int nv, int64_t ldz, int64_t lde,
+                            hipStream_t s);
 
 // ---- Krylov ----------------------------------------------------------------------------------
+// Each call acts on nb_rhs independent right-hand sides: operand i of right-hand side
+// i is its pointer plus i times the stride that follows it (sV, sw, ...).
 int mdot_blocks(int64_t n);
 // out[c] (c < ncols) = sum_r V[r + c ldv] w[r]  (deterministic two-pass); mode 0 store,
-// mode 1 store sqrt
-hipError_t launch_mdot(const double* V, int64_t ldv, int ncols, const double* w, int64_t n,
-                       double* partial, double* out, int mode, hipStream_t s);
+// mode 1 store sqrt (partial: nb_rhs * mdot_blocks(n) * ncols doubles)
+hipError_t launch_mdot(int nb_rhs, const double* V, int64_t ldv, int64_t sV, int ncols,
+                       const double* w, int64_t sw, int64_t n, double* partial, double* out,
+                       int64_t so, int mode, hipStream_t s);
 // w += sign * sum_c V[:, c] h[c]
-hipError_t launch_gemv_acc(const double* V, int64_t ldv, int ncols, const double* h,
-                           double sign, double* w, int64_t n, hipStream_t s);
+hipError_t launch_gemv_acc(int nb_rhs, const double* V, int64_t ldv, int64_t sV, int ncols,
+                           const double* h, int64_t sh, double sign, double* w, int64_t sw,
+                           int64_t n, hipStream_t s);
 // y = x / d[0]  (y = 0 when d[0] == 0)
-hipError_t launch_scale_div(const double* x, const double* d, double* y, int64_t n,
-                            hipStream_t s);
+hipError_t launch_scale_div(int nb_rhs, const double* x, int64_t sx, const double* d,
+                            int64_t sd, double* y, int64_t sy, int64_t n, hipStream_t s);
 // a[i] += b[i], i < k
-hipError_t launch_small_add(double* a, const double* b, int k, hipStream_t s);
+hipError_t launch_small_add(int nb_rhs, double* a, int64_t sa, const double* b, int64_t sb,
+                            int k, hipStream_t s);
 // y = x + alpha * z  with alpha = num[0] / den[0] * sgn   (device scalars)
 hipError_t launch_axpy_ratio(const double* x, const double* z, const double* num,
                              const double* den, double sgn, double* y, int64_t n, hipStream_t s);

@@ -194,6 +194,8 @@ def _cols(t, n):
         if t.stride(0) != 1:
             raise ValueError("vectors must be contiguous")
         return 1, t.shape[0]
+    if t.shape[1] <= 1 and (t.stride(0) == 1 or t.shape[0] <= 1):
+        return t.shape[1], max(n, 1)       # one column: any ld >= n describes it
     if t.stride(0) != 1 or t.stride(1) < n:
         raise ValueError("2-D blocks must be column-major (stride (1, ld) with ld >= n)")
     return t.shape[1], t.stride(1)

@@ -146,3 +146,19 @@ def test_setup_validates_before_device_work(problem_cache, lib):
     o.leaf_prec = 7
     _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
                                    p.dof_node.astype(np.int32), o, stream=0))
+
+
+def test_column_block_layout_checks():
+    """The binding's (nrhs, ld) of vector blocks: 1-D, column-major 2-D, and a single
+    column whose stride torch normalised (any ld >= n describes one column)."""
+    import torch
+    from paper_1210_6266_amd.rsd import _cols, colmajor
+    n = 7
+    assert _cols(torch.zeros(n, dtype=torch.float64), n) == (1, n)
+    b = colmajor(torch.zeros(n, 3, dtype=torch.float64))
+    assert _cols(b, n) == (3, n)
+    one = colmajor(torch.zeros(n, 1, dtype=torch.float64))
+    assert _cols(one, n) == (1, n)
+    assert _cols(torch.zeros(3, n, dtype=torch.float64).t()[:, :1], n) == (1, n)
+    with pytest.raises(ValueError):
+        _cols(torch.zeros(n, 3, dtype=torch.float64), n)     # row-major block
