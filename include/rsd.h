@@ -72,6 +72,17 @@ typedef struct {
 /* Storage / arithmetic precision of a class of dense blocks. */
 enum { RSD_PREC_FP64 = 0, RSD_PREC_FP32 = 1 };
 
+/* How the interface systems S~_t u = g of eq. (schur) are solved inside an apply:
+ *   RSD_IFACE_DENSE  -- exactly, with the explicit inverse of the assembled S~_t
+ *                       (the limit of infinitely many inner iterations);
+ *   RSD_IFACE_GAMMA  -- inexactly, as in the paper's experiments (Section 3.1 and
+ *                       Section 4): gamma steps of unpreconditioned GMRES from zero
+ *                       on S~_t, at every level (happy breakdown stops a system early);
+ *   RSD_IFACE_HYBRID -- gamma steps at the levels whose largest interface has more
+ *                       than dense_max dofs, exact solves at the others.
+ * The preconditioner is then a non-linear function of r: use FGMRES. */
+enum { RSD_IFACE_DENSE = 0, RSD_IFACE_GAMMA = 1, RSD_IFACE_HYBRID = 2 };
+
 typedef struct {
   int32_t struct_size;   /* sizeof(rsd_options) */
   int32_t leaf_prec;     /* inverses of the true sub-domain matrices K_ll              */
@@ -81,9 +92,13 @@ typedef struct {
   int32_t host_pointers; /* 0: csr and hierarchy arrays are device pointers;
                             1: they are host pointers (values are copied to the device) */
   int32_t timing;        /* 1: time every kernel class with HIP events (rsd_get_stats) */
+  int32_t iface_mode;    /* RSD_IFACE_DENSE (default), RSD_IFACE_GAMMA or RSD_IFACE_HYBRID  */
+  int32_t gamma;         /* inner GMRES steps per interface solve (1..64; gamma modes)      */
+  int32_t dense_max;     /* RSD_IFACE_HYBRID: largest interface solved exactly              */
 } rsd_options;
 
-/* Fills *opt with the defaults: all FP64, device pointers, no timing. */
+/* Fills *opt with the defaults: all FP64, device pointers, no timing, exact
+ * (dense) interface solves, gamma = 8, dense_max = 32768. */
 void rsd_options_default(rsd_options* opt);
 
 enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };

@@ -45,6 +45,9 @@ void rsd_options_default(rsd_options* o) {
   o->root_prec = RSD_PREC_FP64;
   o->host_pointers = 0;
   o->timing = 0;
+  o->iface_mode = RSD_IFACE_DENSE;
+  o->gamma = 8;
+  o->dense_max = 32768;
 }
 
 rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analysis* out) {
@@ -82,6 +85,13 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "unknown precision code");
     if (opt->host_pointers != 0 && opt->host_pointers != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "host_pointers must be 0 or 1");
+    if (opt->iface_mode != RSD_IFACE_DENSE && opt->iface_mode != RSD_IFACE_GAMMA &&
+        opt->iface_mode != RSD_IFACE_HYBRID)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "unknown interface mode");
+    if (opt->iface_mode != RSD_IFACE_DENSE && (opt->gamma < 1 || opt->gamma > 64))
+      return fail(RSD_ERR_INVALID_ARGUMENT, "gamma must be in 1..64");
+    if (opt->iface_mode == RSD_IFACE_HYBRID && opt->dense_max < 0)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "dense_max must be >= 0");
   }
   if (!csr->values) return fail(RSD_ERR_INVALID_ARGUMENT, "values must not be NULL");
   rsd_ctx* h = nullptr;

@@ -303,6 +303,25 @@ void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void
 
 }  // namespace
 
+// Scratch of the inexact interface solves for nv vectors (nothing without gamma levels);
+// the caller guarantees that no queued work uses the previous buffers.
+void ensure_gamma(rsd_ctx* h, int nv) {
+  if (!h->any_gamma) return;
+  dfree(h, h->gm_V);
+  dfree(h, h->gm_beta);
+  dfree(h, h->gm_H);
+  dfree(h, h->gm_steps);
+  dfree(h, h->gm_stop);
+  int32_t maxc = 1;
+  for (const DevBatch& b : h->lev) maxc = std::max(maxc, b.count);
+  const size_t g = size_t(h->opt.gamma), sl = size_t(nv) * size_t(maxc);
+  h->gm_V = dalloc<double>(h, (g + 1) * size_t(nv) * size_t(h->P.n));
+  h->gm_beta = dalloc<double>(h, sl);
+  h->gm_H = dalloc<double>(h, sl * (g + 1) * g);
+  h->gm_steps = dalloc<int32_t>(h, sl);
+  h->gm_stop = dalloc<int32_t>(h, sl);
+}
+
 void fill_analysis(const Plan& P, rsd_analysis* a) {
   std::memset(a, 0, sizeof(*a));
   a->num_leaves = int32_t(P.leaf_node.size());
@@ -424,6 +443,14 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec == RSD_PREC_FP32);
     const int NL = int(P.level_depth.size());
     h->lev.assign(NL, DevBatch());
+    h->gam_level.assign(NL, 0);
+    for (int q = 0; q < NL; ++q) {
+      int32_t maxn = 0;
+      for (int32_t v : P.level_batch[q].n) maxn = std::max(maxn, v);
+      h->gam_level[q] = h->opt.iface_mode == RSD_IFACE_GAMMA ||
+                        (h->opt.iface_mode == RSD_IFACE_HYBRID && maxn > h->opt.dense_max);
+      h->any_gamma = h->any_gamma || h->gam_level[q];
+    }
     h->lev_items.assign(NL, SigmaLevelItems());
 
     std::vector<std::vector<int32_t>> il(NL), ir0(NL), ia0(NL), ia1(NL);
@@ -474,6 +501,8 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->t = dalloc<double>(h, size_t(n));
     h->rin = dalloc<double>(h, size_t(n));
     h->zin = dalloc<double>(h, size_t(n));
+    h->nvec = 0;
+    ensure_gamma(h, 1);
     h->nvec = 1;
     size_t part_bytes = std::max<size_t>(8, symv_part_bytes(h->leaf));
     for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
@@ -547,7 +576,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
                                            P.n_leaf, s),
                   "schur assembly");
       }
-      {
+      if (!h->gam_level[q]) {   // gamma levels keep S~ itself for the inner GMRES
         Timer tm(h, RSD_T_IFACE_INVERSE, s);
         invert_batch(h, h->lev[q], pbuf, cbuf, bbuf, iflags + P.level_iface_begin[q],
                      P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, s);
@@ -609,7 +638,7 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
     Timer tm(h, RSD_T_COUPLING, s);
     // interface rows: q_B = r_B - K_{B,leaves} y
     hip_check(h, launch_ell_spmv(nl, n - nl, h->prow, h->segA, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, z, nv, n, h->xil, n, s), "condense");
+                                 h->ell_val, z, r, -1.0, z, nv, n, h->xil, 0, nl, s), "condense");
     hip_check(h, launch_fill(h->e, nB * nv, 0.0, s), "fill e");
   }
   for (size_t q = 0; q < h->lev.size(); ++q) {
@@ -620,22 +649,27 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
       // g_t = q_t - K_{t, deeper interfaces} u - sum over adjacent leaves of e_l
       const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
       hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segA, h->segB, h->prow, h->ell_off,
-                                   h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, n, s),
-                "level rhs");
+                                   h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, nl, r0,
+                                   s), "level rhs");   // deeper levels come first: [nl, r0)
       hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos,
                                     h->B_off, h->e, z, nv, n, nB, s), "level adjacency");
     }
     {
       Timer tm(h, RSD_T_IFACE_APPLY, s);
-      hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, nv, n, s),
-                "interface symv");
+      if (h->gam_level[q])      // u = gamma GMRES steps on S~ u = g (paper mode)
+        hip_check(h, launch_gamma_solve(h->lev[q], h->opt.gamma, nv, z, n, h->gm_V, h->gm_beta,
+                                        h->gm_H, h->gm_steps, h->gm_stop, h->sympart, s),
+                  "interface gamma solve");
+      else                      // u = S~^{-1} g (tiles hold -S~^{-1})
+        hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, nv, n, s),
+                  "interface symv");
     }
   }
   {
     Timer tm(h, RSD_T_COUPLING, s);
     // leaf rows: r_l - K_{l,B} u_B
     hip_check(h, launch_ell_spmv(0, nl, h->segA, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, h->t, nv, n, h->xil, n, s),
+                                 h->ell_val, z, r, -1.0, h->t, nv, n, h->xil, nl, n, s),
               "back-substitution rhs");
   }
   {
@@ -649,7 +683,7 @@ void core_spmv(rsd_ctx* h, int nv, const double* x, const double* base, double a
                hipStream_t s) {
   Timer tm(h, RSD_T_SPMV, s);
   hip_check(h, launch_ell_spmv(0, h->P.n, h->prow, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                               h->ell_val, x, base, alpha, y, nv, h->P.n, h->xil, h->P.n, s),
+                               h->ell_val, x, base, alpha, y, nv, h->P.n, h->xil, 0, h->P.n, s),
             "spmv");
 }
 
@@ -662,10 +696,11 @@ void permute(rsd_ctx* h, int nv, const double* x, int64_t ldx, double* y, int64_
 // Right-hand sides handled together by one apply, SpMV or Krylov iteration.
 constexpr int kRhsGroup = 8;
 
-// Apply work vectors (e, t, rin, zin, xil) for nv vectors at once.
+// Apply work vectors (e, t, rin, zin, xil, the inner GMRES scratch) for nv vectors.
 void ensure_vectors(rsd_ctx* h, int nv) {
   if (h->nvec >= nv) return;
   hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
+  ensure_gamma(h, nv);
   for (double* p : {h->e, h->t, h->rin, h->zin, h->xil}) dfree(h, p);
   const size_t n = size_t(h->P.n), nB = std::max<size_t>(1, h->P.B.size());
   h->xil = dalloc<double>(h, n * size_t(kEllVec));      // interleaved copies for the SpMVs

@@ -57,6 +57,12 @@ struct rsd_ctx {
   double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;   // nvec vectors each
   double* xil = nullptr;     // n * kEllVec: interleaved SpMV operand (null while nvec == 1)
   int nvec = 0;
+  // inexact interface solves: per level, 1 when its systems get gamma GMRES steps; the
+  // GMRES scratch (basis, beta, Hessenberg matrices, steps, stop flags) for nvec vectors
+  std::vector<char> gam_level;
+  bool any_gamma = false;
+  double *gm_V = nullptr, *gm_beta = nullptr, *gm_H = nullptr;
+  int32_t *gm_steps = nullptr, *gm_stop = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
 
   // Krylov work space (grown on demand)

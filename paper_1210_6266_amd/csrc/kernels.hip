@@ -174,10 +174,10 @@ __global__ __launch_bounds__(kEllSlice) void k_ell_fill(int64_t n, const int64_t
 // side, so that one lane's gather for all of them is KV contiguous doubles.
 template <int KV>
 __global__ __launch_bounds__(kBlock) void k_interleave(const double* __restrict__ x, int nv,
-                                                       int64_t ld, int64_t ncols,
+                                                       int64_t ld, int64_t col0, int64_t col1,
                                                        double* __restrict__ xil) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= ncols) return;
+  const int64_t i = col0 + int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= col1) return;
   typedef double D2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < KV; k += 2) {
@@ -1151,13 +1151,13 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
   const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
   auto q4 = [&](int v) { return sizeof(T) == 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
   constexpr bool kColLds = sizeof(T) == 8;
-  __shared__ double xs[KV][2][B][TS];
+  __shared__ P xs[KV][2][B][TS];               // x in the product's precision
   __shared__ P red[KV][4][B][TS];
   __shared__ P colr[kColLds ? KV : 1][B][TS];
   for (int e = t; e < KV * 2 * B * TS; e += kBlock) {
     const int k = e / (2 * B * TS), sd = (e / (B * TS)) % 2, b = (e / TS) % B, r = e % TS;
     const int idx = ((sd == 0 ? BI : BJ) * B + b) * TS + r;
-    xs[k][sd][b][r] = idx < n && k < nv ? x[k * ldx + xo + idx] : 0.0;
+    xs[k][sd][b][r] = P(idx < n && k < nv ? x[k * ldx + xo + idx] : 0.0);
   }
   if (kColLds)
     for (int e = t; e < KV * B * TS; e += kBlock) (&colr[0][0][0])[e] = P(0);
@@ -1178,6 +1178,13 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
 #pragma unroll
       for (int v = 0; v < 4; ++v) ra[k][v] = P(0);
     if (I < nt) {
+      // x_I: in registers for FP32 tiles, read from LDS at each use for FP64 tiles
+      P xi[kColLds ? 1 : KV][4];
+      if constexpr (!kColLds)
+#pragma unroll
+        for (int k = 0; k < KV; ++k)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xi[k][v] = xs[k][0][bi][q4(v)];
 #pragma unroll
       for (int bj = 0; bj < B; ++bj) {
         const int J = BJ * B + bj;
@@ -1194,15 +1201,16 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
           P xk[KV];
 #pragma unroll
           for (int k = 0; k < KV; ++k) {
-            xk[k] = P(xs[k][1][bj][g + 16 * u]);
+            xk[k] = xs[k][1][bj][g + 16 * u];
             cf[k][u] = P(0);
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const P av = P(a[u][v / VEC][v % VEC]);
 #pragma unroll
-            for (int k = 0; k < KV; ++k) {   // x_I is read from LDS: fewer live registers
-              cf[k][u] = fma(av, P(xs[k][0][bi][q4(v)]), cf[k][u]);
+            for (int k = 0; k < KV; ++k) {
+              const P xv = kColLds ? xs[k][0][bi][q4(v)] : xi[kColLds ? 0 : k][v];
+              cf[k][u] = fma(av, xv, cf[k][u]);
               ra[k][v] = fma(av, xk[k], ra[k][v]);
             }
           }
@@ -1478,15 +1486,14 @@ __global__ __launch_bounds__(kBlock) void k_level_adj(
     const int64_t* __restrict__ B_off, const double* __restrict__ e, double* __restrict__ z,
     int nv, int64_t ldz, int64_t lde) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= nrows) return;
+  const int v = blockIdx.y;                    // vector
+  if (i >= nrows || v >= nv) return;
   const int64_t r = row0 + i;
   const int64_t p = r - n_leaf;
-  for (int v = 0; v < nv; ++v) {
-    const double* ev = e + v * lde;
-    double s = z[v * ldz + r];
-    for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += ev[B_off[adj_leaf[k]] + adj_pos[k]];
-    z[v * ldz + r] = s;
-  }
+  const double* ev = e + v * lde;
+  double s = z[v * ldz + r];
+  for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += ev[B_off[adj_leaf[k]] + adj_pos[k]];
+  z[v * ldz + r] = s;
 }
 
 // ================================================================ Krylov
@@ -1591,6 +1598,137 @@ __global__ void k_axpy_ratio(const double* __restrict__ x, const double* __restr
   y[r] = x[r] + alpha * z[r];
 }
 
+
+// ================================================================ inexact interface solves
+// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every matrix m of a
+// level batch (S~_t assembled in the tiles, not inverted) and every vector k: one block
+// per (m, k).  Basis vector j of vector k is V + (j nv + k) ld, used at the matrix's rows
+// vec_off[m] .. vec_off[m] + n[m]; slot = k count + m indexes the per-system state:
+// beta = ||g||, the (gamma + 1) x gamma Hessenberg matrix H (column-major), the steps
+// taken and a stop flag (happy breakdown, or g = 0).
+__device__ __forceinline__ double block_allsum(double v, double* sh) {
+  // sum over the kBlock threads, returned to every thread (fixed order)
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gm_start(
+    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off, int count,
+    const double* __restrict__ z, int64_t ld, int nv, int gamma, double* __restrict__ V,
+    double* __restrict__ beta, double* __restrict__ H, int32_t* __restrict__ steps,
+    int32_t* __restrict__ stop) {
+  __shared__ double sh[4];
+  const int m = blockIdx.x, k = blockIdx.y;
+  const int n = n_arr[m];
+  const int64_t o = vec_off[m];
+  const double* g = z + k * ld + o;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += g[i] * g[i];
+  const double b = sqrt(block_allsum(s, sh));
+  double* v0 = V + int64_t(k) * ld + o;
+  for (int i = threadIdx.x; i < n; i += kBlock) v0[i] = b > 0.0 ? g[i] / b : 0.0;
+  const int64_t slot = int64_t(k) * count + m;
+  double* Hs = H + slot * (gamma + 1) * gamma;
+  for (int i = threadIdx.x; i < (gamma + 1) * gamma; i += kBlock) Hs[i] = 0.0;
+  if (threadIdx.x == 0) {
+    beta[slot] = b;
+    steps[slot] = 0;
+    stop[slot] = b > 0.0 ? 0 : 1;
+  }
+}
+
+// Step j after w = S~ v_j has been written to basis slot j + 1: modified Gram-Schmidt
+// against v_0 .. v_j, the norm, and the normalisation unless the norm is at most
+// 1e-14 beta (happy breakdown: the system stops with j + 1 steps).
+__global__ __launch_bounds__(kBlock) void k_gm_orth(
+    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off, int count, int j,
+    int64_t ld, int nv, int gamma, double* __restrict__ V, const double* __restrict__ beta,
+    double* __restrict__ H, int32_t* __restrict__ steps, int32_t* __restrict__ stop) {
+  __shared__ double sh[4];
+  const int m = blockIdx.x, k = blockIdx.y;
+  const int64_t slot = int64_t(k) * count + m;
+  if (stop[slot] || steps[slot] != j) return;
+  const int n = n_arr[m];
+  const int64_t o = vec_off[m];
+  double* Hs = H + slot * (gamma + 1) * gamma;
+  double* w = V + (int64_t(j + 1) * nv + k) * ld + o;
+  for (int i = 0; i <= j; ++i) {
+    const double* vi = V + (int64_t(i) * nv + k) * ld + o;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < n; r += kBlock) s += vi[r] * w[r];
+    const double hij = block_allsum(s, sh);
+    for (int r = threadIdx.x; r < n; r += kBlock) w[r] -= hij * vi[r];
+    if (threadIdx.x == 0) Hs[i + j * (gamma + 1)] = hij;
+  }
+  double s = 0.0;
+  for (int r = threadIdx.x; r < n; r += kBlock) s += w[r] * w[r];
+  const double hn = sqrt(block_allsum(s, sh));
+  if (threadIdx.x == 0) {
+    Hs[j + 1 + j * (gamma + 1)] = hn;
+    steps[slot] = j + 1;
+  }
+  if (hn <= 1e-14 * beta[slot]) {
+    if (threadIdx.x == 0) stop[slot] = 1;
+    return;
+  }
+  for (int r = threadIdx.x; r < n; r += kBlock) w[r] /= hn;
+}
+
+// u = V_k y with y the least-squares solution of min || beta e1 - H y || over the
+// steps taken (Givens QR of the Hessenberg matrix), written over g in z.
+constexpr int kGammaMax = 64;
+__global__ __launch_bounds__(kBlock) void k_gm_finish(
+    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off, int count,
+    int64_t ld, int nv, int gamma, const double* __restrict__ V,
+    const double* __restrict__ beta, const double* __restrict__ H,
+    const int32_t* __restrict__ steps, double* __restrict__ z) {
+  __shared__ double R[(kGammaMax + 1) * kGammaMax];
+  __shared__ double y[kGammaMax + 1];
+  const int m = blockIdx.x, k = blockIdx.y;
+  const int64_t slot = int64_t(k) * count + m;
+  const int n = n_arr[m];
+  const int64_t o = vec_off[m];
+  const int ks = beta[slot] > 0.0 ? steps[slot] : 0;
+  const double* Hs = H + slot * (gamma + 1) * gamma;
+  for (int i = threadIdx.x; i < (gamma + 1) * gamma; i += kBlock) R[i] = Hs[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int L = gamma + 1;
+    for (int i = 0; i <= ks; ++i) y[i] = i == 0 ? beta[slot] : 0.0;
+    for (int c = 0; c < ks; ++c) {
+      // rotation c acts on rows c, c + 1 of the remaining columns and zeroes R[c + 1, c]
+      const double a = R[c + c * L], b = R[c + 1 + c * L];
+      const double d = hypot(a, b);
+      const double cs = d > 0.0 ? a / d : 1.0, sn = d > 0.0 ? b / d : 0.0;
+      for (int cc = c; cc < ks; ++cc) {
+        const double t0 = R[c + cc * L], t1 = R[c + 1 + cc * L];
+        R[c + cc * L] = cs * t0 + sn * t1;
+        R[c + 1 + cc * L] = -sn * t0 + cs * t1;
+      }
+      const double g0 = y[c], g1 = y[c + 1];
+      y[c] = cs * g0 + sn * g1;
+      y[c + 1] = -sn * g0 + cs * g1;
+    }
+    for (int c = ks - 1; c >= 0; --c) {
+      double v = y[c];
+      for (int cc = c + 1; cc < ks; ++cc) v -= R[c + cc * L] * y[cc];
+      const double dg = R[c + c * L];
+      y[c] = dg != 0.0 ? v / dg : 0.0;
+    }
+  }
+  __syncthreads();
+  double* u = z + k * ld + o;
+  for (int r = threadIdx.x; r < n; r += kBlock) {
+    double s = 0.0;
+    for (int c = 0; c < ks; ++c) s += y[c] * V[(int64_t(c) * nv + k) * ld + o + r];
+    u[r] = s;
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
@@ -1624,7 +1762,7 @@ hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const
                            const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
                            const double* ell_val, const double* x, const double* base,
                            double alpha, double* y, int nv, int64_t ld, double* xil,
-                           int64_t ncols, hipStream_t s) {
+                           int64_t col0, int64_t col1, hipStream_t s) {
   if (nrows <= 0 || nv <= 0) return hipSuccess;
   for (int v0 = 0; v0 < nv; v0 += kEllVec) {
     const int c = nv - v0 < kEllVec ? nv - v0 : kEllVec;
@@ -1637,8 +1775,9 @@ hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const
   k_ell_spmv<KV, IL><<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, s0, s1, prow, ell_off, \
                                                           ell_col, ell_val, xb, xil, bb, alpha, \
                                                           yb, c, ld)
-#define RSD_IL(KV) \
-  k_interleave<KV><<<blocks_for(ncols), kBlock, 0, s>>>(xb, c, ld, ncols, xil)
+#define RSD_IL(KV)                                                                         \
+  if (col1 > col0)                                                                         \
+  k_interleave<KV><<<blocks_for(col1 - col0), kBlock, 0, s>>>(xb, c, ld, col0, col1, xil)
     if (kv == 1) {
       RSD_ELL(1, false);
     } else if (!il) {
@@ -1849,8 +1988,30 @@ hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const i
                             const double* e, double* z, int nv, int64_t ldz, int64_t lde,
                             hipStream_t s) {
   if (nrows <= 0 || nv <= 0) return hipSuccess;
-  k_level_adj<<<blocks_for(nrows), kBlock, 0, s>>>(row0, nrows, n_leaf, adj_ptr, adj_leaf, adj_pos,
-                                                   B_off, e, z, nv, ldz, lde);
+  k_level_adj<<<dim3(blocks_for(nrows), nv), kBlock, 0, s>>>(row0, nrows, n_leaf, adj_ptr,
+                                                             adj_leaf, adj_pos, B_off, e, z, nv,
+                                                             ldz, lde);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_solve(const DevBatch& b, int gamma, int nv, double* z, int64_t ld,
+                              double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
+                              void* part, hipStream_t s) {
+  if (b.count == 0 || nv <= 0) return hipSuccess;
+  if (gamma < 1 || gamma > kGammaMax) return hipErrorInvalidValue;
+  const dim3 grid(unsigned(b.count), unsigned(nv));
+  k_gm_start<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, z, ld, nv, gamma, V, beta, H, steps,
+                                     stop);
+  for (int j = 0; j < gamma; ++j) {
+    // w = S~ v_j into basis slot j + 1 (the tiles hold S~ itself)
+    hipError_t e = launch_symv(b, V + int64_t(j) * nv * ld, part, 1.0, nullptr,
+                               V + int64_t(j + 1) * nv * ld, nv, ld, s);
+    if (e != hipSuccess) return e;
+    k_gm_orth<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, j, ld, nv, gamma, V, beta, H,
+                                      steps, stop);
+  }
+  k_gm_finish<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, ld, nv, gamma, V, beta, H, steps,
+                                      z);
   return hipGetLastError();
 }
 

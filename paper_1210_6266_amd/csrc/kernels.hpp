@@ -42,9 +42,10 @@ hipError_t launch_permute(const double* x, int64_t ldx, double* y, int64_t ldy,
 // y[r] = (base ? base[r] : 0) + alpha * sum over the entries of row r with CSR positions in
 // [s0[r], s1[r]), rows r in [row0, row0 + nrows), entries summed in column order; for
 // nv vectors x_k = x + k ld (likewise base, y) the slots are read once per kEllVec vectors,
-// and when xil (ncols * kEllVec doubles of scratch, or null) is given the vectors are first
-// interleaved there so that the gathers of a column are contiguous.  x, base and y may be
-// the same vectors when the columns read are not the rows written.
+// and when xil (n * kEllVec doubles of scratch, or null) is given the columns [col0, col1)
+// of the vectors -- all that the rows' segments read -- are first interleaved there so that
+// the gathers of a column are contiguous.  x, base and y may be the same vectors when the
+// columns read are not the rows written.
 constexpr int kEllVec = 8;
 hipError_t launch_ell_fill(int64_t n, const int64_t* prow, const int32_t* pcol,
                            const double* pval, const int64_t* ell_off, int32_t* ell_col,
@@ -53,7 +54,7 @@ hipError_t launch_ell_spmv(int64_t row0, int64_t nrows, const int64_t* s0, const
                            const int64_t* prow, const int64_t* ell_off, const int32_t* ell_col,
                            const double* ell_val, const double* x, const double* base,
                            double alpha, double* y, int nv, int64_t ld, double* xil,
-                           int64_t ncols, hipStream_t s);
+                           int64_t col0, int64_t col1, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 // K in internal order from the caller's CSR (device arrays): pcol, pmap (caller value
 // position of each entry) and the row segments segA / segB / segC
@@ -141,6 +142,15 @@ hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const i
                             const int32_t* adj_leaf, const int32_t* adj_pos, const int64_t* B_off,
                             const double* e, double* z, int nv, int64_t ldz, int64_t lde,
                             hipStream_t s);
+
+// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every matrix of the
+// level batch b (tiles holding S~_t, not inverted) and nv vectors: g is read from and u
+// written to z_k = z + k ld at each matrix's rows.  Scratch: V (gamma + 1) * nv * ld
+// doubles (basis), beta nv * count doubles, H nv * count * (gamma + 1) * gamma doubles,
+// steps and stop nv * count ints, part symv_part_bytes(b).  gamma in 1..64.
+hipError_t launch_gamma_solve(const DevBatch& b, int gamma, int nv, double* z, int64_t ld,
+                              double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
+                              void* part, hipStream_t s);
 
 // ---- Krylov ----------------------------------------------------------------------------------
 // Each call acts on nb_rhs independent right-hand sides: operand i of right-hand side

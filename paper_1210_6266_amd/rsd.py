@@ -24,6 +24,7 @@ STATUS = {0: "RSD_OK", 1: "RSD_ERR_INVALID_ARGUMENT", 2: "RSD_ERR_MAP_NOT_SEPARA
           6: "RSD_ERR_OUT_OF_MEMORY", 7: "RSD_ERR_DEVICE", 8: "RSD_ERR_UNSUPPORTED"}
 PREC = {"fp64": 0, "fp32": 1}
 SOLVER = {"fgmres": 0, "pcg": 1}
+IFACE = {"dense": 0, "gamma": 1, "hybrid": 2}
 TIMER_NAMES = ["setup_extract", "leaf_inverse", "leaf_update", "sigma", "iface_assembly",
                "iface_inverse", "iface_update", "root_update", "leaf_apply", "iface_apply",
                "coupling", "spmv", "krylov", "permute"]
@@ -41,7 +42,8 @@ class rsd_hierarchy(C.Structure):
 class rsd_options(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("leaf_prec", C.c_int32), ("sigma_prec", C.c_int32),
                 ("iface_prec", C.c_int32), ("root_prec", C.c_int32),
-                ("host_pointers", C.c_int32), ("timing", C.c_int32)]
+                ("host_pointers", C.c_int32), ("timing", C.c_int32),
+                ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32)]
 
 
 class rsd_solve_options(C.Structure):
@@ -264,7 +266,11 @@ class RSD:
     """One RSD preconditioner handle over a CSR matrix on the current HIP device."""
 
     def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
-                 sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None):
+                 sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
+                 interface="dense", gamma=8, dense_max=32768):
+        """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
+        every interface system, the paper's mode) or "hybrid" (gamma steps where an
+        interface has more than dense_max dofs)."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -284,6 +290,9 @@ class RSD:
         o.iface_prec = PREC[iface_prec or leaf_prec]
         o.root_prec = PREC[root_prec]
         o.timing = 1 if timing else 0
+        o.iface_mode = IFACE[interface]
+        o.gamma = int(gamma)
+        o.dense_max = int(dense_max)
         self.stream = stream
         self.handle = rsd_setup(self.row_ptr, self.col_idx, self.values, self.parent,
                                 self.dof_node, o, stream)

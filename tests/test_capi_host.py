@@ -35,7 +35,8 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
-    assert o.struct_size == 7 * 4 and o.leaf_prec == 0 and o.timing == 0
+    assert o.struct_size == 10 * 4 and o.leaf_prec == 0 and o.timing == 0
+    assert o.iface_mode == 0 and o.gamma == 8 and o.dense_max == 32768
 
 
 def _arrays(p):
@@ -146,6 +147,15 @@ def test_setup_validates_before_device_work(problem_cache, lib):
     o.leaf_prec = 7
     _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
                                    p.dof_node.astype(np.int32), o, stream=0))
+    # interface-solve options: unknown mode, gamma out of 1..64, negative dense_max
+    for mode, gamma, dmax, what in ((5, 8, 0, "interface mode"), (1, 0, 0, "gamma"),
+                                    (2, 65, 0, "gamma"), (2, 4, -1, "dense_max")):
+        o = R.rsd_options_default()
+        o.host_pointers = 1
+        o.iface_mode, o.gamma, o.dense_max = mode, gamma, dmax
+        msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
+                                             p.dof_node.astype(np.int32), o, stream=0))
+        assert what in msg, msg
 
 
 def test_column_block_layout_checks():
