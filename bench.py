@@ -15,6 +15,11 @@ interface blocks in FP32 and the root interface, the Krylov vectors, dot product
 orthogonalisation and residuals in FP64; the plain FP64 variant is timed beside it.
 
 value = solves per second of the mixed variant (1 / time-to-1e-10 including set-up).
+
+Secondary blocks on the same line: the differentiable solve on diffusion 32^3
+(forward + adjoint + gradient per pass) and 3-D elasticity 48^3 on 512 uneven
+sub-domains with 8 right-hand sides solved in lockstep.  `--blocks elasticity48`
+(without `main`) runs only the chosen blocks, for profiling.
 """
 from __future__ import annotations
 
@@ -55,6 +60,12 @@ def parse():
                     help="time one variant only (for profiling runs)")
     ap.add_argument("--adjoint-steps", type=int, default=5,
                     help="forward+backward passes timed on the 32^3 adjoint workload (0: skip)")
+    ap.add_argument("--elasticity-steps", type=int, default=2,
+                    help="set-up + 8-RHS solves timed on the 48^3 elasticity workload (0: skip)")
+    ap.add_argument("--blocks", default="main,adjoint32,elasticity48",
+                    help="comma list of what to run: main (the 64^3 diffusion line), adjoint32, "
+                         "elasticity48; without main only the chosen blocks are run and printed "
+                         "(a profiling aid, not the benchmark line)")
     return ap.parse_args()
 
 
@@ -95,6 +106,108 @@ def measured_traffic(key):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def bench_adjoint(a, dev):
+    """Differentiable solve on the 32^3 adjoint workload (None when skipped)."""
+    import torch
+
+    from workloads import config_problem
+    # ---- differentiable solve (adjoint method) on the 32^3 adjoint workload: one pass
+    # = assembly of K(theta) + set-up refresh + forward solve + adjoint solve + gradient
+    adjoint = None
+    if a.adjoint_steps > 0:
+        from paper_1210_6266_amd.adjoint import DifferentiableSolve
+        from workloads import diffusion_fe_map
+        pa = config_problem("adjoint32", seed=a.seed)
+        fe = diffusion_fe_map(pa)
+        rpa, cia, _ = pa.csr_arrays()
+        th0 = torch.as_tensor(pa.meta["theta"], device=dev)
+        ba = torch.as_tensor(np.ascontiguousarray(pa.b[:, 0]), device=dev)
+        xt = torch.as_tensor(pa.meta["x_target"], device=dev)
+        adjoint = {}
+        for name, prec in (("mixed", dict(leaf_prec="fp32", sigma_prec="fp32",
+                                          iface_prec="fp32", root_prec="fp64")), ("fp64", {})):
+            sysd = DifferentiableSolve(rpa, cia, pa.parent, pa.dof_node, fe, rtol=1e-10, **prec)
+
+            def one(k):
+                theta = (th0 + 1e-3 * k).requires_grad_(True)   # a new K every pass
+                x = sysd(theta, ba)
+                loss = 0.5 * ((x - xt) ** 2).sum()
+                loss.backward()
+                return theta.grad
+
+            one(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(a.adjoint_steps):
+                one(k + 1)
+            torch.cuda.synchronize()
+            its = [i["iterations"] for i in sysd.last_info[-2 * a.adjoint_steps:]]
+            adjoint[name] = dict(ms_per_fwd_bwd=1e3 * (time.perf_counter() - t0) / a.adjoint_steps,
+                                 krylov_iterations=its[:2])
+            sysd.close()
+        adjoint["workload"] = ("diffusion 32^3 Q1, k = exp(theta), theta ~ N(0, 0.5^2), octree h=2; "
+                               "L = 1/2 ||x - x_t||^2; FGMRES(30) to 1e-10 forward and adjoint")
+
+    return adjoint
+
+
+def bench_elasticity(a, dev):
+    """Set-up + lockstep 8-RHS solves on the 48^3 elasticity workload (None when skipped)."""
+    import torch
+
+    from paper_1210_6266_amd import RSD
+    from workloads import config_problem
+    # ---- 3-D elasticity 48^3 on 512 uneven sub-domains with 8 right-hand sides: one pass
+    # = set-up + lockstep FGMRES(30) of the 8 columns to 1e-10 + destroy
+    elastic = None
+    if a.elasticity_steps > 0:
+        pe = config_problem("elasticity48", seed=a.seed)
+        rpe, cie, ve = pe.csr_arrays()
+        de = [torch.as_tensor(t, device=dev) for t in
+              (rpe, cie, ve, pe.parent.astype(np.int32), pe.dof_node.astype(np.int32))]
+        Be = torch.as_tensor(np.ascontiguousarray(pe.b.T), device=dev).t()   # n x 8, column-major
+        elastic = {}
+        for name, prec in (("mixed", dict(leaf_prec="fp32", sigma_prec="fp32",
+                                          iface_prec="fp32", root_prec="fp64")), ("fp64", {})):
+            if a.only is not None and name != a.only:
+                continue
+
+            def one():
+                h = RSD(*de, **prec)
+                X, st, info = h.solve(Be, rtol=1e-10, restart=30, maxit=2000)
+                torch.cuda.synchronize()
+                return h, X, st, info
+
+            h, X, st, info = one()
+            # one column alone on the same handle: what the group saves per column
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st1, info1 = h.solve(Be[:, :1], rtol=1e-10, restart=30, maxit=2000)
+            torch.cuda.synchronize()
+            single = time.perf_counter() - t0
+            h.close()
+            t0 = time.perf_counter()
+            for _ in range(a.elasticity_steps):
+                h, X, st, info = one()
+                h.close()
+            sec = (time.perf_counter() - t0) / a.elasticity_steps
+            Xh = X.cpu().numpy()
+            rel = max(float(np.linalg.norm(pe.b[:, j] - pe.K @ Xh[:, j]) / np.linalg.norm(pe.b[:, j]))
+                      for j in range(pe.b.shape[1]))
+            elastic[name] = dict(ms_setup_plus_8rhs_solve=1e3 * sec,
+                                 solves_per_s=pe.b.shape[1] / sec,
+                                 status=int(st), iterations=[i["iterations"] for i in info],
+                                 max_true_relres=rel,
+                                 ms_one_column_solve_alone=1e3 * single,
+                                 iterations_one_column=info1[0]["iterations"])
+        elastic["workload"] = ("3-D linear elasticity Q1 48^3 (E = 1, nu = 0.3, clamped x = 0), "
+                               f"n = {pe.n}, nnz = {pe.K.nnz}; octree h = 3 over uneven cut planes "
+                               "(512 leaves of 192-882 dofs); 8 right-hand sides (body load + "
+                               "N(0, 0.1^2) per dof); lockstep FGMRES(30) to 1e-10")
+
+    return elastic
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -109,6 +222,12 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if "main" not in a.blocks.split(","):
+        blocks = set(a.blocks.split(","))
+        out = {"adjoint32": bench_adjoint(a, dev) if "adjoint32" in blocks else None,
+               "elasticity48": bench_elasticity(a, dev) if "elasticity48" in blocks else None}
+        print(json.dumps(out), flush=True)
+        return
     p = config_problem("diffusion64", seed=a.seed)
     rp, ci, v = p.csr_arrays()
     ana = rsd_analyze(rp, ci, p.parent, p.dof_node)
@@ -243,42 +362,9 @@ def main():
         fl = update_flops(leaf_sizes)
         extra["leaf_update_TFLOPs"] = fl / (ms["leaf_update"] * 1e-3) / 1e12
 
-    # ---- differentiable solve (adjoint method) on the 32^3 adjoint workload: one pass
-    # = assembly of K(theta) + set-up refresh + forward solve + adjoint solve + gradient
-    adjoint = None
-    if a.adjoint_steps > 0 and a.only is None:
-        from paper_1210_6266_amd.adjoint import DifferentiableSolve
-        from workloads import diffusion_fe_map
-        pa = config_problem("adjoint32", seed=a.seed)
-        fe = diffusion_fe_map(pa)
-        rpa, cia, _ = pa.csr_arrays()
-        th0 = torch.as_tensor(pa.meta["theta"], device=dev)
-        ba = torch.as_tensor(np.ascontiguousarray(pa.b[:, 0]), device=dev)
-        xt = torch.as_tensor(pa.meta["x_target"], device=dev)
-        adjoint = {}
-        for name, prec in (("mixed", dict(leaf_prec="fp32", sigma_prec="fp32",
-                                          iface_prec="fp32", root_prec="fp64")), ("fp64", {})):
-            sysd = DifferentiableSolve(rpa, cia, pa.parent, pa.dof_node, fe, rtol=1e-10, **prec)
-
-            def one(k):
-                theta = (th0 + 1e-3 * k).requires_grad_(True)   # a new K every pass
-                x = sysd(theta, ba)
-                loss = 0.5 * ((x - xt) ** 2).sum()
-                loss.backward()
-                return theta.grad
-
-            one(0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(a.adjoint_steps):
-                one(k + 1)
-            torch.cuda.synchronize()
-            its = [i["iterations"] for i in sysd.last_info[-2 * a.adjoint_steps:]]
-            adjoint[name] = dict(ms_per_fwd_bwd=1e3 * (time.perf_counter() - t0) / a.adjoint_steps,
-                                 krylov_iterations=its[:2])
-            sysd.close()
-        adjoint["workload"] = ("diffusion 32^3 Q1, k = exp(theta), theta ~ N(0, 0.5^2), octree h=2; "
-                               "L = 1/2 ||x - x_t||^2; FGMRES(30) to 1e-10 forward and adjoint")
+    blocks = set(a.blocks.split(","))
+    adjoint = bench_adjoint(a, dev) if "adjoint32" in blocks and a.only is None else None
+    elastic = bench_elasticity(a, dev) if "elasticity48" in blocks and a.only is None else None
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -335,6 +421,7 @@ def main():
         "roofline": roof,
         "secondary": extra,
         "adjoint32": adjoint,
+        "elasticity48": elastic,
         "cpu_baseline": cpu,
     }
     if "mixed" in res and "fp64" in res:
