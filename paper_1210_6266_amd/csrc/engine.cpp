@@ -225,7 +225,9 @@ void fold_timings(rsd_ctx* h) {
   h->pending.clear();
 }
 
-void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool fp32) {
+// (tiles = false: the systems' sizes and offsets only, for levels solved matrix-free)
+void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool fp32,
+                  bool tiles = true) {
   d->count = b.count;
   d->max_nt = b.max_nt;
   d->max_tiles = b.max_tiles;
@@ -239,7 +241,8 @@ void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool
   up.add(&d->item_BJ, b.item_BJ);
   up.add(&d->item_base, b.item_base);
   d->fp32 = fp32 ? 1 : 0;
-  if (b.total_elems > 0) {
+  if (!tiles) d->num_items = 0;
+  if (tiles && b.total_elems > 0) {
     if (fp32)
       d->tiles = dalloc<float>(h, size_t(b.total_elems));
     else
@@ -452,26 +455,36 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       h->any_gamma = h->any_gamma || h->gam_level[q];
     }
     h->lev_items.assign(NL, SigmaLevelItems());
+    h->lev_own_items.assign(NL, SigmaLevelItems());
 
-    std::vector<std::vector<int32_t>> il(NL), ir0(NL), ia0(NL), ia1(NL);
+    // Sigma products per level, split into row chunks of kSigRows: against the deeper
+    // levels' columns (the apply), and against the level's own columns (the S-MatVec of
+    // Alg. 1 for the levels solved with gamma GMRES steps)
+    struct ItemLists { std::vector<int32_t> l, c0, c1, a0, a1; };
+    std::vector<ItemLists> deep(NL), own(NL);
+    auto items = [&](const std::vector<LevelSigmaItem>& src, bool own_cols, ItemLists* o,
+                     SigmaLevelItems* li) {
+      for (const auto& it : src)
+        for (int32_t a0 = it.r0; a0 < it.r1; a0 += kSigRows) {
+          o->l.push_back(it.leaf);
+          o->c0.push_back(own_cols ? it.r0 : 0);
+          o->c1.push_back(own_cols ? it.r1 : it.r0);
+          o->a0.push_back(a0);
+          o->a1.push_back(std::min(it.r1, a0 + kSigRows));
+        }
+      li->count = int32_t(o->l.size());
+      up.add(&li->leaf, o->l);
+      up.add(&li->c0, o->c0);
+      up.add(&li->c1, o->c1);
+      up.add(&li->a0, o->a0);
+      up.add(&li->a1, o->a1);
+    };
     for (int q = 0; q < NL; ++q) {
       const bool root = P.level_depth[q] == 0;
       const int prec = root ? h->opt.root_prec : h->opt.iface_prec;
-      upload_batch(h, up, &h->lev[q], P.level_batch[q], prec == RSD_PREC_FP32);
-      // Sigma products of this level, split into row chunks of kSigRows
-      for (const auto& it : P.level_sigma[q])
-        for (int32_t a0 = it.r0; a0 < it.r1; a0 += kSigRows) {
-          il[q].push_back(it.leaf);
-          ir0[q].push_back(it.r0);
-          ia0[q].push_back(a0);
-          ia1[q].push_back(std::min(it.r1, a0 + kSigRows));
-        }
-      SigmaLevelItems& li = h->lev_items[q];
-      li.count = int32_t(il[q].size());
-      up.add(&li.leaf, il[q]);
-      up.add(&li.r0, ir0[q]);
-      up.add(&li.a0, ia0[q]);
-      up.add(&li.a1, ia1[q]);
+      upload_batch(h, up, &h->lev[q], P.level_batch[q], prec == RSD_PREC_FP32, !h->gam_level[q]);
+      items(P.level_sigma[q], false, &deep[q], &h->lev_items[q]);
+      if (h->gam_level[q]) items(P.level_sigma_own[q], true, &own[q], &h->lev_own_items[q]);
     }
     // the caller's CSR structure on the device (copied when given on the host)
     const int64_t* d_rp = csr->row_ptr;
@@ -506,6 +519,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->nvec = 1;
     size_t part_bytes = std::max<size_t>(8, symv_part_bytes(h->leaf));
     for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
+    // (levels solved matrix-free have num_items = 0: no symmetric product)
     h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     up.done(h);
@@ -544,7 +558,9 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     sym_invert_scratch_bytes(h->leaf, group_for(h, h->leaf), &pb, &cb);
     need_p = pb;
     need_c = cb;
-    for (const auto& L : h->lev) {
+    for (size_t q = 0; q < h->lev.size(); ++q) {
+      if (h->gam_level[q]) continue;   // no dense factor at the levels solved matrix-free
+      const DevBatch& L = h->lev[q];
       sym_invert_scratch_bytes(L, group_for(h, L), &pb, &cb);
       need_p = std::max(need_p, pb);
       need_c = std::max(need_c, cb);
@@ -564,6 +580,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     }
     int32_t* iflags = h->flags + P.leaf_node.size();
     for (size_t q = 0; q < h->lev.size(); ++q) {
+      if (h->gam_level[q]) continue;   // S~ is applied matrix-free (Alg. 1), never formed
       {
         Timer tm(h, RSD_T_IFACE_ASSEMBLY, s);
         int32_t maxn = 0;
@@ -576,7 +593,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
                                            P.n_leaf, s),
                   "schur assembly");
       }
-      if (!h->gam_level[q]) {   // gamma levels keep S~ itself for the inner GMRES
+      {
         Timer tm(h, RSD_T_IFACE_INVERSE, s);
         invert_batch(h, h->lev[q], pbuf, cbuf, bbuf, iflags + P.level_iface_begin[q],
                      P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, s);
@@ -620,6 +637,36 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
 
 namespace {
 
+// u = gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every interface
+// t of level q and nv vectors (Section 3.1, inexact interface solve); g is read from and
+// u written to z at the level's rows.  Each product w = S~_t v is Alg. 1's S-MatVec with
+// the Sigma blocks: the own-node columns of K_tt, minus Sigma_l[I_t, I_t] v over every
+// leaf adjacent to t (the e buffer is free again once the level's g is formed).
+void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
+  const Plan& P = h->P;
+  const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
+  const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
+  const DevBatch& b = h->lev[q];
+  const int g = h->opt.gamma;
+  hip_check(h, launch_gm_start(b, g, nv, z, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
+                               h->gm_stop, s), "gmres start");
+  for (int j = 0; j < g; ++j) {
+    const double* vj = h->gm_V + int64_t(j) * nv * n;
+    double* w = h->gm_V + int64_t(j + 1) * nv * n;
+    hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segB, h->segC, h->prow, h->ell_off, h->ell_col,
+                                 h->ell_val, vj, nullptr, 1.0, w, nv, n, h->xil, r0, r1, s),
+              "S-MatVec K_tt");
+    hip_check(h, launch_sigma_level(h->lev_own_items[q], h->sigma, h->sigma_fp32, h->sig_off_d,
+                                    h->B_off, h->B, vj, h->e, nv, n, nB, s), "S-MatVec Sigma");
+    hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos, h->B_off,
+                                  h->e, w, nv, n, nB, -1.0, s), "S-MatVec sum");
+    hip_check(h, launch_gm_orth(b, g, nv, j, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
+                                h->gm_stop, s), "gmres step");
+  }
+  hip_check(h, launch_gm_finish(b, g, nv, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps, z, s),
+            "gmres finish");
+}
+
 // z = M^{-1} r on internal-order vectors (Alg. 2 with exact interface solves):
 // every sub-domain solve; per interface level from the deepest: right-hand side g
 // of eq. (schur) -- the interface part of r minus the couplings to the already
@@ -652,14 +699,12 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
                                    h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, nl, r0,
                                    s), "level rhs");   // deeper levels come first: [nl, r0)
       hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos,
-                                    h->B_off, h->e, z, nv, n, nB, s), "level adjacency");
+                                    h->B_off, h->e, z, nv, n, nB, 1.0, s), "level adjacency");
     }
     {
       Timer tm(h, RSD_T_IFACE_APPLY, s);
       if (h->gam_level[q])      // u = gamma GMRES steps on S~ u = g (paper mode)
-        hip_check(h, launch_gamma_solve(h->lev[q], h->opt.gamma, nv, z, n, h->gm_V, h->gm_beta,
-                                        h->gm_H, h->gm_steps, h->gm_stop, h->sympart, s),
-                  "interface gamma solve");
+        gamma_solve(h, q, nv, z, s);
       else                      // u = S~^{-1} g (tiles hold -S~^{-1})
         hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, nv, n, s),
                   "interface symv");

@@ -47,7 +47,8 @@ struct rsd_ctx {
   int sigma_fp32 = 0;
   rsd::DevBatch leaf{};
   std::vector<rsd::DevBatch> lev;
-  std::vector<rsd::SigmaLevelItems> lev_items;
+  std::vector<rsd::SigmaLevelItems> lev_items;       // Sigma products against deeper levels
+  std::vector<rsd::SigmaLevelItems> lev_own_items;   // and against the level itself (gamma)
   int32_t* flags = nullptr;  // one per leaf, then one per interface
   hipStream_t aux = nullptr;          // look-ahead stream of the inversions
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;

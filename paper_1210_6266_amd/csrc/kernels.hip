@@ -1410,17 +1410,18 @@ __global__ __launch_bounds__(kBlock) void k_schur_assemble(
 // ================================================================ apply helpers
 template <typename S, int KV>
 __global__ __launch_bounds__(kBlock) void k_sigma_level(
-    const int32_t* __restrict__ it_leaf, const int32_t* __restrict__ it_r0,
-    const int32_t* __restrict__ it_a0, const int32_t* __restrict__ it_a1,
+    const int32_t* __restrict__ it_leaf, const int32_t* __restrict__ it_c0,
+    const int32_t* __restrict__ it_c1, const int32_t* __restrict__ it_a0,
+    const int32_t* __restrict__ it_a1,
     const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
     const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
     const double* __restrict__ z, double* __restrict__ e, int nv, int64_t ldz, int64_t lde) {
-  // e_l[a] = sum_{b < r0} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= kSigRows),
+  // e_l[a] = sum_{c0 <= b < c1} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1) (<= kSigRows),
   // for nv <= KV vectors (u_k = z + k ldz, e_k = e + k lde).  Sigma_l is symmetric: row
   // a is read as column a (contiguous in b), one wave per row, the gathered u staged in
   // LDS; each row's sum is taken in a fixed order that does not depend on KV.
   const int it = blockIdx.x;
-  const int l = it_leaf[it], r0 = it_r0[it], a0 = it_a0[it], a1 = it_a1[it];
+  const int l = it_leaf[it], c0 = it_c0[it], c1 = it_c1[it], a0 = it_a0[it], a1 = it_a1[it];
   const int64_t m = B_off[l + 1] - B_off[l];
   const S* Sg = sigma + sig_off[l];
   const int32_t* Bl = B + B_off[l];
@@ -1433,8 +1434,8 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
   for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int k = 0; k < KV; ++k) acc[q][k] = 0.0;
-  for (int b0 = 0; b0 < r0; b0 += kSigStage) {
-    const int nb = min(kSigStage, r0 - b0);
+  for (int b0 = c0; b0 < c1; b0 += kSigStage) {
+    const int nb = min(kSigStage, c1 - b0);
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += kBlock) {
       const int32_t gi = Bl[b0 + b];
@@ -1478,13 +1479,14 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     }
 }
 
-// z_v[r] += sum over the leaves l adjacent to interface dof r of e_l[position of r in
-// B_l], rows r in [row0, row0 + nrows), for nv vectors (z_v = z + v ldz, e_v = e + v lde)
+// z_v[r] += alpha * sum over the leaves l adjacent to interface dof r of e_l[position of
+// r in B_l], rows r in [row0, row0 + nrows), for nv vectors (z_v = z + v ldz, e_v = e +
+// v lde)
 __global__ __launch_bounds__(kBlock) void k_level_adj(
     int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* __restrict__ adj_ptr,
     const int32_t* __restrict__ adj_leaf, const int32_t* __restrict__ adj_pos,
     const int64_t* __restrict__ B_off, const double* __restrict__ e, double* __restrict__ z,
-    int nv, int64_t ldz, int64_t lde) {
+    int nv, int64_t ldz, int64_t lde, double alpha) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int v = blockIdx.y;                    // vector
   if (i >= nrows || v >= nv) return;
@@ -1492,7 +1494,8 @@ __global__ __launch_bounds__(kBlock) void k_level_adj(
   const int64_t p = r - n_leaf;
   const double* ev = e + v * lde;
   double s = z[v * ldz + r];
-  for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k) s += ev[B_off[adj_leaf[k]] + adj_pos[k]];
+  for (int64_t k = adj_ptr[p]; k < adj_ptr[p + 1]; ++k)
+    s += alpha * ev[B_off[adj_leaf[k]] + adj_pos[k]];
   z[v * ldz + r] = s;
 }
 
@@ -1600,9 +1603,9 @@ __global__ void k_axpy_ratio(const double* __restrict__ x, const double* __restr
 
 
 // ================================================================ inexact interface solves
-// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every matrix m of a
-// level batch (S~_t assembled in the tiles, not inverted) and every vector k: one block
-// per (m, k).  Basis vector j of vector k is V + (j nv + k) ld, used at the matrix's rows
+// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every system m of a
+// level and every vector k: one block per (m, k); the products w = S~ v_j between the
+// steps are the caller's (Alg. 1's operator, applied matrix-free).  Basis vector j of vector k is V + (j nv + k) ld, used at the matrix's rows
 // vec_off[m] .. vec_off[m] + n[m]; slot = k count + m indexes the per-system state:
 // beta = ||g||, the (gamma + 1) x gamma Hessenberg matrix H (column-major), the steps
 // taken and a stop flag (happy breakdown, or g = 0).
@@ -1680,7 +1683,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_orth(
 
 // u = V_k y with y the least-squares solution of min || beta e1 - H y || over the
 // steps taken (Givens QR of the Hessenberg matrix), written over g in z.
-constexpr int kGammaMax = 64;
+constexpr int kGammaMax = kGammaMaxSteps;
 __global__ __launch_bounds__(kBlock) void k_gm_finish(
     const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off, int count,
     int64_t ld, int nv, int gamma, const double* __restrict__ V,
@@ -1970,7 +1973,7 @@ hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int 
     const double* zb = z + v0 * ldz;
     double* eb = e + v0 * lde;
 #define RSD_SIGL(S, KV)                                                                     \
-  k_sigma_level<S, KV><<<it.count, kBlock, 0, s>>>(it.leaf, it.r0, it.a0, it.a1,         \
+  k_sigma_level<S, KV><<<it.count, kBlock, 0, s>>>(it.leaf, it.c0, it.c1, it.a0, it.a1,  \
                                                    (const S*)sigma, sig_off, B_off, B, zb, eb, \
                                                    c, ldz, lde)
     if (sigma_fp32) {
@@ -1986,32 +1989,41 @@ hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int 
 hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* adj_ptr,
                             const int32_t* adj_leaf, const int32_t* adj_pos, const int64_t* B_off,
                             const double* e, double* z, int nv, int64_t ldz, int64_t lde,
-                            hipStream_t s) {
+                            double alpha, hipStream_t s) {
   if (nrows <= 0 || nv <= 0) return hipSuccess;
   k_level_adj<<<dim3(blocks_for(nrows), nv), kBlock, 0, s>>>(row0, nrows, n_leaf, adj_ptr,
                                                              adj_leaf, adj_pos, B_off, e, z, nv,
-                                                             ldz, lde);
+                                                             ldz, lde, alpha);
   return hipGetLastError();
 }
 
-hipError_t launch_gamma_solve(const DevBatch& b, int gamma, int nv, double* z, int64_t ld,
-                              double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
-                              void* part, hipStream_t s) {
+hipError_t launch_gm_start(const DevBatch& b, int gamma, int nv, const double* z, int64_t ld,
+                           double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
+                           hipStream_t s) {
   if (b.count == 0 || nv <= 0) return hipSuccess;
   if (gamma < 1 || gamma > kGammaMax) return hipErrorInvalidValue;
-  const dim3 grid(unsigned(b.count), unsigned(nv));
-  k_gm_start<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, z, ld, nv, gamma, V, beta, H, steps,
-                                     stop);
-  for (int j = 0; j < gamma; ++j) {
-    // w = S~ v_j into basis slot j + 1 (the tiles hold S~ itself)
-    hipError_t e = launch_symv(b, V + int64_t(j) * nv * ld, part, 1.0, nullptr,
-                               V + int64_t(j + 1) * nv * ld, nv, ld, s);
-    if (e != hipSuccess) return e;
-    k_gm_orth<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, j, ld, nv, gamma, V, beta, H,
-                                      steps, stop);
-  }
-  k_gm_finish<<<grid, kBlock, 0, s>>>(b.n, b.vec_off, b.count, ld, nv, gamma, V, beta, H, steps,
-                                      z);
+  k_gm_start<<<dim3(unsigned(b.count), unsigned(nv)), kBlock, 0, s>>>(
+      b.n, b.vec_off, b.count, z, ld, nv, gamma, V, beta, H, steps, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_orth(const DevBatch& b, int gamma, int nv, int j, int64_t ld, double* V,
+                          const double* beta, double* H, int32_t* steps, int32_t* stop,
+                          hipStream_t s) {
+  if (b.count == 0 || nv <= 0) return hipSuccess;
+  if (gamma < 1 || gamma > kGammaMax || j < 0 || j >= gamma) return hipErrorInvalidValue;
+  k_gm_orth<<<dim3(unsigned(b.count), unsigned(nv)), kBlock, 0, s>>>(
+      b.n, b.vec_off, b.count, j, ld, nv, gamma, V, beta, H, steps, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_finish(const DevBatch& b, int gamma, int nv, int64_t ld, const double* V,
+                            const double* beta, const double* H, const int32_t* steps,
+                            double* z, hipStream_t s) {
+  if (b.count == 0 || nv <= 0) return hipSuccess;
+  if (gamma < 1 || gamma > kGammaMax) return hipErrorInvalidValue;
+  k_gm_finish<<<dim3(unsigned(b.count), unsigned(nv)), kBlock, 0, s>>>(
+      b.n, b.vec_off, b.count, ld, nv, gamma, V, beta, H, steps, z);
   return hipGetLastError();
 }
 

@@ -125,10 +125,12 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
 // rows of Sigma_l per work item of the level product (4 waves, kSigRows / 4 rows each)
 constexpr int kSigRows = 16;
 
+// item: rows [a0, a1) of Sigma_l (leaf l) against the columns [c0, c1) of B_l
 struct SigmaLevelItems {
   int32_t count = 0;
   const int32_t* leaf = nullptr;
-  const int32_t* r0 = nullptr;
+  const int32_t* c0 = nullptr;
+  const int32_t* c1 = nullptr;
   const int32_t* a0 = nullptr;
   const int32_t* a1 = nullptr;
 };
@@ -137,20 +139,31 @@ hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int 
                               const int64_t* sig_off, const int64_t* B_off, const int32_t* B,
                               const double* z, double* e, int nv, int64_t ldz, int64_t lde,
                               hipStream_t s);
-// z[r] += sum of e over the leaves adjacent to interface dof r (rows [row0, row0 + nrows))
+// z[r] += alpha * sum of e over the leaves adjacent to interface dof r (rows
+// [row0, row0 + nrows))
 hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const int64_t* adj_ptr,
                             const int32_t* adj_leaf, const int32_t* adj_pos, const int64_t* B_off,
                             const double* e, double* z, int nv, int64_t ldz, int64_t lde,
-                            hipStream_t s);
+                            double alpha, hipStream_t s);
 
-// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every matrix of the
-// level batch b (tiles holding S~_t, not inverted) and nv vectors: g is read from and u
-// written to z_k = z + k ld at each matrix's rows.  Scratch: V (gamma + 1) * nv * ld
-// doubles (basis), beta nv * count doubles, H nv * count * (gamma + 1) * gamma doubles,
-// steps and stop nv * count ints, part symv_part_bytes(b).  gamma in 1..64.
-hipError_t launch_gamma_solve(const DevBatch& b, int gamma, int nv, double* z, int64_t ld,
-                              double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
-                              void* part, hipStream_t s);
+// gamma steps of unpreconditioned GMRES from zero on S~_t u = g for every system t of a
+// level (the batch b gives each system's rows: n, vec_off) and nv vectors.  Basis vector
+// j of vector k is V + (j nv + k) ld ((gamma + 1) * nv * ld doubles); per system and
+// vector: beta, the (gamma + 1) x gamma Hessenberg matrix H, steps and stop flags
+// (nv * count entries each).  start: beta = ||g||, v_0 = g / beta (g at z_k's rows).
+// Between orth steps the caller writes w = S~ v_j into basis slot j + 1; orth(j):
+// modified Gram-Schmidt, norm, happy-breakdown test, normalisation.  finish: the
+// least-squares solution y and u = V y written over g.  gamma in 1..64.
+constexpr int kGammaMaxSteps = 64;
+hipError_t launch_gm_start(const DevBatch& b, int gamma, int nv, const double* z, int64_t ld,
+                           double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
+                           hipStream_t s);
+hipError_t launch_gm_orth(const DevBatch& b, int gamma, int nv, int j, int64_t ld, double* V,
+                          const double* beta, double* H, int32_t* steps, int32_t* stop,
+                          hipStream_t s);
+hipError_t launch_gm_finish(const DevBatch& b, int gamma, int nv, int64_t ld, const double* V,
+                            const double* beta, const double* H, const int32_t* steps,
+                            double* z, hipStream_t s);
 
 // ---- Krylov ----------------------------------------------------------------------------------
 // Each call acts on nb_rhs independent right-hand sides: operand i of right-hand side

@@ -467,6 +467,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
 
   // ---- apply schedule: Sigma products per level --------------------------------------
   P->level_sigma.assign(NL, {});
+  P->level_sigma_own.assign(NL, {});
   P->sum_sigma_apply = 0;
   for (int32_t q = 0; q < NL; ++q)
     for (int32_t l = 0; l < L; ++l) {
@@ -478,6 +479,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
         P->level_sigma[q].push_back({l, r0, r1});
         P->sum_sigma_apply += int64_t(r1 - r0) * r0;
       }
+      if (r1 > r0) P->level_sigma_own[q].push_back({l, r0, r1});
     }
 
   // ---- dense batches ---------------------------------------------------------------

@@ -45,7 +45,7 @@ struct SymBatch {
   int64_t num_items = 0;
 };
 
-struct LevelSigmaItem {            // Sigma_l[rows r0..r1, cols 0..r0] of one leaf
+struct LevelSigmaItem {            // rows r0..r1 of Sigma_l (positions in B_l) of one leaf
   int32_t leaf, r0, r1;
 };
 
@@ -106,7 +106,8 @@ struct Plan {
   int64_t w_total = 0;
 
   // apply: Sigma products per level (processing order)
-  std::vector<std::vector<LevelSigmaItem>> level_sigma;
+  std::vector<std::vector<LevelSigmaItem>> level_sigma;       // cols 0..r0: deeper levels
+  std::vector<std::vector<LevelSigmaItem>> level_sigma_own;   // cols r0..r1: the level itself
 
   SymBatch leaf_batch;
   std::vector<SymBatch> level_batch;         // per level
