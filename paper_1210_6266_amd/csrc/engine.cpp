@@ -315,6 +315,8 @@ void ensure_gamma(rsd_ctx* h, int nv) {
   dfree(h, h->gm_H);
   dfree(h, h->gm_steps);
   dfree(h, h->gm_stop);
+  dfree(h, h->gm_part);
+  dfree(h, h->gm_coef);
   int32_t maxc = 1;
   for (const DevBatch& b : h->lev) maxc = std::max(maxc, b.count);
   const size_t g = size_t(h->opt.gamma), sl = size_t(nv) * size_t(maxc);
@@ -323,6 +325,8 @@ void ensure_gamma(rsd_ctx* h, int nv) {
   h->gm_H = dalloc<double>(h, sl * (g + 1) * g);
   h->gm_steps = dalloc<int32_t>(h, sl);
   h->gm_stop = dalloc<int32_t>(h, sl);
+  h->gm_part = dalloc<double>(h, size_t(nv) * size_t(std::max(1, h->gm_max_items)) * (g + 1));
+  h->gm_coef = dalloc<double>(h, sl * (g + 2));
 }
 
 void fill_analysis(const Plan& P, rsd_analysis* a) {
@@ -486,6 +490,35 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       items(P.level_sigma[q], false, &deep[q], &h->lev_items[q]);
       if (h->gam_level[q]) items(P.level_sigma_own[q], true, &own[q], &h->lev_own_items[q]);
     }
+    // work items of the chunked inner GMRES: levels with a system above one chunk
+    h->gm_lev.assign(NL, rsd_ctx::GmLevel());
+    struct GmLists { std::vector<int32_t> sys, first; std::vector<int64_t> b, e; };
+    std::vector<GmLists> gml(NL);
+    for (int q = 0; q < NL; ++q) {
+      if (!h->gam_level[q]) continue;
+      const SymBatch& sb = P.level_batch[q];
+      int32_t maxn = 0;
+      for (int32_t v : sb.n) maxn = std::max(maxn, v);
+      if (maxn <= kGmChunk) continue;          // one workgroup per system
+      GmLists& L = gml[q];
+      for (int32_t m = 0; m < sb.count; ++m) {
+        L.first.push_back(int32_t(L.sys.size()));
+        for (int64_t c = 0; c < sb.n[m]; c += kGmChunk) {
+          L.sys.push_back(m);
+          L.b.push_back(sb.vec_off[m] + c);
+          L.e.push_back(sb.vec_off[m] + std::min<int64_t>(sb.n[m], c + kGmChunk));
+        }
+      }
+      L.first.push_back(int32_t(L.sys.size()));
+      rsd_ctx::GmLevel& G = h->gm_lev[q];
+      G.chunked = true;
+      G.nitems = int32_t(L.sys.size());
+      up.add(&G.item_sys, L.sys);
+      up.add(&G.item_b, L.b);
+      up.add(&G.item_e, L.e);
+      up.add(&G.sys_first, L.first);
+      h->gm_max_items = std::max(h->gm_max_items, G.nitems);
+    }
     // the caller's CSR structure on the device (copied when given on the host)
     const int64_t* d_rp = csr->row_ptr;
     const int32_t* d_ci = csr->col_idx;
@@ -648,8 +681,29 @@ void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
   const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
   const DevBatch& b = h->lev[q];
   const int g = h->opt.gamma;
-  hip_check(h, launch_gm_start(b, g, nv, z, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
-                               h->gm_stop, s), "gmres start");
+  const rsd_ctx::GmLevel& G = h->gm_lev[q];
+  GmArgs a;                                   // chunked kernels (large systems)
+  a.count = b.count;
+  a.nitems = G.nitems;
+  a.nv = nv;
+  a.gamma = g;
+  a.ld = n;
+  a.item_sys = G.item_sys;
+  a.item_b = G.item_b;
+  a.item_e = G.item_e;
+  a.sys_first = G.sys_first;
+  a.V = h->gm_V;
+  a.beta = h->gm_beta;
+  a.H = h->gm_H;
+  a.steps = h->gm_steps;
+  a.stop = h->gm_stop;
+  a.part = h->gm_part;
+  a.coef = h->gm_coef;
+  if (G.chunked)
+    hip_check(h, launch_gmc(a, 0, 0, z, nullptr, s), "gmres start");
+  else
+    hip_check(h, launch_gm_start(b, g, nv, z, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
+                                 h->gm_stop, s), "gmres start");
   for (int j = 0; j < g; ++j) {
     const double* vj = h->gm_V + int64_t(j) * nv * n;
     double* w = h->gm_V + int64_t(j + 1) * nv * n;
@@ -660,11 +714,17 @@ void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
                                     h->B_off, h->B, vj, h->e, nv, n, nB, s), "S-MatVec Sigma");
     hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos, h->B_off,
                                   h->e, w, nv, n, nB, -1.0, s), "S-MatVec sum");
-    hip_check(h, launch_gm_orth(b, g, nv, j, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
-                                h->gm_stop, s), "gmres step");
+    if (G.chunked)
+      hip_check(h, launch_gmc(a, 1, j, nullptr, nullptr, s), "gmres step");
+    else
+      hip_check(h, launch_gm_orth(b, g, nv, j, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
+                                  h->gm_stop, s), "gmres step");
   }
-  hip_check(h, launch_gm_finish(b, g, nv, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps, z, s),
-            "gmres finish");
+  if (G.chunked)
+    hip_check(h, launch_gmc(a, 2, 0, nullptr, z, s), "gmres finish");
+  else
+    hip_check(h, launch_gm_finish(b, g, nv, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps, z, s),
+              "gmres finish");
 }
 
 // z = M^{-1} r on internal-order vectors (Alg. 2 with exact interface solves):

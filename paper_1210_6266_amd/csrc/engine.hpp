@@ -64,6 +64,17 @@ struct rsd_ctx {
   bool any_gamma = false;
   double *gm_V = nullptr, *gm_beta = nullptr, *gm_H = nullptr;
   int32_t *gm_steps = nullptr, *gm_stop = nullptr;
+  // levels with systems larger than one chunk: work items of the chunked kernels
+  struct GmLevel {
+    bool chunked = false;
+    int32_t nitems = 0;
+    int32_t* item_sys = nullptr;
+    int64_t *item_b = nullptr, *item_e = nullptr;
+    int32_t* sys_first = nullptr;
+  };
+  std::vector<GmLevel> gm_lev;
+  int32_t gm_max_items = 0;
+  double *gm_part = nullptr, *gm_coef = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
 
   // Krylov work space (grown on demand)

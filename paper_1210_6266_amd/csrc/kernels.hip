@@ -1732,6 +1732,176 @@ __global__ __launch_bounds__(kBlock) void k_gm_finish(
   }
 }
 
+// ---- the same steps for levels with large systems: each system's rows are cut into
+// chunks of at most kGmChunk entries (work items); a (chunk, vector) pair is one
+// workgroup, so one large interface spreads over the whole GPU.  Gram-Schmidt is
+// classical and done twice (two reductions per step instead of j + 1); every sum is a
+// fixed-order two-pass reduction (per chunk, then per system in chunk order).  The
+// state per (system, vector) slot is that of the one-workgroup kernels above, plus
+// coef[slot][0 .. gamma + 1]: the current projection coefficients, then y; the last
+// entry holds beta (start) or the new norm (step).
+constexpr int kGmPer = kGmChunk / kBlock;       // rows per thread in a chunk
+
+// partial sums of one chunk, mode 0: ||g||^2 of the right-hand side (z); mode 1: the
+// projections v_i . w (i < ncols) of w = basis slot ncols; mode 2: ||w||^2 (w = slot j + 1)
+__global__ __launch_bounds__(kBlock) void k_gmc_dots(GmArgs a, const double* __restrict__ z,
+                                                     int j, int mode) {
+  __shared__ double sh[4];
+  const int it = blockIdx.x, k = blockIdx.y;
+  const int m = a.item_sys[it];
+  const int64_t slot = int64_t(k) * a.count + m;
+  if (mode != 0 && (a.stop[slot] || a.steps[slot] != j)) return;
+  const int64_t b = a.item_b[it], e = a.item_e[it];
+  const double* w = mode == 0 ? z + k * a.ld : a.V + (int64_t(j + 1) * a.nv + k) * a.ld;
+  double wv[kGmPer];
+#pragma unroll
+  for (int u = 0; u < kGmPer; ++u) {
+    const int64_t r = b + threadIdx.x + int64_t(u) * kBlock;
+    wv[u] = r < e ? w[r] : 0.0;
+  }
+  double* out = a.part + (int64_t(k) * a.nitems + it) * (a.gamma + 1);
+  const int ncols = mode == 1 ? j + 1 : 1;
+  for (int i = 0; i < ncols; ++i) {
+    const double* vi = mode == 1 ? a.V + (int64_t(i) * a.nv + k) * a.ld : nullptr;
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kGmPer; ++u) {
+      const int64_t r = b + threadIdx.x + int64_t(u) * kBlock;
+      if (r < e) s += (mode == 1 ? vi[r] : wv[u]) * wv[u];
+    }
+    const double t = block_allsum(s, sh);
+    if (threadIdx.x == 0) out[i] = t;
+  }
+}
+
+// per slot: sum the chunk partials in chunk order.  mode 0: beta, v_0 scale, reset of the
+// state; mode 1 / 2: first / second Gram-Schmidt pass (H column j set / incremented,
+// coefficients for the update); mode 3: the new norm, steps, happy-breakdown test.
+__global__ void k_gmc_reduce(GmArgs a, int j, int mode) {
+  const int m = blockIdx.x, k = blockIdx.y;
+  const int64_t slot = int64_t(k) * a.count + m;
+  const int L = a.gamma + 1;
+  double* Hs = a.H + slot * L * a.gamma;
+  double* cf = a.coef + slot * (L + 1);
+  const int f = a.sys_first[m], l = a.sys_first[m + 1];
+  const double* part = a.part + int64_t(k) * a.nitems * L;
+  if (mode == 0) {
+    for (int i = threadIdx.x; i < L * a.gamma; i += blockDim.x) Hs[i] = 0.0;
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int it = f; it < l; ++it) s += part[int64_t(it) * L];
+      const double b = sqrt(s);
+      a.beta[slot] = b;
+      a.steps[slot] = 0;
+      a.stop[slot] = b > 0.0 ? 0 : 1;
+      cf[L] = b;
+    }
+    return;
+  }
+  if (a.stop[slot] || a.steps[slot] != j) return;
+  if (mode == 3) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int it = f; it < l; ++it) s += part[int64_t(it) * L];
+      const double hn = sqrt(s);
+      Hs[j + 1 + j * L] = hn;
+      cf[L] = hn;
+      a.steps[slot] = j + 1;
+      if (hn <= 1e-14 * a.beta[slot]) a.stop[slot] = 1;
+    }
+    return;
+  }
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    double s = 0.0;
+    for (int it = f; it < l; ++it) s += part[int64_t(it) * L + i];
+    Hs[i + j * L] = mode == 1 ? s : Hs[i + j * L] + s;
+    cf[i] = s;
+  }
+}
+
+// mode 0: v_0 = g / beta (0 when beta = 0); mode 1: w -= sum_{i <= j} coef_i v_i
+// (active slots of step j); mode 2: w /= norm unless the slot stopped at step j
+__global__ __launch_bounds__(kBlock) void k_gmc_update(GmArgs a, const double* __restrict__ z,
+                                                       int j, int mode) {
+  const int it = blockIdx.x, k = blockIdx.y;
+  const int m = a.item_sys[it];
+  const int64_t slot = int64_t(k) * a.count + m;
+  const int L = a.gamma + 1;
+  const double* cf = a.coef + slot * (L + 1);
+  const int64_t b = a.item_b[it], e = a.item_e[it];
+  if (mode == 0) {
+    const double bt = cf[L];
+    const double* g = z + k * a.ld;
+    double* v0 = a.V + int64_t(k) * a.ld;
+    for (int64_t r = b + threadIdx.x; r < e; r += kBlock) v0[r] = bt > 0.0 ? g[r] / bt : 0.0;
+    return;
+  }
+  double* w = a.V + (int64_t(j + 1) * a.nv + k) * a.ld;
+  if (mode == 1) {
+    if (a.stop[slot] || a.steps[slot] != j) return;
+    for (int64_t r = b + threadIdx.x; r < e; r += kBlock) {
+      double s = w[r];
+      for (int i = 0; i <= j; ++i) s -= cf[i] * a.V[(int64_t(i) * a.nv + k) * a.ld + r];
+      w[r] = s;
+    }
+    return;
+  }
+  if (a.stop[slot] || a.steps[slot] != j + 1) return;
+  const double hn = cf[L];
+  for (int64_t r = b + threadIdx.x; r < e; r += kBlock) w[r] /= hn;
+}
+
+// least squares of each slot (one thread, Givens QR as in k_gm_finish): y into coef
+__global__ void k_gmc_lsq(GmArgs a) {
+  __shared__ double R[(kGammaMax + 1) * kGammaMax];
+  const int m = blockIdx.x, k = blockIdx.y;
+  const int64_t slot = int64_t(k) * a.count + m;
+  const int L = a.gamma + 1;
+  const double* Hs = a.H + slot * L * a.gamma;
+  for (int i = threadIdx.x; i < L * a.gamma; i += blockDim.x) R[i] = Hs[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double* y = a.coef + slot * (L + 1);
+  const int ks = a.beta[slot] > 0.0 ? a.steps[slot] : 0;
+  for (int i = 0; i <= ks; ++i) y[i] = i == 0 ? a.beta[slot] : 0.0;
+  for (int c = 0; c < ks; ++c) {
+    const double p = R[c + c * L], q = R[c + 1 + c * L];
+    const double d = hypot(p, q);
+    const double cs = d > 0.0 ? p / d : 1.0, sn = d > 0.0 ? q / d : 0.0;
+    for (int cc = c; cc < ks; ++cc) {
+      const double t0 = R[c + cc * L], t1 = R[c + 1 + cc * L];
+      R[c + cc * L] = cs * t0 + sn * t1;
+      R[c + 1 + cc * L] = -sn * t0 + cs * t1;
+    }
+    const double g0 = y[c], g1 = y[c + 1];
+    y[c] = cs * g0 + sn * g1;
+    y[c + 1] = -sn * g0 + cs * g1;
+  }
+  for (int c = ks - 1; c >= 0; --c) {
+    double v = y[c];
+    for (int cc = c + 1; cc < ks; ++cc) v -= R[c + cc * L] * y[cc];
+    const double dg = R[c + c * L];
+    y[c] = dg != 0.0 ? v / dg : 0.0;
+  }
+}
+
+// u = V_k y over a chunk, written over g in z
+__global__ __launch_bounds__(kBlock) void k_gmc_combine(GmArgs a, double* __restrict__ z) {
+  const int it = blockIdx.x, k = blockIdx.y;
+  const int m = a.item_sys[it];
+  const int64_t slot = int64_t(k) * a.count + m;
+  const int L = a.gamma + 1;
+  const double* y = a.coef + slot * (L + 1);
+  const int ks = a.beta[slot] > 0.0 ? a.steps[slot] : 0;
+  const int64_t b = a.item_b[it], e = a.item_e[it];
+  double* u = z + k * a.ld;
+  for (int64_t r = b + threadIdx.x; r < e; r += kBlock) {
+    double s = 0.0;
+    for (int c = 0; c < ks; ++c) s += y[c] * a.V[(int64_t(c) * a.nv + k) * a.ld + r];
+    u[r] = s;
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
@@ -2014,6 +2184,34 @@ hipError_t launch_gm_orth(const DevBatch& b, int gamma, int nv, int j, int64_t l
   if (gamma < 1 || gamma > kGammaMax || j < 0 || j >= gamma) return hipErrorInvalidValue;
   k_gm_orth<<<dim3(unsigned(b.count), unsigned(nv)), kBlock, 0, s>>>(
       b.n, b.vec_off, b.count, j, ld, nv, gamma, V, beta, H, steps, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmc(const GmArgs& a, int op, int j, const double* zin, double* zout,
+                      hipStream_t s) {
+  if (a.count == 0 || a.nv <= 0 || a.nitems == 0) return hipSuccess;
+  if (a.gamma < 1 || a.gamma > kGammaMax || j < 0 || j >= a.gamma) return hipErrorInvalidValue;
+  const dim3 gi(unsigned(a.nitems), unsigned(a.nv)), gs(unsigned(a.count), unsigned(a.nv));
+  switch (op) {
+    case 0:   // start: beta = ||g||, v_0 = g / beta
+      k_gmc_dots<<<gi, kBlock, 0, s>>>(a, zin, 0, 0);
+      k_gmc_reduce<<<gs, 64, 0, s>>>(a, 0, 0);
+      k_gmc_update<<<gi, kBlock, 0, s>>>(a, zin, 0, 0);
+      break;
+    case 1:   // step j after w = S~ v_j: classical Gram-Schmidt twice, norm, normalisation
+      for (int pass = 1; pass <= 2; ++pass) {
+        k_gmc_dots<<<gi, kBlock, 0, s>>>(a, nullptr, j, 1);
+        k_gmc_reduce<<<gs, 64, 0, s>>>(a, j, pass);
+        k_gmc_update<<<gi, kBlock, 0, s>>>(a, nullptr, j, 1);
+      }
+      k_gmc_dots<<<gi, kBlock, 0, s>>>(a, nullptr, j, 2);
+      k_gmc_reduce<<<gs, 64, 0, s>>>(a, j, 3);
+      k_gmc_update<<<gi, kBlock, 0, s>>>(a, nullptr, j, 2);
+      break;
+    default:  // finish: least squares, u = V y
+      k_gmc_lsq<<<gs, 64, 0, s>>>(a);
+      k_gmc_combine<<<gi, kBlock, 0, s>>>(a, zout);
+  }
   return hipGetLastError();
 }
 

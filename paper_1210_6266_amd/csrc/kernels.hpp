@@ -155,6 +155,29 @@ hipError_t launch_level_adj(int64_t row0, int64_t nrows, int64_t n_leaf, const i
 // modified Gram-Schmidt, norm, happy-breakdown test, normalisation.  finish: the
 // least-squares solution y and u = V y written over g.  gamma in 1..64.
 constexpr int kGammaMaxSteps = 64;
+// Levels whose systems are larger than one chunk use the chunked kernels (launch_gmc):
+// work items of at most kGmChunk rows of one system, any number per system.
+constexpr int kGmChunk = 4096;
+struct GmArgs {
+  int32_t count = 0, nitems = 0, nv = 0, gamma = 0;
+  int64_t ld = 0;
+  const int32_t* item_sys = nullptr;   // system of each work item
+  const int64_t* item_b = nullptr;     // rows [item_b, item_e) (internal positions)
+  const int64_t* item_e = nullptr;
+  const int32_t* sys_first = nullptr;  // items of system m: sys_first[m] .. sys_first[m + 1]
+  double* V = nullptr;                 // basis, as for the one-workgroup kernels
+  double* beta = nullptr;
+  double* H = nullptr;
+  int32_t* steps = nullptr;
+  int32_t* stop = nullptr;
+  double* part = nullptr;              // nv * nitems * (gamma + 1) chunk partials
+  double* coef = nullptr;              // nv * count * (gamma + 2): coefficients, then y
+};
+// op 0: start (g from zin); op 1: step j (after w = S~ v_j is in basis slot j + 1);
+// op 2: finish (u into zout).  Same result as the one-workgroup kernels up to rounding
+// (classical Gram-Schmidt twice instead of modified Gram-Schmidt).
+hipError_t launch_gmc(const GmArgs& a, int op, int j, const double* zin, double* zout,
+                      hipStream_t s);
 hipError_t launch_gm_start(const DevBatch& b, int gamma, int nv, const double* z, int64_t ld,
                            double* V, double* beta, double* H, int32_t* steps, int32_t* stop,
                            hipStream_t s);

@@ -149,3 +149,30 @@ def test_gamma_multi_rhs_columns_bitwise(problem_cache):
         xj, _, ij = h.solve(_vec(R[:, j]), rtol=1e-10)
         assert ij[0] == info[j] and np.array_equal(X.cpu().numpy()[:, j], xj.cpu().numpy())
     h.close()
+
+
+def test_gamma_chunked_large_interface():
+    """Root interface of 5,256 dofs (elasticity 24^3, octree of height 1, uneven cuts):
+    above one work chunk (4,096 rows), so the inner GMRES runs on the chunked kernels
+    (classical Gram-Schmidt twice, two-pass sums).  Apply vs the oracle's gamma mode to
+    1e-8, several right-hand sides bitwise, and a hybrid solve to 1e-10."""
+    from workloads import elasticity_problem
+    _log("gamma chunked elasticity 24^3 h=1")
+    p = elasticity_problem(24, 1, 2, nrhs=3)
+    o = RSDOracle(p.K, p.parent, p.dof_node, interface="gamma", gamma=6)
+    R = np.random.default_rng(17).uniform(-1, 1, size=(p.n, 3))
+    h = _handle(p, interface="gamma", gamma=6)
+    Z = h.apply(_cm(R)).cpu().numpy()
+    zo = o.apply(R[:, 0])
+    assert _rel(Z[:, 0], zo) <= 1e-8, _rel(Z[:, 0], zo)
+    for j in range(3):
+        assert np.array_equal(Z[:, j], h.apply(_vec(R[:, j])).cpu().numpy()), j
+    h.close()
+    h = _handle(p, interface="hybrid", gamma=6, dense_max=4000,
+                leaf_prec="fp32", sigma_prec="fp32", iface_prec="fp32")
+    X, st, info = h.solve(_cm(p.b), rtol=1e-10)
+    assert st == 0
+    X = X.cpu().numpy()
+    for j in range(3):
+        assert np.linalg.norm(p.b[:, j] - p.K @ X[:, j]) <= 1e-10 * np.linalg.norm(p.b[:, j])
+    h.close()
