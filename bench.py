@@ -17,9 +17,11 @@ orthogonalisation and residuals in FP64; the plain FP64 variant is timed beside 
 value = solves per second of the mixed variant (1 / time-to-1e-10 including set-up).
 
 Secondary blocks on the same line: the differentiable solve on diffusion 32^3
-(forward + adjoint + gradient per pass) and 3-D elasticity 48^3 on 512 uneven
-sub-domains with 8 right-hand sides solved in lockstep.  `--blocks elasticity48`
-(without `main`) runs only the chosen blocks, for profiling.
+(forward + adjoint + gradient per pass), 3-D elasticity 48^3 on 512 uneven
+sub-domains with 8 right-hand sides solved in lockstep, and Poisson 256^3 on 32,768
+sub-domains with 16 right-hand sides (16-bit sub-domain inverses, matrix-free gamma
+steps on the two largest interface levels).  `--blocks elasticity48` (without
+`main`) runs only the chosen blocks, for profiling.
 """
 from __future__ import annotations
 
@@ -62,10 +64,10 @@ def parse():
                     help="forward+backward passes timed on the 32^3 adjoint workload (0: skip)")
     ap.add_argument("--elasticity-steps", type=int, default=2,
                     help="set-up + 8-RHS solves timed on the 48^3 elasticity workload (0: skip)")
-    ap.add_argument("--blocks", default="main,adjoint32,elasticity48",
+    ap.add_argument("--blocks", default="main,adjoint32,elasticity48,poisson256",
                     help="comma list of what to run: main (the 64^3 diffusion line), adjoint32, "
-                         "elasticity48; without main only the chosen blocks are run and printed "
-                         "(a profiling aid, not the benchmark line)")
+                         "elasticity48, poisson256; without main only the chosen blocks are run "
+                         "and printed (a profiling aid, not the benchmark line)")
     return ap.parse_args()
 
 
@@ -208,6 +210,54 @@ def bench_elasticity(a, dev):
     return elastic
 
 
+def bench_poisson256(a, dev):
+    """256^3 Poisson on 32,768 sub-domains with 16 right-hand sides: one cold pass of
+    set-up + two lockstep groups of FGMRES(30) to 1e-10 (None when skipped; the error
+    text when it fails, so that the benchmark line still prints)."""
+    import torch
+
+    from paper_1210_6266_amd import RSD
+    from workloads import config_problem
+    try:
+        t0 = time.perf_counter()
+        p = config_problem("poisson256", seed=a.seed)
+        gen_s = time.perf_counter() - t0
+        rp, ci, v = p.csr_arrays()
+        d = [torch.as_tensor(t, device=dev) for t in
+             (rp, ci, v, p.parent.astype(np.int32), p.dof_node.astype(np.int32))]
+        B = torch.as_tensor(np.ascontiguousarray(p.b.T), device=dev).t()      # n x 16
+        opts = dict(leaf_prec="bf16", sigma_prec="fp32", iface_prec="fp32", root_prec="fp64",
+                    interface="hybrid", gamma=8, dense_max=12000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = RSD(*d, **opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, st, info = h.solve(B, rtol=1e-10, restart=30, maxit=1000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        # true residuals: every column with the library's FP64 SpMV, column 0 also by scipy
+        R = B - h.spmv(X)
+        rel = (torch.linalg.vector_norm(R, dim=0) / torch.linalg.vector_norm(B, dim=0)).cpu()
+        x0 = X[:, 0].cpu().numpy()
+        rel0 = float(np.linalg.norm(p.b[:, 0] - p.K @ x0) / np.linalg.norm(p.b[:, 0]))
+        dev_bytes = h.stats()["device_bytes"]
+        h.close()
+        return dict(ms_setup=1e3 * (t1 - t0), ms_solve_16rhs=1e3 * (t2 - t1),
+                    solves_per_s=p.b.shape[1] / (t2 - t0), status=int(st),
+                    iterations=[i["iterations"] for i in info],
+                    max_true_relres=float(rel.max()), relres_col0_scipy=rel0,
+                    device_bytes=int(dev_bytes), host_generation_s=gen_s,
+                    options="BF16 sub-domain inverses (formed in FP32), FP32 Sigma and level "
+                            "2-4 interface inverses, levels 0-1 (interfaces > 12,000 dofs) by "
+                            "8 matrix-free GMRES steps, FP64 Krylov; one cold pass",
+                    workload=(f"Poisson Q1 256^3, n = {p.n}, nnz = {p.K.nnz}; octree h = 5: "
+                              "32,768 sub-domains of 343 dofs; 16 right-hand sides U[-1, 1]; "
+                              "two lockstep groups of 8, FGMRES(30) to 1e-10"))
+    except Exception as e:  # a secondary block: report, do not fail the line
+        return dict(error=repr(e))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -225,7 +275,8 @@ def main():
     if "main" not in a.blocks.split(","):
         blocks = set(a.blocks.split(","))
         out = {"adjoint32": bench_adjoint(a, dev) if "adjoint32" in blocks else None,
-               "elasticity48": bench_elasticity(a, dev) if "elasticity48" in blocks else None}
+               "elasticity48": bench_elasticity(a, dev) if "elasticity48" in blocks else None,
+               "poisson256": bench_poisson256(a, dev) if "poisson256" in blocks else None}
         print(json.dumps(out), flush=True)
         return
     p = config_problem("diffusion64", seed=a.seed)
@@ -365,6 +416,7 @@ def main():
     blocks = set(a.blocks.split(","))
     adjoint = bench_adjoint(a, dev) if "adjoint32" in blocks and a.only is None else None
     elastic = bench_elasticity(a, dev) if "elasticity48" in blocks and a.only is None else None
+    big = bench_poisson256(a, dev) if "poisson256" in blocks and a.only is None else None
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -422,6 +474,7 @@ def main():
         "secondary": extra,
         "adjoint32": adjoint,
         "elasticity48": elastic,
+        "poisson256": big,
         "cpu_baseline": cpu,
     }
     if "mixed" in res and "fp64" in res:

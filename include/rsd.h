@@ -69,8 +69,11 @@ typedef struct {
   const int32_t* dof_node;
 } rsd_hierarchy;
 
-/* Storage / arithmetic precision of a class of dense blocks. */
-enum { RSD_PREC_FP64 = 0, RSD_PREC_FP32 = 1 };
+/* Storage / arithmetic precision of a class of dense blocks.  FP16 and BF16 apply to
+ * the sub-domain inverses only (leaf_prec): they are formed in FP32 (the Sigma blocks
+ * too, from the FP32 inverses) and stored in 16 bits for the applies, whose products
+ * accumulate in FP32; the outer FP64 Krylov iteration refines the result. */
+enum { RSD_PREC_FP64 = 0, RSD_PREC_FP32 = 1, RSD_PREC_FP16 = 2, RSD_PREC_BF16 = 3 };
 
 /* How the interface systems S~_t u = g of eq. (schur) are solved inside an apply:
  *   RSD_IFACE_DENSE  -- exactly, with the explicit inverse of the assembled S~_t

@@ -15,6 +15,7 @@ rsd_status fail(rsd_status st, const std::string& msg) {
 }
 
 bool prec_ok(int32_t p) { return p == RSD_PREC_FP64 || p == RSD_PREC_FP32; }
+bool leaf_prec_ok(int32_t p) { return prec_ok(p) || p == RSD_PREC_FP16 || p == RSD_PREC_BF16; }
 
 rsd_status check_inputs(const rsd_csr* csr, const rsd_hierarchy* hier) {
   if (!csr || !hier) return fail(RSD_ERR_INVALID_ARGUMENT, "csr and hierarchy must not be NULL");
@@ -80,7 +81,7 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
   if (opt) {
     if (opt->struct_size != int32_t(sizeof(rsd_options)))
       return fail(RSD_ERR_INVALID_ARGUMENT, "rsd_options.struct_size mismatch");
-    if (!prec_ok(opt->leaf_prec) || !prec_ok(opt->sigma_prec) || !prec_ok(opt->iface_prec) ||
+    if (!leaf_prec_ok(opt->leaf_prec) || !prec_ok(opt->sigma_prec) || !prec_ok(opt->iface_prec) ||
         !prec_ok(opt->root_prec))
       return fail(RSD_ERR_INVALID_ARGUMENT, "unknown precision code");
     if (opt->host_pointers != 0 && opt->host_pointers != 1)

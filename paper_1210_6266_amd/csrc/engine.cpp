@@ -447,7 +447,12 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       h->sigma = dalloc<float>(h, size_t(P.sig_total));
     else
       h->sigma = dalloc<double>(h, size_t(P.sig_total));
-    upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec == RSD_PREC_FP32);
+    upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec != RSD_PREC_FP64);
+    // 16-bit leaves: the apply reads a 16-bit copy of the FP32 inverses
+    h->leaf_elems = P.leaf_batch.total_elems;
+    void* half_tiles = nullptr;
+    const int half = h->opt.leaf_prec == RSD_PREC_FP16 ? 1 : h->opt.leaf_prec == RSD_PREC_BF16 ? 2 : 0;
+    if (half) half_tiles = dalloc<uint16_t>(h, size_t(std::max<int64_t>(1, h->leaf_elems)));
     const int NL = int(P.level_depth.size());
     h->lev.assign(NL, DevBatch());
     h->gam_level.assign(NL, 0);
@@ -535,6 +540,11 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     } else {
       up.commit(h, s);
     }
+    h->leaf_apply = h->leaf;            // (device pointers are set by the commit above)
+    if (half) {
+      h->leaf_apply.half = half;
+      h->leaf_apply.tiles = half_tiles;
+    }
     hip_check(h, launch_permute_csr(n, P.n_leaf, h->perm, h->iperm, d_rp, d_ci, h->prow,
                                     h->skel_lvl_begin, h->skel_own_end, h->pcol, h->pmap,
                                     h->segA, h->segB, h->segC, s), "permute csr");
@@ -610,6 +620,11 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       Timer tm(h, RSD_T_SIGMA, s);
       hip_check(h, launch_sigma_w(h->leaf, h->sig, W, s), "sigma W");
       hip_check(h, launch_sigma_s(h->sig, W, h->sigma, h->sigma_fp32, s), "sigma S");
+    }
+    if (h->leaf_apply.half) {
+      Timer tm(h, RSD_T_LEAF_INVERSE, s);
+      hip_check(h, launch_narrow(static_cast<const float*>(h->leaf.tiles), h->leaf_apply.tiles,
+                                 h->leaf_elems, h->leaf_apply.half, s), "16-bit leaf copy");
     }
     int32_t* iflags = h->flags + P.leaf_node.size();
     for (size_t q = 0; q < h->lev.size(); ++q) {
@@ -739,7 +754,8 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, r, h->sympart, -1.0, nullptr, z, nv, n, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf_apply, r, h->sympart, -1.0, nullptr, z, nv, n, s),
+              "leaf symv");
   }
   {
     Timer tm(h, RSD_T_COUPLING, s);
@@ -779,7 +795,8 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf, h->t, h->sympart, -1.0, nullptr, z, nv, n, s), "leaf symv");
+    hip_check(h, launch_symv(h->leaf_apply, h->t, h->sympart, -1.0, nullptr, z, nv, n, s),
+              "leaf symv");
   }
 }
 

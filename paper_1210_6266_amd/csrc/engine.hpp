@@ -47,6 +47,8 @@ struct rsd_ctx {
   int sigma_fp32 = 0;
   rsd::DevBatch leaf{};
   std::vector<rsd::DevBatch> lev;
+  rsd::DevBatch leaf_apply;    // the leaf batch as the applies read it (16-bit copy or leaf)
+  int64_t leaf_elems = 0;
   std::vector<rsd::SigmaLevelItems> lev_items;       // Sigma products against deeper levels
   std::vector<rsd::SigmaLevelItems> lev_own_items;   // and against the level itself (gamma)
   int32_t* flags = nullptr;  // one per leaf, then one per interface

@@ -15,11 +15,15 @@ constexpr int TS = 64;            // tile side
 constexpr int TT = TS * TS;       // tile elements
 constexpr int kBlock = 256;
 
-// partial sums of the symmetric products: FP32 for FP32 factors, FP64 otherwise
+// partial sums of the symmetric products: FP32 for FP32 and 16-bit factors, FP64 otherwise
 template <typename T>
 struct SymPart { using type = double; };
 template <>
 struct SymPart<float> { using type = float; };
+template <>
+struct SymPart<_Float16> { using type = float; };
+template <>
+struct SymPart<__bf16> { using type = float; };
 
 __host__ __device__ __forceinline__ int64_t tri(int64_t I) { return I * (I + 1) / 2; }
 __device__ __forceinline__ int64_t tile_index(int I, int J) { return tri(I) + J; }
@@ -1138,7 +1142,8 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
     typename SymPart<T>::type* __restrict__ part) {
   using P = typename SymPart<T>::type;
   constexpr int B = kSymB;
-  constexpr int VEC = 16 / int(sizeof(T));     // elements per 16-byte load
+  // elements per load: 16-byte loads of FP64 / FP32, 8-byte loads of 16-bit values
+  constexpr int VEC = sizeof(T) == 8 ? 2 : 4;
   constexpr int LPC = 4 / VEC;                 // loads per column (four rows per thread)
   typedef T V __attribute__((ext_vector_type(VEC)));
   const int it = blockIdx.x;
@@ -1146,10 +1151,10 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
   const int n = n_arr[m], nt = nt_arr[m];
   const int64_t xo = vec_off[m];
   // thread t: rows q4(v) of the tile (q = t % 16), columns g + 16 u (g = t / 16, u < 4);
-  // FP32: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1, 32 + 2q,
-  // 33 + 2q (two loads per column, each contiguous over 16 lanes)
+  // FP32 and 16-bit: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1,
+  // 32 + 2q, 33 + 2q (two loads per column, each contiguous over 16 lanes)
   const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
-  auto q4 = [&](int v) { return sizeof(T) == 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
+  auto q4 = [&](int v) { return sizeof(T) <= 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
   constexpr bool kColLds = sizeof(T) == 8;
   __shared__ P xs[KV][2][B][TS];               // x in the product's precision
   __shared__ P red[KV][4][B][TS];
@@ -1902,6 +1907,14 @@ __global__ __launch_bounds__(kBlock) void k_gmc_combine(GmArgs a, double* __rest
   }
 }
 
+// 16-bit copy of FP32 tiles (round to nearest)
+template <typename H>
+__global__ __launch_bounds__(kBlock) void k_narrow(const float* __restrict__ src,
+                                                   H* __restrict__ dst, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < count) dst[i] = H(src[i]);
+}
+
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return unsigned((n + per - 1) / per); }
 
 }  // namespace
@@ -2076,7 +2089,15 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
   k_symv1<T, KV><<<b.num_items, kBlock, 0, s>>>((const T*)b.tiles, b.tile_off, b.n, b.nt,       \
                                                 b.vec_off, b.item_mat, b.item_BI, b.item_BJ, xb, \
                                                 ld, c, (typename SymPart<T>::type*)part)
-    if (b.fp32) {
+    if (b.half) {
+      if (b.half == 1) {
+        if (kv == 1) RSD_SYMV(_Float16, 1); else if (kv == 2) RSD_SYMV(_Float16, 2); else RSD_SYMV(_Float16, 4);
+      } else {
+        if (kv == 1) RSD_SYMV(__bf16, 1); else if (kv == 2) RSD_SYMV(__bf16, 2); else RSD_SYMV(__bf16, 4);
+      }
+      k_symv2<float><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
+          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld);
+    } else if (b.fp32) {
       if (kv == 1) RSD_SYMV(float, 1); else if (kv == 2) RSD_SYMV(float, 2); else RSD_SYMV(float, 4);
       k_symv2<float><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
           b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld);
@@ -2087,6 +2108,17 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
     }
 #undef RSD_SYMV
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow(const float* src, void* dst, int64_t count, int kind, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (kind == 1)
+    k_narrow<_Float16><<<blocks_for(count), kBlock, 0, s>>>(src, (_Float16*)dst, count);
+  else if (kind == 2)
+    k_narrow<__bf16><<<blocks_for(count), kBlock, 0, s>>>(src, (__bf16*)dst, count);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

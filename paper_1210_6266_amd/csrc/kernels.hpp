@@ -28,8 +28,9 @@ struct DevBatch {
   const int32_t* item_BI = nullptr;
   const int32_t* item_BJ = nullptr;
   const int64_t* item_base = nullptr;
-  void* tiles = nullptr;  // double* or float*
+  void* tiles = nullptr;  // double* or float* (or 16-bit values, see half)
   int32_t fp32 = 0;
+  int32_t half = 0;       // apply-side 16-bit copy of FP32 tiles: 1 FP16, 2 BF16 (0: none)
 };
 
 // ---- sparse / vector ------------------------------------------------------------------
@@ -88,6 +89,8 @@ size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, si
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
                        const double* base, double* y, int nv, int64_t ld, hipStream_t s);
 inline int symv_vectors(const DevBatch&) { return 4; }
+// dst (count 16-bit values, FP16 for kind 1, BF16 for kind 2) = src rounded to nearest
+hipError_t launch_narrow(const float* src, void* dst, int64_t count, int kind, hipStream_t s);
 inline size_t symv_part_bytes(const DevBatch& b) {
   return size_t(b.num_items) * 2 * kSymB * kTile * size_t(symv_vectors(b)) *
          (b.fp32 ? sizeof(float) : sizeof(double));

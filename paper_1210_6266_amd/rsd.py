@@ -22,7 +22,7 @@ RSD_OK = 0
 STATUS = {0: "RSD_OK", 1: "RSD_ERR_INVALID_ARGUMENT", 2: "RSD_ERR_MAP_NOT_SEPARABLE",
           3: "RSD_ERR_NOT_SPD", 4: "RSD_ERR_NOT_CONVERGED", 5: "RSD_ERR_BREAKDOWN",
           6: "RSD_ERR_OUT_OF_MEMORY", 7: "RSD_ERR_DEVICE", 8: "RSD_ERR_UNSUPPORTED"}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 SOLVER = {"fgmres": 0, "pcg": 1}
 IFACE = {"dense": 0, "gamma": 1, "hybrid": 2}
 TIMER_NAMES = ["setup_extract", "leaf_inverse", "leaf_update", "sigma", "iface_assembly",
@@ -286,8 +286,9 @@ class RSD:
         self.n = self.row_ptr.numel() - 1
         o = rsd_options_default()
         o.leaf_prec = PREC[leaf_prec]
-        o.sigma_prec = PREC[sigma_prec or leaf_prec]
-        o.iface_prec = PREC[iface_prec or leaf_prec]
+        low = "fp32" if leaf_prec in ("fp16", "bf16") else leaf_prec   # 16 bits: leaves only
+        o.sigma_prec = PREC[sigma_prec or low]
+        o.iface_prec = PREC[iface_prec or low]
         o.root_prec = PREC[root_prec]
         o.timing = 1 if timing else 0
         o.iface_mode = IFACE[interface]

@@ -24,6 +24,7 @@ CASES = [  # (name, problem key, handle options, oracle bar)
     ("diffusion13-fp64", ("diffusion", 13, 2, 1.0, 2), {}, 1e-10),
     ("diffusion20-fp32", ("diffusion", 20, 2, 1.0, 5), FP32, 2e-4),
     ("elasticity8-fp32", ("elasticity", 8, 2, 1), FP32, 2e-4),
+    ("diffusion20-bf16", ("diffusion", 20, 2, 1.0, 5), dict(leaf_prec="bf16"), 1e-1),
 ]
 
 

@@ -221,3 +221,24 @@ def test_maxit_reports_not_converged(problem_cache):
     assert st == 4 and info[0]["iterations"] == 2
     assert info[0]["relres"] > 1e-14
     h.close()
+
+
+@pytest.mark.parametrize("prec,bar", [("fp16", 2e-2), ("bf16", 1e-1)])
+def test_half_precision_leaves(problem_cache, prec, bar):
+    """16-bit sub-domain inverses (formed in FP32, stored in 16 bits, FP32 products):
+    the apply error is of order kappa(K_ll) * eps_16 (eps = 2^-11 FP16, 2^-8 BF16) and
+    clearly above the FP32 one; the FP64 FGMRES still reaches 1e-10."""
+    _log(f"16-bit leaves {prec}")
+    p = problem_cache("diffusion", 20, 2, 1.0, 5)
+    o = RSDOracle(p.K, p.parent, p.dof_node)
+    r = np.random.default_rng(9).uniform(-1, 1, p.n)
+    zo = o.apply(r)
+    h = _handle(p, leaf_prec=prec, root_prec="fp64")
+    z = h.apply(_dev(r, torch.float64)).cpu().numpy()
+    err = np.abs(z - zo).max() / np.abs(zo).max()
+    assert 1e-6 < err <= bar, err
+    b = p.b[:, 0]
+    x, st, info = h.solve(_dev(b, torch.float64), rtol=1e-10)
+    x = x.cpu().numpy()
+    assert st == 0 and np.linalg.norm(b - p.K @ x) / np.linalg.norm(b) <= 1e-10
+    h.close()

@@ -86,6 +86,10 @@ def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
         return diffusion_problem(64, 2, 1.0, seed, nrhs, name)
     if name == "elasticity48":
         return elasticity_problem(48, 3, seed, 8 if nrhs == 1 else nrhs, name)
+    if name == "poisson256":
+        # 256^3 Poisson, octree of height 5: 32,768 sub-domains of 8^3 elements (343
+        # interior dofs), 16 right-hand sides ~ U[-1, 1]
+        return diffusion_problem(256, 5, 0.0, seed, 16 if nrhs == 1 else nrhs, name)
     if name == "adjoint32":
         p = diffusion_problem(32, 2, 0.5, seed, nrhs, name)
         # draw order continues after b: the adjoint target
