@@ -98,10 +98,13 @@ typedef struct {
   int32_t iface_mode;    /* RSD_IFACE_DENSE (default), RSD_IFACE_GAMMA or RSD_IFACE_HYBRID  */
   int32_t gamma;         /* inner GMRES steps per interface solve (1..64; gamma modes)      */
   int32_t dense_max;     /* RSD_IFACE_HYBRID: largest interface solved exactly              */
+  int32_t graphs;        /* 1: replay each preconditioner application from a HIP graph
+                            captured on first use (one per number of columns, 1..8);
+                            ignored while timing = 1                                       */
 } rsd_options;
 
 /* Fills *opt with the defaults: all FP64, device pointers, no timing, exact
- * (dense) interface solves, gamma = 8, dense_max = 32768. */
+ * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on. */
 void rsd_options_default(rsd_options* opt);
 
 enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };

@@ -49,6 +49,7 @@ void rsd_options_default(rsd_options* o) {
   o->iface_mode = RSD_IFACE_DENSE;
   o->gamma = 8;
   o->dense_max = 32768;
+  o->graphs = 1;
 }
 
 rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analysis* out) {
@@ -93,6 +94,8 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "gamma must be in 1..64");
     if (opt->iface_mode == RSD_IFACE_HYBRID && opt->dense_max < 0)
       return fail(RSD_ERR_INVALID_ARGUMENT, "dense_max must be >= 0");
+    if (opt->graphs != 0 && opt->graphs != 1)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "graphs must be 0 or 1");
   }
   if (!csr->values) return fail(RSD_ERR_INVALID_ARGUMENT, "values must not be NULL");
   rsd_ctx* h = nullptr;

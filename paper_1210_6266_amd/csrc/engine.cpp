@@ -818,10 +818,55 @@ void permute(rsd_ctx* h, int nv, const double* x, int64_t ldx, double* y, int64_
 // Right-hand sides handled together by one apply, SpMV or Krylov iteration.
 constexpr int kRhsGroup = 8;
 
+void drop_graphs(rsd_ctx* h) {
+  for (hipGraphExec_t& g : h->apply_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  h->apply_graph.clear();
+}
+
+// z = M^{-1} r for nv vectors at stride n.  With graphs on (and timing off) the whole
+// application is replayed from a graph captured on first use for this nv on the fixed
+// vectors rin -> zin; r and z are copied in and out unless they are those vectors.  The
+// capture runs on the handle's own stream (capturing executes nothing); the replays run
+// on the caller's stream.
+void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
+  if (!h->opt.graphs || h->opt.timing) {
+    core_apply(h, nv, r, z, s);
+    return;
+  }
+  const size_t bytes = sizeof(double) * size_t(nv) * size_t(h->P.n);
+  if (r != h->rin)
+    hip_check(h, hipMemcpyAsync(h->rin, r, bytes, hipMemcpyDeviceToDevice, s), "apply in");
+  if (int(h->apply_graph.size()) <= nv) h->apply_graph.resize(size_t(nv) + 1, nullptr);
+  hipGraphExec_t& ex = h->apply_graph[size_t(nv)];
+  if (!ex) {
+    if (!h->cap)
+      hip_check(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreate");
+    hipGraph_t g = nullptr;
+    hip_check(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal),
+              "begin capture");
+    try {
+      core_apply(h, nv, h->rin, h->zin, h->cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(h->cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hip_check(h, hipStreamEndCapture(h->cap, &g), "end capture");
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(h, e, "hipGraphInstantiate");
+  }
+  hip_check(h, hipGraphLaunch(ex, s), "hipGraphLaunch");
+  if (z != h->zin)
+    hip_check(h, hipMemcpyAsync(z, h->zin, bytes, hipMemcpyDeviceToDevice, s), "apply out");
+}
+
 // Apply work vectors (e, t, rin, zin, xil, the inner GMRES scratch) for nv vectors.
 void ensure_vectors(rsd_ctx* h, int nv) {
   if (h->nvec >= nv) return;
   hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
+  drop_graphs(h);                       // they refer to the buffers replaced here
   ensure_gamma(h, nv);
   for (double* p : {h->e, h->t, h->rin, h->zin, h->xil}) dfree(h, p);
   const size_t n = size_t(h->P.n), nB = std::max<size_t>(1, h->P.B.size());
@@ -976,7 +1021,8 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
       const int nv = hi - lo;
       const double* Vb = h->V + lo * n;                 // column 0 of right-hand side lo
       double* Wb = W + lo * n;
-      core_apply(h, nv, h->V + (int64_t(j) * nr + lo) * n, h->Z + (int64_t(j) * nr + lo) * n, s);
+      apply_vectors(h, nv, h->V + (int64_t(j) * nr + lo) * n, h->Z + (int64_t(j) * nr + lo) * n,
+                    s);
       core_spmv(h, nv, h->Z + (int64_t(j) * nr + lo) * n, nullptr, 1.0, Wb, s);
       {
         Timer tm(h, RSD_T_KRYLOV, s);
@@ -1095,7 +1141,7 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
     info->relres = rn / bnorm;
     return RSD_OK;
   }
-  core_apply(h, 1, r, z, s);
+  apply_vectors(h, 1, r, z, s);
   {
     Timer tm(h, RSD_T_KRYLOV, s);
     hip_check(h, launch_mdot(1, r, n, 0, 1, z, 0, n, h->part, h->scal + cur, 0, 0, s), "rz");
@@ -1137,7 +1183,7 @@ rsd_status pcg_one(rsd_ctx* h, const double* b, double* x, const rsd_solve_optio
       info->relres = dev_norm(h, h->w, h->scal + 5, s) / bnorm;
       return RSD_ERR_NOT_CONVERGED;
     }
-    core_apply(h, 1, r, z, s);
+    apply_vectors(h, 1, r, z, s);
     {
       Timer tm(h, RSD_T_KRYLOV, s);
       const int nxt = 1 - cur;
@@ -1158,7 +1204,7 @@ rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, doub
       const int c = std::min(kRhsGroup, nrhs - j0);
       ensure_vectors(h, c);
       permute(h, c, r + size_t(j0) * ldr, ldr, h->rin, n, 0, s);
-      core_apply(h, c, h->rin, h->zin, s);
+      apply_vectors(h, c, h->rin, h->zin, s);
       permute(h, c, h->zin, n, z + size_t(j0) * ldz, ldz, 1, s);
     }
     return RSD_OK;
@@ -1261,6 +1307,9 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
 void engine_free(rsd_ctx* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
+  drop_graphs(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  h->cap = nullptr;
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);

@@ -76,6 +76,10 @@ struct rsd_ctx {
   };
   std::vector<GmLevel> gm_lev;
   int32_t gm_max_items = 0;
+  // captured preconditioner applications: graph exec per number of columns (index nv),
+  // on rin -> zin; dropped whenever a buffer they use is reallocated
+  std::vector<hipGraphExec_t> apply_graph;
+  hipStream_t cap = nullptr;    // capture stream (the caller's may be the legacy null stream)
   double *gm_part = nullptr, *gm_coef = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
 
