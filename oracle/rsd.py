@@ -10,7 +10,8 @@ What it computes (Sampath et al., "Recursive Schur Decomposition"):
   interiors and their interface I, the interface unknowns solve the Schur
   complement system S u_I = g of eq. (schur), and the interiors follow by the
   back-substitution of eq. (backSub).  Sub-domain matrices are inverted
-  exactly with a direct method (here: dense Cholesky).
+  exactly with a direct method (here: dense Cholesky; LU with partial pivoting
+  when K is not symmetric, as for the paper's two-field Problems 2 and 3).
 * Many sub-domains (Section 3.2): the pseudo sub-domain solves that produce
   K^{-1} f inside g are replaced by the same algorithm applied recursively to
   the sub-tree (Alg. 2, RSD); the two other uses of a pseudo sub-domain inverse
@@ -116,12 +117,14 @@ class RSDOracle:
         self.H = Hierarchy(parent, dof_node, self.n)
         H = self.H
         K = self.K
-        # Direct solver on each true sub-domain (Section 3.1: exact inversion)
+        # Direct solver on each true sub-domain (Section 3.1: exact inversion):
+        # Cholesky for a symmetric K, LU with partial pivoting otherwise
+        self.symmetric = abs(K - K.T).max() == 0.0
         self.leaf_chol = {}
         for l in H.leaves:
             d = H.dofs[l]
             if d.size:
-                self.leaf_chol[l] = sla.cho_factor(K[d][:, d].toarray(), lower=True)
+                self.leaf_chol[l] = self._factor(K[d][:, d].toarray())
         # Per internal node: I, V = D(t) \ I, C_t and the coupling blocks
         self.I = {}
         self.V = {}
@@ -151,14 +154,24 @@ class RSDOracle:
                     self.K_lI[(l, t)] = K[d][:, I]
             self.C[t] = Ct
             if interface == "dense" and I.size:
-                self.S_chol[t] = sla.cho_factor(self.schur_dense(t), lower=True)
+                self.S_chol[t] = self._factor(self.schur_dense(t))
 
     # -- building blocks -------------------------------------------------------------
+    def _factor(self, A: np.ndarray):
+        if self.symmetric:
+            return ("chol", sla.cho_factor(A, lower=True))
+        return ("lu", sla.lu_factor(A))
+
+    @staticmethod
+    def _solve(f, rhs: np.ndarray) -> np.ndarray:
+        kind, fac = f
+        return sla.cho_solve(fac, rhs) if kind == "chol" else sla.lu_solve(fac, rhs)
+
     def leaf_solve(self, l: int, rhs: np.ndarray) -> np.ndarray:
         """K_ll^{-1} rhs by the sub-domain's direct factorisation."""
         if rhs.size == 0:
             return rhs.copy()
-        return sla.cho_solve(self.leaf_chol[l], rhs)
+        return self._solve(self.leaf_chol[l], rhs)
 
     def schur_dense(self, t: int) -> np.ndarray:
         """S~_t = K_II - sum_{l in C_t} K_Il K_ll^{-1} K_lI (the operator of Alg. 1).
@@ -215,7 +228,7 @@ class RSDOracle:
         if g.size == 0:
             return g.copy()
         if self.interface == "dense":
-            return sla.cho_solve(self.S_chol[t], g)
+            return self._solve(self.S_chol[t], g)
         return self.inner_gmres(t, g, self.gamma)
 
     # -- Alg. 2 ----------------------------------------------------------------------

@@ -192,3 +192,43 @@ def test_planted_mistakes_are_caught(problem_cache, monkeypatch):
     o = RSDOracle(p1.K, p1.parent, p1.dof_node)
     o.C[0] = o.C[0][1:]
     assert rel(o.dense(), Kinv) > 1e-3
+
+
+# ------------------------------------------- the paper's two-field (non-symmetric) systems
+def _golden_coupled_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_outer_iterations_coupled.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                prob, N, P, g, beta = line.split()
+                rows.append((prob, int(N), int(P), int(g), int(beta)))
+    return rows
+
+
+@pytest.mark.parametrize("prob,N,P,gamma,beta", _golden_coupled_rows())
+def test_paper_coupled_iteration_counts_p8(problem_cache, prob, N, P, gamma, beta):
+    """Tables 4 and 7 with LU sub-domain solves.  Problem 3 within +-2.  Problem 2
+    (weak coupling) drifts below the printed counts as they grow (80 vs 87 at N = 33,
+    gamma = 2): within max(2, 12%) -- the reading of its scaling is stated in DESIGN."""
+    s = problem_cache("strip", N, P, prob, 0)
+    assert abs(s.K - s.K.T).max() > 0                   # really non-symmetric
+    o = RSDOracle(s.K, s.parent, s.dof_node, interface="gamma", gamma=gamma)
+    assert not o.symmetric
+    x, info = fgmres(s.K, s.b[:, 0], o.apply, rtol=1e-12, restart=30, maxit=500)
+    assert info["converged"]
+    tol = 2 if prob == "coupled_strong" else max(2, int(0.12 * beta))
+    assert abs(info["iterations"] - beta) <= tol, (info["iterations"], beta)
+    assert rel(x, s.meta["x_true"]) < 1e-8
+
+
+@pytest.mark.parametrize("prob", ["coupled_weak", "coupled_strong"])
+def test_lu_path_one_level_is_exact(problem_cache, prob):
+    """Two sub-domains, exact interface solve: M^{-1} = K^{-1} for a non-symmetric K
+    (the LU sub-domain and interface solves of the oracle)."""
+    s = problem_cache("strip", 9, 2, prob, 0)
+    o = RSDOracle(s.K, s.parent, s.dof_node)
+    Kinv = np.linalg.inv(s.K.toarray())
+    assert np.abs(o.dense() - Kinv).max() <= 1e-11 * np.abs(Kinv).max()
+    g = RSDOracle(s.K, s.parent, s.dof_node, interface="gamma", gamma=14)   # dim(S~) = 14
+    r = np.random.default_rng(2).uniform(-1, 1, s.n)
+    assert rel(g.apply(r), o.apply(r)) < 1e-10

@@ -149,12 +149,15 @@ def _element_connectivity(ne: tuple) -> np.ndarray:
 
 
 def assemble_grid(ne: tuple, elem: np.ndarray, coef: np.ndarray | None = None,
-                  ndof: int = 1, dirichlet: str = "all", h: tuple | None = None) -> GridSystem:
+                  ndof: int = 1, dirichlet: str = "all", h: tuple | None = None,
+                  symmetric: bool = True) -> GridSystem:
     """Assemble  sum_e coef_e * elem  over a uniform grid of ne elements per axis.
 
     ``elem`` is the element matrix already scaled for the element size.
     ``dirichlet`` is "all" (every boundary node constrained) or "x0" (only the
     face x = 0).  Constrained dofs are eliminated (rows and columns removed).
+    ``symmetric``: make K bitwise symmetric (for a symmetric element matrix);
+    False keeps a non-symmetric operator as assembled.
     """
     dim = len(ne)
     nn = tuple(e + 1 for e in ne)
@@ -183,10 +186,11 @@ def assemble_grid(ne: tuple, elem: np.ndarray, coef: np.ndarray | None = None,
     n = int(free.sum()) * ndof
     K = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, n)).tocsr()
     K.sum_duplicates()
-    # duplicates are summed in a data-dependent order, so K_ij and K_ji can differ
-    # in the last bit; the average is symmetric bit for bit (a + b == b + a)
-    K = ((K + K.T) * 0.5).tocsr()
-    K.sum_duplicates()
+    if symmetric:
+        # duplicates are summed in a data-dependent order, so K_ij and K_ji can differ
+        # in the last bit; the average is symmetric bit for bit (a + b == b + a)
+        K = ((K + K.T) * 0.5).tocsr()
+        K.sum_duplicates()
     K.sort_indices()
     if h is None:
         h = tuple(1.0 / e for e in ne)
@@ -210,17 +214,54 @@ def assemble_elasticity_3d(ne: int, E: float = 1.0, nu: float = 0.3) -> GridSyst
                          (h, h, h))
 
 
+def anisotropic_laplace_element_2d(ax: float, ay: float) -> np.ndarray:
+    """Unit-cell  int ax phi_a,x phi_b,x + ay phi_a,y phi_b,y  (4 x 4)."""
+    K = np.zeros((4, 4))
+    for q in itertools.product(range(2), repeat=2):
+        xi = np.array([_G2[i] for i in q])
+        w = np.prod([_W2[i] for i in q])
+        _, g = _shape(2, xi)
+        K += w * (ax * np.outer(g[:, 0], g[:, 0]) + ay * np.outer(g[:, 1], g[:, 1]))
+    return K
+
+
+def coupled_element_2d(c: float, h: float) -> np.ndarray:
+    """Element of the paper's two-field systems (Problems 2 and 3), dofs (u, v) per node:
+      -u_xx/100 - u_yy + c v = f,   -c u - v_xx - v_yy/100 = g
+    as  [[A_u, c h^2 M], [-c h^2 M, A_v]]  with the unit-cell anisotropic stiffness
+    matrices (scale-invariant in 2-D) and the consistent mass matrix of an h x h element.
+    The coupling is antisymmetric, so the operator is not symmetric."""
+    Au = anisotropic_laplace_element_2d(0.01, 1.0)
+    Av = anisotropic_laplace_element_2d(1.0, 0.01)
+    M = mass_element(2) * h * h
+    E = np.zeros((8, 8))
+    for a in range(4):
+        for b in range(4):
+            E[2 * a, 2 * b] = Au[a, b]
+            E[2 * a + 1, 2 * b + 1] = Av[a, b]
+            E[2 * a, 2 * b + 1] = c * M[a, b]
+            E[2 * a + 1, 2 * b] = -c * M[a, b]
+    return E
+
+
 def assemble_strip_2d(N: int, P: int, problem: str) -> GridSystem:
     """The paper's 2-D strip: P true sub-domains of N x N nodes placed along x.
 
     Neighbouring sub-domains share one node line, so the domain has
-    P(N-1) x (N-1) elements; Dirichlet on every side.  Unit element size: the
-    bilinear forms used here (Laplace, Navier-Lame) are scale-invariant in 2-D.
-    problem: "poisson" (Problem 1) or "navier_lame" (Problem 4, lambda=10, mu=1).
+    P(N-1) x (N-1) elements; Dirichlet on every side.  The stiffness forms used
+    here are scale-invariant in 2-D; for the two-field systems each sub-domain is a
+    unit square (element size h = 1/(N-1)), which sets the weight of the coupling.
+    problem: "poisson" (Problem 1), "coupled_weak" (Problem 2, c = 1/100),
+    "coupled_strong" (Problem 3, c = 100) or "navier_lame" (Problem 4, lambda=10,
+    mu=1).
     """
     ne = (P * (N - 1), N - 1)
     if problem == "poisson":
         return assemble_grid(ne, laplace_element(2), None, 1, "all", (1.0, 1.0))
+    if problem in ("coupled_weak", "coupled_strong"):
+        c = 0.01 if problem == "coupled_weak" else 100.0
+        return assemble_grid(ne, coupled_element_2d(c, 1.0 / (N - 1)), None, 2, "all",
+                             (1.0, 1.0), symmetric=False)
     if problem == "navier_lame":
         return assemble_grid(ne, navier_lame_element_2d(10.0, 1.0), None, 2, "all", (1.0, 1.0))
     raise ValueError(problem)
