@@ -36,7 +36,8 @@ typedef enum {
   RSD_ERR_MAP_NOT_SEPARABLE = 2, /* K couples two dofs whose tree nodes are not on one
                                     root-to-leaf path (e.g. two different leaves)        */
   RSD_ERR_NOT_SPD = 3,           /* a sub-domain or interface block has a pivot <= 0 or
-                                    a non-finite pivot; rsd_last_error names the block    */
+                                    a non-finite pivot (symmetric = 0: a zero or
+                                    non-finite pivot); rsd_last_error names the block     */
   RSD_ERR_NOT_CONVERGED = 4,     /* Krylov reached maxit; x holds the last iterate       */
   RSD_ERR_BREAKDOWN = 5,         /* NaN/Inf in the Krylov recurrence                     */
   RSD_ERR_OUT_OF_MEMORY = 6,     /* device allocation failed                             */
@@ -101,10 +102,15 @@ typedef struct {
   int32_t graphs;        /* 1: replay each preconditioner application from a HIP graph
                             captured on first use (one per number of columns, 1..8);
                             ignored while timing = 1                                       */
+  int32_t symmetric;     /* 1: K is symmetric (sub-domains inverted by symmetric sweeps).
+                            0: K may be non-symmetric (pattern still symmetric): dense
+                            sub-domain inverses by Gauss-Jordan with partial pivoting (at
+                            most 2,048 dofs, leaf_prec FP64 or FP32) and iface_mode GAMMA,
+                            i.e. every interface solved by inner GMRES steps              */
 } rsd_options;
 
 /* Fills *opt with the defaults: all FP64, device pointers, no timing, exact
- * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on. */
+ * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on, symmetric. */
 void rsd_options_default(rsd_options* opt);
 
 enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };

@@ -50,6 +50,7 @@ void rsd_options_default(rsd_options* o) {
   o->gamma = 8;
   o->dense_max = 32768;
   o->graphs = 1;
+  o->symmetric = 1;
 }
 
 rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analysis* out) {
@@ -96,6 +97,13 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "dense_max must be >= 0");
     if (opt->graphs != 0 && opt->graphs != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "graphs must be 0 or 1");
+    if (opt->symmetric != 0 && opt->symmetric != 1)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "symmetric must be 0 or 1");
+    if (opt->symmetric == 0 && opt->iface_mode != RSD_IFACE_GAMMA)
+      return fail(RSD_ERR_UNSUPPORTED,
+                  "symmetric = 0 needs iface_mode GAMMA (the interface inverses are symmetric)");
+    if (opt->symmetric == 0 && !prec_ok(opt->leaf_prec))
+      return fail(RSD_ERR_UNSUPPORTED, "symmetric = 0 needs leaf_prec FP64 or FP32");
   }
   if (!csr->values) return fail(RSD_ERR_INVALID_ARGUMENT, "values must not be NULL");
   rsd_ctx* h = nullptr;

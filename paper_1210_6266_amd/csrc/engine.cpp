@@ -447,7 +447,37 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       h->sigma = dalloc<float>(h, size_t(P.sig_total));
     else
       h->sigma = dalloc<double>(h, size_t(P.sig_total));
-    upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec != RSD_PREC_FP64);
+    const bool general = h->opt.symmetric == 0;
+    upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec != RSD_PREC_FP64, !general);
+    // a K that is not symmetric: dense sub-domain inverses (Gauss-Jordan, partial pivoting)
+    std::vector<int64_t> gen_off, perm_off;
+    if (general) {
+      if (P.max_leaf > kGenMax) {
+        h->err = "symmetric = 0 supports sub-domains of at most 2048 dofs";
+        return RSD_ERR_UNSUPPORTED;
+      }
+      GenBatch& g = h->gen;
+      g.count = P.leaf_batch.count;
+      g.max_n = P.max_leaf;
+      g.fp32 = h->opt.leaf_prec == RSD_PREC_FP32;
+      gen_off.assign(size_t(g.count) + 1, 0);
+      perm_off.assign(size_t(g.count) + 1, 0);
+      for (int32_t l = 0; l < g.count; ++l) {
+        const int64_t nl_ = P.leaf_batch.n[l];
+        gen_off[l + 1] = gen_off[l] + nl_ * nl_;
+        perm_off[l + 1] = perm_off[l] + nl_;
+      }
+      up.add(&g.n, P.leaf_batch.n);
+      up.add(&g.vec_off, P.leaf_batch.vec_off);
+      up.add(&g.gen_off, gen_off);
+      up.add(&g.perm_off, perm_off);
+      g.perm = dalloc<int32_t>(h, size_t(std::max<int64_t>(1, perm_off[g.count])));
+      if (g.fp32)
+        g.A = dalloc<float>(h, size_t(std::max<int64_t>(1, gen_off[g.count])));
+      else
+        g.A = dalloc<double>(h, size_t(std::max<int64_t>(1, gen_off[g.count])));
+      h->sig.row_major = 1;     // Sigma_l is not symmetric: the apply reads its rows
+    }
     // 16-bit leaves: the apply reads a 16-bit copy of the FP32 inverses
     h->leaf_elems = P.leaf_batch.total_elems;
     void* half_tiles = nullptr;
@@ -592,15 +622,19 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
                 "gather couplings");
       const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
       hip_check(h, hipMemsetAsync(h->flags, 0, size_t(nflags) * 4, s), "hipMemsetAsync flags");
-      hip_check(h, launch_sym_fill(h->leaf, s), "leaf fill");
-      hip_check(h, launch_sym_extract(h->leaf, h->prow, h->segA, h->pcol, h->pval, P.max_leaf, s),
-                "leaf extract");
+      if (h->opt.symmetric) {
+        hip_check(h, launch_sym_fill(h->leaf, s), "leaf fill");
+        hip_check(h, launch_sym_extract(h->leaf, h->prow, h->segA, h->pcol, h->pval, P.max_leaf,
+                                        s), "leaf extract");
+      }
     }
     // scratch of the sweeps: sized for the largest batch
     size_t pb = 0, cb = 0, need_p = 0, need_c = 0;
-    sym_invert_scratch_bytes(h->leaf, group_for(h, h->leaf), &pb, &cb);
-    need_p = pb;
-    need_c = cb;
+    if (h->opt.symmetric) {
+      sym_invert_scratch_bytes(h->leaf, group_for(h, h->leaf), &pb, &cb);
+      need_p = pb;
+      need_c = cb;
+    }
     for (size_t q = 0; q < h->lev.size(); ++q) {
       if (h->gam_level[q]) continue;   // no dense factor at the levels solved matrix-free
       const DevBatch& L = h->lev[q];
@@ -613,12 +647,19 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     void* bbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
     {
       Timer tm(h, RSD_T_LEAF_INVERSE, s);
-      invert_batch(h, h->leaf, pbuf, cbuf, bbuf, h->flags, RSD_T_LEAF_UPDATE, s);
+      if (h->opt.symmetric)
+        invert_batch(h, h->leaf, pbuf, cbuf, bbuf, h->flags, RSD_T_LEAF_UPDATE, s);
+      else
+        hip_check(h, launch_gen_invert(h->gen, h->prow, h->segA, h->pcol, h->pval, h->flags, s),
+                  "general sub-domain inverses");
     }
     double* W = dalloc<double>(h, size_t(std::max<int64_t>(1, P.w_total)));
     {
       Timer tm(h, RSD_T_SIGMA, s);
-      hip_check(h, launch_sigma_w(h->leaf, h->sig, W, s), "sigma W");
+      if (h->opt.symmetric)
+        hip_check(h, launch_sigma_w(h->leaf, h->sig, W, s), "sigma W");
+      else
+        hip_check(h, launch_sigma_w_gen(h->gen, h->sig, W, s), "sigma W");
       hip_check(h, launch_sigma_s(h->sig, W, h->sigma, h->sigma_fp32, s), "sigma S");
     }
     if (h->leaf_apply.half) {
@@ -664,7 +705,12 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     for (size_t i = 0; i < fl.size(); ++i)
       if (fl[i]) {
         char buf[256];
-        if (i < P.leaf_node.size())
+        if (i < P.leaf_node.size() && !h->opt.symmetric)
+          std::snprintf(buf, sizeof(buf),
+                        "sub-domain matrix of leaf node %d is singular "
+                        "(zero or non-finite pivot in column %d)",
+                        P.leaf_node[i], fl[i] - 1);
+        else if (i < P.leaf_node.size())
           std::snprintf(buf, sizeof(buf),
                         "sub-domain matrix of leaf node %d is not positive definite "
                         "(non-positive pivot near tile column %d)",
@@ -754,8 +800,11 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf_apply, r, h->sympart, -1.0, nullptr, z, nv, n, s),
-              "leaf symv");
+    if (h->opt.symmetric)    // tiles hold -K_ll^{-1}
+      hip_check(h, launch_symv(h->leaf_apply, r, h->sympart, -1.0, nullptr, z, nv, n, s),
+                "leaf symv");
+    else
+      hip_check(h, launch_gen_matvec(h->gen, r, 1.0, z, nv, n, s), "leaf matvec");
   }
   {
     Timer tm(h, RSD_T_COUPLING, s);
@@ -795,8 +844,11 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    hip_check(h, launch_symv(h->leaf_apply, h->t, h->sympart, -1.0, nullptr, z, nv, n, s),
-              "leaf symv");
+    if (h->opt.symmetric)
+      hip_check(h, launch_symv(h->leaf_apply, h->t, h->sympart, -1.0, nullptr, z, nv, n, s),
+                "leaf symv");
+    else
+      hip_check(h, launch_gen_matvec(h->gen, h->t, 1.0, z, nv, n, s), "leaf matvec");
   }
 }
 

@@ -48,6 +48,7 @@ struct rsd_ctx {
   rsd::DevBatch leaf{};
   std::vector<rsd::DevBatch> lev;
   rsd::DevBatch leaf_apply;    // the leaf batch as the applies read it (16-bit copy or leaf)
+  rsd::GenBatch gen;           // symmetric = 0: dense general sub-domain inverses
   int64_t leaf_elems = 0;
   std::vector<rsd::SigmaLevelItems> lev_items;       // Sigma products against deeper levels
   std::vector<rsd::SigmaLevelItems> lev_own_items;   // and against the level itself (gamma)

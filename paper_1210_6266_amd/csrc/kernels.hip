@@ -1368,7 +1368,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma_s(SigmaArgs a, const double* _
       for (int64_t e = a.krow_ptr[f]; e < a.krow_ptr[f + 1]; ++e)
         v += a.krow_v[e] * Wc[a.krow_col[e]];
     }
-    out[r + b * m] = S(v);
+    out[a.row_major ? r * m + b : r + b * m] = S(v);
   }
 }
 
@@ -1916,6 +1916,161 @@ __global__ __launch_bounds__(kBlock) void k_gmc_combine(GmArgs a, double* __rest
   }
 }
 
+// ================================================================ general sub-domains
+// For a K that is not symmetric (the paper's two-field Problems 2 and 3) each leaf
+// matrix is kept dense, column-major (n x n at gen_off[l]), and inverted by Gauss-Jordan
+// elimination with partial pivoting -- the explicit-inverse counterpart of an LU solve.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gen_extract(
+    T* __restrict__ A, const int64_t* __restrict__ gen_off, const int32_t* __restrict__ n_arr,
+    const int64_t* __restrict__ vec_off, const int64_t* __restrict__ s0,
+    const int64_t* __restrict__ s1, const int32_t* __restrict__ pcol,
+    const double* __restrict__ pval) {
+  const int m = blockIdx.y;
+  const int n = n_arr[m];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  T* Am = A + gen_off[m];
+  if (i >= n) return;
+  for (int j = 0; j < n; ++j) Am[i + int64_t(j) * n] = T(0);
+  const int64_t off = vec_off[m], r = off + i;
+  for (int64_t k = s0[r]; k < s1[r]; ++k) {
+    const int64_t j = int64_t(pcol[k]) - off;
+    if (j >= 0 && j < n) Am[i + j * n] = T(pval[k]);
+  }
+}
+
+// One workgroup per matrix; column k and the scaled pivot row are staged in LDS for
+// each step (n <= kGenMax).  Arithmetic in FP64, storage T.  flags[m] = k + 1 when the
+// largest candidate pivot of column k is zero or not finite.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gen_invert(T* __restrict__ A,
+                                                       const int64_t* __restrict__ gen_off,
+                                                       const int32_t* __restrict__ n_arr,
+                                                       const int64_t* __restrict__ perm_off,
+                                                       int32_t* __restrict__ perm,
+                                                       int32_t* __restrict__ flags) {
+  __shared__ double colk[kGenMax], rowk[kGenMax];
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  const int m = blockIdx.x;
+  const int n = n_arr[m];
+  T* Am = A + gen_off[m];
+  int32_t* pm = perm + perm_off[m];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = 0; k < n; ++k) {
+    // pivot: largest |A[i, k]|, i >= k (smallest index among equals)
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + threadIdx.x; i < n; i += kBlock) {
+      const double v = fabs(double(Am[i + int64_t(k) * n]));
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    __syncthreads();
+    if (lane == 0) { rv[w] = best; ri[w] = bi; }
+    __syncthreads();
+    best = rv[0];
+    bi = ri[0];
+    for (int q = 1; q < 4; ++q)
+      if (rv[q] > best || (rv[q] == best && ri[q] < bi)) { best = rv[q]; bi = ri[q]; }
+    if (!(best > 0.0) || best > 1.7e308) {      // zero, NaN or infinite pivot
+      if (threadIdx.x == 0) flags[m] = k + 1;
+      return;
+    }
+    if (bi != k)
+      for (int j = threadIdx.x; j < n; j += kBlock) {
+        const T t = Am[k + int64_t(j) * n];
+        Am[k + int64_t(j) * n] = Am[bi + int64_t(j) * n];
+        Am[bi + int64_t(j) * n] = t;
+      }
+    if (threadIdx.x == 0) pm[k] = bi;
+    __syncthreads();
+    const double d = double(Am[k + int64_t(k) * n]);
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      colk[i] = double(Am[i + int64_t(k) * n]);
+      rowk[i] = (i == k ? 1.0 : double(Am[k + int64_t(i) * n])) / d;
+    }
+    __syncthreads();
+    // A[k, :] <- row k / d (with A[k, k] = 1 / d); A[i, :] -= A[i, k] row_k otherwise
+    // (A[i, k] <- -A[i, k] / d)
+    const int64_t nn = int64_t(n) * n;
+    for (int64_t e = threadIdx.x; e < nn; e += kBlock) {
+      const int i = int(e % n), j = int(e / n);
+      if (i == k) {
+        Am[e] = T(rowk[j]);
+      } else {
+        const double a = j == k ? 0.0 : double(Am[e]);
+        Am[e] = T(a - colk[i] * rowk[j]);
+      }
+    }
+    __syncthreads();
+  }
+  // the row interchanges of the elimination become column interchanges of the inverse
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = pm[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < n; i += kBlock) {
+        const T t = Am[i + int64_t(k) * n];
+        Am[i + int64_t(k) * n] = Am[i + int64_t(p) * n];
+        Am[i + int64_t(p) * n] = t;
+      }
+    __syncthreads();
+  }
+}
+
+// y_k = alpha A_m x_k on every leaf's rows (one thread per row, x staged in LDS)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gen_matvec(
+    const T* __restrict__ A, const int64_t* __restrict__ gen_off,
+    const int32_t* __restrict__ n_arr, const int64_t* __restrict__ vec_off,
+    const double* __restrict__ x, double alpha, double* __restrict__ y, int64_t ld) {
+  __shared__ double xs[1024];
+  const int m = blockIdx.y, k = blockIdx.z;
+  const int n = n_arr[m];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (blockIdx.x * kBlock >= n) return;
+  const T* Am = A + gen_off[m];
+  const double* xv = x + k * ld + vec_off[m];
+  double s = 0.0;
+  for (int j0 = 0; j0 < n; j0 += 1024) {
+    const int nb = min(1024, n - j0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nb; j += kBlock) xs[j] = xv[j0 + j];
+    __syncthreads();
+    if (i < n)
+      for (int j = 0; j < nb; ++j) s += double(Am[i + int64_t(j0 + j) * n]) * xs[j];
+  }
+  if (i < n) y[k * ld + vec_off[m] + i] = alpha * s;
+}
+
+// W_l = K_ll^{-1}[shell, :] K_{l,B_l} from the dense inverses (cf. k_sigma_w)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sigma_w_gen(const T* __restrict__ A,
+                                                        const int64_t* __restrict__ gen_off,
+                                                        const int32_t* __restrict__ n_arr,
+                                                        SigmaArgs a, double* __restrict__ W) {
+  const int l = blockIdx.y, b = blockIdx.x;
+  const int64_t m = a.B_off[l + 1] - a.B_off[l];
+  if (b >= m) return;
+  const int64_t s = a.shell_off[l + 1] - a.shell_off[l];
+  const int n = n_arr[l];
+  const T* Al = A + gen_off[l];
+  const int64_t f = a.B_off[l] + b;
+  double* Wc = W + a.w_off[l] + int64_t(b) * s;
+  const int32_t* sh = a.shell + a.shell_off[l];
+  for (int64_t si = threadIdx.x; si < s; si += kBlock) {
+    const int i = sh[si];
+    double v = 0.0;
+    for (int64_t e = a.kcol_ptr[f]; e < a.kcol_ptr[f + 1]; ++e)
+      v += double(Al[i + int64_t(a.kcol_row[e]) * n]) * a.kcol_v[e];
+    Wc[si] = v;
+  }
+}
+
 // 16-bit copy of FP32 tiles (round to nearest)
 template <typename H>
 __global__ __launch_bounds__(kBlock) void k_narrow(const float* __restrict__ src,
@@ -2117,6 +2272,49 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
     }
 #undef RSD_SYMV
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_invert(const GenBatch& g, const int64_t* prow, const int64_t* segA,
+                             const int32_t* pcol, const double* pval, int32_t* flags,
+                             hipStream_t s) {
+  if (g.count == 0) return hipSuccess;
+  if (g.max_n > kGenMax) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(g.max_n), unsigned(g.count));
+  if (g.fp32) {
+    k_gen_extract<float><<<grid, kBlock, 0, s>>>((float*)g.A, g.gen_off, g.n, g.vec_off, prow,
+                                                 segA, pcol, pval);
+    k_gen_invert<float><<<g.count, kBlock, 0, s>>>((float*)g.A, g.gen_off, g.n, g.perm_off,
+                                                   g.perm, flags);
+  } else {
+    k_gen_extract<double><<<grid, kBlock, 0, s>>>((double*)g.A, g.gen_off, g.n, g.vec_off, prow,
+                                                  segA, pcol, pval);
+    k_gen_invert<double><<<g.count, kBlock, 0, s>>>((double*)g.A, g.gen_off, g.n, g.perm_off,
+                                                    g.perm, flags);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_matvec(const GenBatch& g, const double* x, double alpha, double* y,
+                             int nv, int64_t ld, hipStream_t s) {
+  if (g.count == 0 || nv <= 0) return hipSuccess;
+  const dim3 grid(blocks_for(g.max_n), unsigned(g.count), unsigned(nv));
+  if (g.fp32)
+    k_gen_matvec<float><<<grid, kBlock, 0, s>>>((const float*)g.A, g.gen_off, g.n, g.vec_off, x,
+                                                alpha, y, ld);
+  else
+    k_gen_matvec<double><<<grid, kBlock, 0, s>>>((const double*)g.A, g.gen_off, g.n, g.vec_off,
+                                                 x, alpha, y, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_w_gen(const GenBatch& g, const SigmaArgs& a, double* W, hipStream_t s) {
+  if (a.num_leaves == 0 || a.max_m == 0) return hipSuccess;
+  dim3 grid(a.max_m, a.num_leaves);
+  if (g.fp32)
+    k_sigma_w_gen<float><<<grid, kBlock, 0, s>>>((const float*)g.A, g.gen_off, g.n, a, W);
+  else
+    k_sigma_w_gen<double><<<grid, kBlock, 0, s>>>((const double*)g.A, g.gen_off, g.n, a, W);
   return hipGetLastError();
 }
 

@@ -96,6 +96,26 @@ inline size_t symv_part_bytes(const DevBatch& b) {
          (b.fp32 ? sizeof(float) : sizeof(double));
 }
 
+// ---- general (non-symmetric) sub-domains: dense column-major inverses ----------------------
+constexpr int kGenMax = 2048;   // largest sub-domain (LDS staging of one column and one row)
+struct GenBatch {
+  int32_t count = 0, max_n = 0, fp32 = 0;
+  const int32_t* n = nullptr;
+  const int64_t* vec_off = nullptr;
+  const int64_t* gen_off = nullptr;   // n_l^2 prefix sums
+  const int64_t* perm_off = nullptr;  // n_l prefix sums
+  int32_t* perm = nullptr;            // pivot rows of the elimination
+  void* A = nullptr;                  // double* or float*
+};
+// A_l = K_ll (rows' segments [prow[r], segA[r]) of the internal CSR), then A_l <- A_l^{-1}
+// by Gauss-Jordan elimination with partial pivoting (flags[l] = k + 1 on a zero pivot)
+hipError_t launch_gen_invert(const GenBatch& g, const int64_t* prow, const int64_t* segA,
+                             const int32_t* pcol, const double* pval, int32_t* flags,
+                             hipStream_t s);
+// y_k = alpha A_l x_k on every leaf's rows, nv vectors at stride ld
+hipError_t launch_gen_matvec(const GenBatch& g, const double* x, double alpha, double* y,
+                             int nv, int64_t ld, hipStream_t s);
+
 // ---- Schur complements --------------------------------------------------------------------
 struct SigmaArgs {
   int32_t num_leaves, max_m;
@@ -111,10 +131,13 @@ struct SigmaArgs {
   const double* krow_v;     // values of K_{B_l,l} by rows
   const int64_t* w_off;
   const int64_t* sig_off;
+  int32_t row_major = 0;    // Sigma_l stored row-major (a K that is not symmetric)
 };
 // W_l = K_ll^{-1}[shell, :] K_{l,B_l}  (from the leaf batch's -K_ll^{-1} tiles)
 hipError_t launch_sigma_w(const DevBatch& leaf, const SigmaArgs& a, double* W, hipStream_t s);
-// Sigma_l = K_{B_l,l} W_l   (stored fp64 or fp32)
+// the same W_l from the dense inverses of a general batch
+hipError_t launch_sigma_w_gen(const GenBatch& g, const SigmaArgs& a, double* W, hipStream_t s);
+// Sigma_l = K_{B_l,l} W_l   (stored fp64 or fp32; row-major when a.row_major)
 hipError_t launch_sigma_s(const SigmaArgs& a, const double* W, void* sigma, int sigma_fp32,
                           hipStream_t s);
 // S~ tiles (already holding K_tt) -= sum over adjacent leaves of Sigma_l[I_t, I_t]

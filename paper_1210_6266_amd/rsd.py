@@ -44,7 +44,7 @@ class rsd_options(C.Structure):
                 ("iface_prec", C.c_int32), ("root_prec", C.c_int32),
                 ("host_pointers", C.c_int32), ("timing", C.c_int32),
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("symmetric", C.c_int32)]
 
 
 class rsd_solve_options(C.Structure):
@@ -268,7 +268,7 @@ class RSD:
 
     def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
                  sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
-                 interface="dense", gamma=8, dense_max=32768, graphs=True):
+                 interface="dense", gamma=8, dense_max=32768, graphs=True, symmetric=True):
         """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
         every interface system, the paper's mode) or "hybrid" (gamma steps where an
         interface has more than dense_max dofs)."""
@@ -296,6 +296,7 @@ class RSD:
         o.gamma = int(gamma)
         o.dense_max = int(dense_max)
         o.graphs = 1 if graphs else 0
+        o.symmetric = 1 if symmetric else 0
         self.stream = stream
         self.handle = rsd_setup(self.row_ptr, self.col_idx, self.values, self.parent,
                                 self.dof_node, o, stream)

@@ -35,7 +35,8 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
-    assert o.struct_size == 11 * 4 and o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
+    assert o.struct_size == 12 * 4 and o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
+    assert o.symmetric == 1
     assert o.iface_mode == 0 and o.gamma == 8 and o.dense_max == 32768
 
 
@@ -156,6 +157,15 @@ def test_setup_validates_before_device_work(problem_cache, lib):
         msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
                                              p.dof_node.astype(np.int32), o, stream=0))
         assert what in msg, msg
+    # a non-symmetric K needs the gamma interface mode and FP64 / FP32 sub-domains
+    for mode, prec, code in ((0, 0, 8), (2, 0, 8), (1, 2, 8), (1, 0, None)):
+        o = R.rsd_options_default()
+        o.host_pointers = 1
+        o.symmetric, o.iface_mode, o.leaf_prec = 0, mode, prec
+        if code is not None:
+            msg = _expect(code, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
+                                                    p.dof_node.astype(np.int32), o, stream=0))
+            assert "symmetric = 0" in msg, msg
 
 
 def test_column_block_layout_checks():
