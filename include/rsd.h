@@ -102,6 +102,11 @@ typedef struct {
   int32_t graphs;        /* 1: replay each preconditioner application from a HIP graph
                             captured on first use (one per number of columns, 1..8);
                             ignored while timing = 1                                       */
+  int32_t autotune;      /* 1: before the first application to 2..8 columns, time the
+                            candidate numbers of vectors per pass (1, 2, 4) of every dense
+                            batch's symmetric product on the handle's own blocks and keep
+                            the fastest (results do not depend on the choice); the choices
+                            are remembered per process for batches of the same shape      */
   int32_t symmetric;     /* 1: K is symmetric (sub-domains inverted by symmetric sweeps).
                             0: K may be non-symmetric (pattern still symmetric): dense
                             sub-domain inverses by Gauss-Jordan with partial pivoting (at
@@ -110,7 +115,8 @@ typedef struct {
 } rsd_options;
 
 /* Fills *opt with the defaults: all FP64, device pointers, no timing, exact
- * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on, symmetric. */
+ * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on, autotune on,
+ * symmetric. */
 void rsd_options_default(rsd_options* opt);
 
 enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };
@@ -242,6 +248,9 @@ typedef struct {
                               [1] device allocation and index upload,
                               [2] enqueueing the dense set-up,
                               [3] waiting for it and releasing scratch memory  */
+  int32_t vec_pass[8];     /* vectors per pass of the symmetric products chosen by the
+                              autotuner (0: not tuned): [0] sub-domains, then the dense
+                              interface levels, deepest first                  */
 } rsd_stats;
 
 /* Copies the handle's statistics (synchronises `stream` when timing is on).

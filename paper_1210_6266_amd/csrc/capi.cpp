@@ -50,6 +50,7 @@ void rsd_options_default(rsd_options* o) {
   o->gamma = 8;
   o->dense_max = 32768;
   o->graphs = 1;
+  o->autotune = 1;
   o->symmetric = 1;
 }
 
@@ -97,6 +98,8 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "dense_max must be >= 0");
     if (opt->graphs != 0 && opt->graphs != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "graphs must be 0 or 1");
+    if (opt->autotune != 0 && opt->autotune != 1)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "autotune must be 0 or 1");
     if (opt->symmetric != 0 && opt->symmetric != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "symmetric must be 0 or 1");
     if (opt->symmetric == 0 && opt->iface_mode != RSD_IFACE_GAMMA)

@@ -10,6 +10,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
+#include <unordered_map>
 #include <mutex>
 #include <type_traits>
 
@@ -795,8 +797,11 @@ void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
 // of eq. (backSub) on every sub-domain at once.  nv vectors (r_k = r + k n, likewise
 // z) go through every step together: the factors and K are read once per group of
 // vectors that a kernel holds, and each vector's result is the one it has alone.
+void set_vec_pass(rsd_ctx* h, int nv);
+
 void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   const Plan& P = h->P;
+  set_vec_pass(h, nv);
   const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
@@ -870,6 +875,81 @@ void permute(rsd_ctx* h, int nv, const double* x, int64_t ldx, double* y, int64_
 // Right-hand sides handled together by one apply, SpMV or Krylov iteration.
 constexpr int kRhsGroup = 8;
 
+// ---- autotuner: vectors per pass of the symmetric products -------------------------------
+// For a column count nv in 2..8, every dense batch (the sub-domains, each exactly solved
+// interface level) times one product of nv vectors with passes of 1, 2 and 4 vectors on
+// the handle's own blocks (one warm-up, two timed runs each) and keeps the fastest; a
+// tie keeps more vectors per pass.  Every grouping gives the same bits, so only speed
+// depends on the choice.  Choices are remembered per process for batches of the same
+// shape (count, sizes, storage type, nv).
+std::mutex g_tune_mu;
+std::unordered_map<std::string, int32_t> g_tune;
+
+std::string tune_key(const SymBatch& sb, const DevBatch& d, int nv) {
+  uint64_t hsh = 1469598103934665603ull;                 // FNV-1a over the sizes
+  for (int32_t v : sb.n) {
+    hsh ^= uint64_t(uint32_t(v));
+    hsh *= 1099511628211ull;
+  }
+  return std::to_string(d.fp32) + ":" + std::to_string(d.half) + ":" + std::to_string(nv) + ":" +
+         std::to_string(sb.count) + ":" + std::to_string(hsh);
+}
+
+int32_t tune_batch(rsd_ctx* h, DevBatch& b, const SymBatch& sb, int nv, hipStream_t s) {
+  if (b.num_items == 0) return 0;
+  const std::string key = tune_key(sb, b, nv);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  const int64_t n = h->P.n;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hip_check(h, hipEventCreate(&e0), "hipEventCreate");
+  hip_check(h, hipEventCreate(&e1), "hipEventCreate");
+  int32_t best = 4;
+  float best_ms = 0.0f;
+  for (int32_t cand : {4, 2, 1}) {
+    b.vec_pass = cand;
+    hip_check(h, launch_symv(b, h->rin, h->sympart, -1.0, nullptr, h->zin, nv, n, s), "tune");
+    hip_check(h, hipEventRecord(e0, s), "hipEventRecord");
+    for (int r = 0; r < 2; ++r)
+      hip_check(h, launch_symv(b, h->rin, h->sympart, -1.0, nullptr, h->zin, nv, n, s), "tune");
+    hip_check(h, hipEventRecord(e1, s), "hipEventRecord");
+    hip_check(h, hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.0f;
+    hip_check(h, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (cand == 4 || ms < best_ms) {
+      best = cand;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
+void autotune_apply(rsd_ctx* h, int nv, hipStream_t s) {
+  if (h->vec_pass.size() < 9) h->vec_pass.assign(9, std::array<int32_t, 9>{});
+  std::array<int32_t, 9>& vp = h->vec_pass[size_t(nv)];
+  vp.fill(0);
+  if (h->opt.symmetric) vp[0] = tune_batch(h, h->leaf_apply, h->P.leaf_batch, nv, s);
+  for (size_t q = 0; q < h->lev.size() && q < 8; ++q)
+    if (!h->gam_level[q]) vp[1 + q] = tune_batch(h, h->lev[q], h->P.level_batch[q], nv, s);
+  h->tuned[size_t(nv)] = true;
+  h->last_tuned = nv;
+}
+
+// the tuned vectors per pass for nv columns (0: the default) on every dense batch
+void set_vec_pass(rsd_ctx* h, int nv) {
+  const bool have = nv >= 0 && size_t(nv) < h->vec_pass.size() && h->tuned[size_t(nv)];
+  h->leaf_apply.vec_pass = have ? h->vec_pass[size_t(nv)][0] : 0;
+  for (size_t q = 0; q < h->lev.size(); ++q)
+    h->lev[q].vec_pass = have && q < 8 ? h->vec_pass[size_t(nv)][1 + q] : 0;
+}
+
 void drop_graphs(rsd_ctx* h) {
   for (hipGraphExec_t& g : h->apply_graph)
     if (g) (void)hipGraphExecDestroy(g);
@@ -882,6 +962,8 @@ void drop_graphs(rsd_ctx* h) {
 // capture runs on the handle's own stream (capturing executes nothing); the replays run
 // on the caller's stream.
 void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
+  if (h->opt.autotune && nv >= 2 && nv <= kRhsGroup && !h->tuned[size_t(nv)])
+    autotune_apply(h, nv, s);            // before this nv's graph is captured
   if (!h->opt.graphs || h->opt.timing) {
     core_apply(h, nv, r, z, s);
     return;
@@ -1346,6 +1428,8 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
     out->host_analysis_ms = h->host_ms;
     out->device_bytes = h->device_bytes;
     for (int i = 0; i < 4; ++i) out->setup_wall_ms[i] = h->setup_wall[i];
+    if (h->last_tuned > 0)
+      for (int i = 0; i < 8; ++i) out->vec_pass[i] = h->vec_pass[size_t(h->last_tuned)][size_t(i)];
     if (reset) {
       std::memset(h->time_ms, 0, sizeof(h->time_ms));
       std::memset(h->launches, 0, sizeof(h->launches));

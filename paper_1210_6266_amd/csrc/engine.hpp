@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <string>
 #include <utility>
 #include <vector>
@@ -81,6 +82,11 @@ struct rsd_ctx {
   // on rin -> zin; dropped whenever a buffer they use is reallocated
   std::vector<hipGraphExec_t> apply_graph;
   hipStream_t cap = nullptr;    // capture stream (the caller's may be the legacy null stream)
+  // autotuned vectors per pass of the symmetric products, per column count (index nv):
+  // [0] the sub-domain batch, [1 + q] dense interface level q; tuned[nv] once done
+  std::vector<std::array<int32_t, 9>> vec_pass;
+  std::array<bool, 9> tuned{};
+  int32_t last_tuned = 0;
   double *gm_part = nullptr, *gm_coef = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
 

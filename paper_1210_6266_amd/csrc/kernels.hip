@@ -2242,7 +2242,7 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
                        const double* base, double* y, int nv, int64_t ld, hipStream_t s) {
   if (b.count == 0 || b.num_items == 0 || nv <= 0) return hipSuccess;
-  const int kmax = symv_vectors(b);
+  const int kmax = b.vec_pass > 0 ? min(b.vec_pass, symv_vectors(b)) : symv_vectors(b);
   for (int v0 = 0; v0 < nv; v0 += kmax) {
     const int c = nv - v0 < kmax ? nv - v0 : kmax;
     const int kv = c == 1 ? 1 : c == 2 ? 2 : 4;

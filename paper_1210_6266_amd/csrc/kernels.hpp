@@ -31,6 +31,7 @@ struct DevBatch {
   void* tiles = nullptr;  // double* or float* (or 16-bit values, see half)
   int32_t fp32 = 0;
   int32_t half = 0;       // apply-side 16-bit copy of FP32 tiles: 1 FP16, 2 BF16 (0: none)
+  int32_t vec_pass = 0;   // vectors per pass of the symmetric product (0: symv_vectors)
 };
 
 // ---- sparse / vector ------------------------------------------------------------------

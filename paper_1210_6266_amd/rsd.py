@@ -44,7 +44,7 @@ class rsd_options(C.Structure):
                 ("iface_prec", C.c_int32), ("root_prec", C.c_int32),
                 ("host_pointers", C.c_int32), ("timing", C.c_int32),
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
-                ("graphs", C.c_int32), ("symmetric", C.c_int32)]
+                ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32)]
 
 
 class rsd_solve_options(C.Structure):
@@ -69,7 +69,8 @@ class rsd_analysis(C.Structure):
 class rsd_stats(C.Structure):
     _fields_ = [("analysis", rsd_analysis), ("time_ms", C.c_double * 14),
                 ("launches", C.c_int64 * 14), ("host_analysis_ms", C.c_double),
-                ("device_bytes", C.c_int64), ("setup_wall_ms", C.c_double * 4)]
+                ("device_bytes", C.c_int64), ("setup_wall_ms", C.c_double * 4),
+                ("vec_pass", C.c_int32 * 8)]
 
 
 class rsd_fe_map(C.Structure):
@@ -250,6 +251,7 @@ def rsd_get_stats(handle, reset=False, stream=None) -> dict:
     out["host_analysis_ms"] = s.host_analysis_ms
     out["device_bytes"] = s.device_bytes
     out["setup_wall_ms"] = list(s.setup_wall_ms)
+    out["vec_pass"] = list(s.vec_pass)
     return out
 
 
@@ -268,7 +270,8 @@ class RSD:
 
     def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
                  sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
-                 interface="dense", gamma=8, dense_max=32768, graphs=True, symmetric=True):
+                 interface="dense", gamma=8, dense_max=32768, graphs=True, autotune=True,
+                 symmetric=True):
         """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
         every interface system, the paper's mode) or "hybrid" (gamma steps where an
         interface has more than dense_max dofs)."""
@@ -297,6 +300,7 @@ class RSD:
         o.dense_max = int(dense_max)
         o.graphs = 1 if graphs else 0
         o.symmetric = 1 if symmetric else 0
+        o.autotune = 1 if autotune else 0
         self.stream = stream
         self.handle = rsd_setup(self.row_ptr, self.col_idx, self.values, self.parent,
                                 self.dof_node, o, stream)

@@ -35,8 +35,8 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
-    assert o.struct_size == 12 * 4 and o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
-    assert o.symmetric == 1
+    assert o.struct_size == 13 * 4 and o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
+    assert o.symmetric == 1 and o.autotune == 1
     assert o.iface_mode == 0 and o.gamma == 8 and o.dense_max == 32768
 
 
