@@ -1422,11 +1422,11 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
     const double* __restrict__ z, double* __restrict__ e, int nv, int64_t ldz, int64_t lde) {
   // e_l[a] = sum_{c0 <= b < c1} Sigma_l[a, b] u[B_l[b]] for rows a in [a0, a1)
-  // (<= kSigItemRows), for nv <= KV vectors (u_k = z + k ldz, e_k = e + k lde).  Sigma_l
-  // is symmetric: row a is read as column a (contiguous in b), kSigRows rows at a time
-  // (kSigRows / 4 per wave); the gathered u is staged in LDS once for all the item's
-  // rows when the column range fits one stage.  Each row's sum is taken in a fixed order
-  // that depends neither on KV nor on the item's extent.
+  // (<= kSigRows), for nv <= KV vectors (u_k = z + k ldz, e_k = e + k lde).  Row a of
+  // Sigma_l is read contiguously in b (a symmetric Sigma_l is stored by columns, which
+  // are its rows; a general one is stored by rows), one wave per kSigRows / 4 rows, the
+  // gathered u staged in LDS; each row's sum is taken in a fixed order that does not
+  // depend on KV.
   const int it = blockIdx.x;
   const int l = it_leaf[it], c0 = it_c0[it], c1 = it_c1[it], a0 = it_a0[it], a1 = it_a1[it];
   const int64_t m = B_off[l + 1] - B_off[l];
@@ -1436,9 +1436,6 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
   __shared__ double ub[KV][kSigStage];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int RW = kSigRows / 4;             // rows per wave
-  int staged = -1;                             // first column of the staged u (block-uniform)
-  for (int g0 = a0; g0 < a1; g0 += kSigRows) {
-  const int g1 = min(a1, g0 + kSigRows);
   double acc[RW][KV];
 #pragma unroll
   for (int q = 0; q < RW; ++q)
@@ -1446,20 +1443,17 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     for (int k = 0; k < KV; ++k) acc[q][k] = 0.0;
   for (int b0 = c0; b0 < c1; b0 += kSigStage) {
     const int nb = min(kSigStage, c1 - b0);
-    if (staged != b0) {
-      __syncthreads();
-      for (int b = threadIdx.x; b < nb; b += kBlock) {
-        const int32_t gi = Bl[b0 + b];
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+      const int32_t gi = Bl[b0 + b];
 #pragma unroll
-        for (int k = 0; k < KV; ++k) ub[k][b] = k < nv ? z[k * ldz + gi] : 0.0;
-      }
-      __syncthreads();
-      staged = b0;
+      for (int k = 0; k < KV; ++k) ub[k][b] = k < nv ? z[k * ldz + gi] : 0.0;
     }
+    __syncthreads();
     const S* col[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
-      const int a = min(g0 + w * RW + q, g1 - 1);   // rows past g1 repeat a valid row
+      const int a = min(a0 + w * RW + q, a1 - 1);   // rows past a1 repeat a valid row
       col[q] = Sg + int64_t(a) * m + b0;
     }
     int b = lane;
@@ -1487,10 +1481,9 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
       double v = acc[q][k];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      const int a = g0 + w * RW + q;
-      if (lane == 0 && a < g1 && k < nv) e[k * lde + B_off[l] + a] = v;
+      const int a = a0 + w * RW + q;
+      if (lane == 0 && a < a1 && k < nv) e[k * lde + B_off[l] + a] = v;
     }
-  }
 }
 
 // z_v[r] += alpha * sum over the leaves l adjacent to interface dof r of e_l[position of

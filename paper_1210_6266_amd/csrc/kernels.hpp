@@ -149,12 +149,10 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
                                  hipStream_t s);
 
 // ---- apply helpers -------------------------------------------------------------------------
-// rows of Sigma_l per pass of the level product (4 waves, kSigRows / 4 rows each), and
-// per work item (one staging of the gathered vector serves all of them).  Items of one
-// pass measured faster than items of 8 passes on 32,768 small leaves: more workgroups
-// in flight outweigh the repeated staging.
+// rows of Sigma_l per work item of the level product (4 waves, kSigRows / 4 rows each).
+// Items of 128 rows that stage the gathered vector once measured slower on 32,768 small
+// leaves: more workgroups in flight outweigh the repeated staging.
 constexpr int kSigRows = 16;
-constexpr int kSigItemRows = 16;
 
 // item: rows [a0, a1) of Sigma_l (leaf l) against the columns [c0, c1) of B_l
 struct SigmaLevelItems {
