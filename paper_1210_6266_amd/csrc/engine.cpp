@@ -253,9 +253,12 @@ void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool
 }
 
 // Blocked sweep inversion of a batch; the MFMA update launches are timed as `upd`.
-// With two- or four-tile pivot groups the next step's pivot and panel run on the auxiliary
-// stream as soon as the tiles they read are updated (look-ahead), overlapping the
-// bulk of the current update; the panel buffers alternate between steps.
+// With two- or four-tile pivot groups each step's update is split: the part that the
+// next step's pivot and panel read runs first on the main stream, then the next pivot
+// and panel follow it there while the bulk of the update runs on the auxiliary stream
+// (look-ahead); the panel buffers alternate between steps.  The pivot is queued behind
+// an in-stream dependency so that its one workgroup per matrix (large LDS) is dispatched
+// before the bulk update's workgroups take every compute unit.
 // Pivot tiles per sweep step: four (K = 256 for the MFMA update, half the passes over
 // the matrix) unless the matrices are small; RSD_SWEEP_GROUP overrides.
 int group_for(const rsd_ctx* h, const DevBatch& b) {
@@ -282,27 +285,30 @@ void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void
   int k = 0;
   for (int c0 = 0; c0 < b.max_nt; c0 += G, ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
-    const bool more = c0 + G < b.max_nt;
-    if (more) {
-      {
-        Timer tm(h, upd, s);
-        hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s, 1),
-                  "sweep update (look-ahead part)");
-      }
-      hip_check(h, hipEventRecord(h->ev_main, s), "hipEventRecord");
-      hip_check(h, hipStreamWaitEvent(a, h->ev_main, 0), "hipStreamWaitEvent");
-      hip_check(h, launch_sweep_step(b, c0 + G, 0, pbuf, cbuf[nxt], bbuf[nxt], flags, G, a),
-                "sweep pivot");
-      hip_check(h, launch_sweep_step(b, c0 + G, 1, pbuf, cbuf[nxt], bbuf[nxt], flags, G, a),
-                "sweep panel");
-      hip_check(h, hipEventRecord(h->ev_aux, a), "hipEventRecord");
+    if (c0 + G >= b.max_nt) {
+      Timer tm(h, upd, s);
+      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s, 0),
+                "sweep update");
+      break;
     }
     {
       Timer tm(h, upd, s);
-      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s,
-                                     more ? 2 : 0), "sweep update");
+      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, s, 1),
+                "sweep update (look-ahead part)");
     }
-    if (more) hip_check(h, hipStreamWaitEvent(s, h->ev_aux, 0), "hipStreamWaitEvent");
+    hip_check(h, hipEventRecord(h->ev_main, s), "hipEventRecord");
+    hip_check(h, hipStreamWaitEvent(a, h->ev_main, 0), "hipStreamWaitEvent");
+    {
+      Timer tm(h, upd, a);
+      hip_check(h, launch_sweep_step(b, c0, 2, pbuf, cbuf[cur], bbuf[cur], flags, G, a, 2),
+                "sweep update");
+    }
+    hip_check(h, launch_sweep_step(b, c0 + G, 0, pbuf, cbuf[nxt], bbuf[nxt], flags, G, s),
+              "sweep pivot");
+    hip_check(h, launch_sweep_step(b, c0 + G, 1, pbuf, cbuf[nxt], bbuf[nxt], flags, G, s),
+              "sweep panel");
+    hip_check(h, hipEventRecord(h->ev_aux, a), "hipEventRecord");
+    hip_check(h, hipStreamWaitEvent(s, h->ev_aux, 0), "hipStreamWaitEvent");
   }
 }
 

@@ -581,6 +581,9 @@ template <typename T, int G>
 __global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
     T* tiles, const int64_t* tile_off, const int32_t* nt_arr, int c0, T* pbuf, int32_t* flags) {
   constexpr int PB = G * TS, NTH = PivCfg<T>::threads, NW = NTH / 64;
+  // on the critical path while the bulk update of the previous step shares the compute
+  // units: its waves take issue priority over the update's
+  __builtin_amdgcn_s_setprio(3);
   const int m = blockIdx.x;
   const int nt = nt_arr[m];
   if (c0 >= nt) return;
@@ -781,6 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
   constexpr int PB = G * TS, KC = PanelCfg<T>::KC, NCH = PB / KC;
   constexpr int LDC = TS + 16, LDP = PB + 16;         // padded LDS rows (bank-spread)
   constexpr int NC = KC * TS / kBlock, NP = KC * PB / kBlock;   // loads per thread and chunk
+  __builtin_amdgcn_s_setprio(3);               // critical path, as the pivot
   const int m = blockIdx.y, i = blockIdx.x;
   const int nt = nt_arr[m];
   if (c0 >= nt || i >= nt) return;
