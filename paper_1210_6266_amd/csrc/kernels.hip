@@ -1490,6 +1490,67 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     }
 }
 
+// The same product for a symmetric Sigma_l (stored by columns: Sigma_l[a, b] at b m + a)
+// and items of up to 64 rows: one wave per item, lane = row a, so each load of a column
+// segment is coalesced and each row's sum runs over b in ascending order in one lane (no
+// cross-lane reduction, no workgroup barrier).  The gathered u of 64 columns at a time
+// is staged in the wave's own LDS slice and read back as broadcasts.  Small blocks (the
+// face blocks of small sub-domains) keep the whole wave busy on one item.
+template <typename S, int KV>
+__global__ __launch_bounds__(kBlock) void k_sigma_rows(
+    const int32_t* __restrict__ it_leaf, const int32_t* __restrict__ it_c0,
+    const int32_t* __restrict__ it_c1, const int32_t* __restrict__ it_a0,
+    const int32_t* __restrict__ it_a1, int count,
+    const S* __restrict__ sigma, const int64_t* __restrict__ sig_off,
+    const int64_t* __restrict__ B_off, const int32_t* __restrict__ B,
+    const double* __restrict__ z, double* __restrict__ e, int nv, int64_t ldz, int64_t lde) {
+  constexpr int NWV = kBlock / 64;
+  __shared__ double ub[NWV][64][KV];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int it = blockIdx.x * NWV + w;
+  if (it >= count) return;                     // wave-uniform: no block barrier below
+  const int l = it_leaf[it], c0 = it_c0[it], c1 = it_c1[it], a0 = it_a0[it], a1 = it_a1[it];
+  const int64_t m = B_off[l + 1] - B_off[l];
+  const S* Sg = sigma + sig_off[l];
+  const int32_t* Bl = B + B_off[l];
+  const int a = min(a0 + lane, a1 - 1);        // lanes past a1 repeat a valid row
+  double (*u)[KV] = ub[w];
+  double acc[KV];
+#pragma unroll
+  for (int k = 0; k < KV; ++k) acc[k] = 0.0;
+  for (int b0 = c0; b0 < c1; b0 += 64) {
+    const int nb = min(64, c1 - b0);
+    wave_sync();                               // the previous chunk's broadcasts are read
+    if (lane < nb) {
+      const int32_t gi = Bl[b0 + lane];
+#pragma unroll
+      for (int k = 0; k < KV; ++k) u[lane][k] = k < nv ? z[k * ldz + gi] : 0.0;
+    }
+    wave_sync();
+    const S* col = Sg + int64_t(b0) * m + a;
+    int j = 0;
+    for (; j + 8 <= nb; j += 8) {
+      S sv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sv[q] = col[int64_t(j + q) * m];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int k = 0; k < KV; ++k) acc[k] = fma(double(sv[q]), u[j + q][k], acc[k]);
+    }
+    for (; j < nb; ++j) {
+      const double sv = double(col[int64_t(j) * m]);
+#pragma unroll
+      for (int k = 0; k < KV; ++k) acc[k] = fma(sv, u[j][k], acc[k]);
+    }
+  }
+  if (lane < a1 - a0) {
+#pragma unroll
+    for (int k = 0; k < KV; ++k)
+      if (k < nv) e[k * lde + B_off[l] + a] = acc[k];
+  }
+}
+
 // z_v[r] += alpha * sum over the leaves l adjacent to interface dof r of e_l[position of
 // r in B_l], rows r in [row0, row0 + nrows), for nv vectors (z_v = z + v ldz, e_v = e +
 // v lde)
@@ -2379,9 +2440,16 @@ hipError_t launch_sigma_level(const SigmaLevelItems& it, const void* sigma, int 
     const double* zb = z + v0 * ldz;
     double* eb = e + v0 * lde;
 #define RSD_SIGL(S, KV)                                                                     \
-  k_sigma_level<S, KV><<<it.count, kBlock, 0, s>>>(it.leaf, it.c0, it.c1, it.a0, it.a1,  \
-                                                   (const S*)sigma, sig_off, B_off, B, zb, eb, \
-                                                   c, ldz, lde)
+  do {                                                                                      \
+    if (it.by_rows)                                                                         \
+      k_sigma_rows<S, KV><<<(it.count + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s>>>(  \
+          it.leaf, it.c0, it.c1, it.a0, it.a1, it.count, (const S*)sigma, sig_off, B_off, B, \
+          zb, eb, c, ldz, lde);                                                             \
+    else                                                                                    \
+      k_sigma_level<S, KV><<<it.count, kBlock, 0, s>>>(it.leaf, it.c0, it.c1, it.a0, it.a1, \
+                                                       (const S*)sigma, sig_off, B_off, B, zb, \
+                                                       eb, c, ldz, lde);                    \
+  } while (0)
     if (sigma_fp32) {
       if (c == 1) RSD_SIGL(float, 1); else if (c == 2) RSD_SIGL(float, 2); else RSD_SIGL(float, 4);
     } else {

@@ -149,14 +149,17 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
                                  hipStream_t s);
 
 // ---- apply helpers -------------------------------------------------------------------------
-// rows of Sigma_l per work item of the level product (4 waves, kSigRows / 4 rows each).
-// Items of 128 rows that stage the gathered vector once measured slower on 32,768 small
-// leaves: more workgroups in flight outweigh the repeated staging.
+// rows of Sigma_l per work item of the level product: kSigRows for a general Sigma_l (4
+// waves, kSigRows / 4 rows each, lanes over columns), kSigRowsWave for a symmetric one
+// (one wave, one row per lane).
 constexpr int kSigRows = 16;
+constexpr int kSigRowsWave = 64;
 
-// item: rows [a0, a1) of Sigma_l (leaf l) against the columns [c0, c1) of B_l
+// item: rows [a0, a1) of Sigma_l (leaf l) against the columns [c0, c1) of B_l; by_rows
+// marks items of up to kSigRowsWave rows of symmetric Sigma blocks
 struct SigmaLevelItems {
   int32_t count = 0;
+  int32_t by_rows = 0;
   const int32_t* leaf = nullptr;
   const int32_t* c0 = nullptr;
   const int32_t* c1 = nullptr;
