@@ -140,9 +140,11 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     return false;
   }, msg);
   if (e != PlanError::kOk) return e;
-  // structural symmetry: (i, j) present => (j, i) present
+  // structural symmetry: (i, j) present => (j, i) present.  Each entry above the
+  // diagonal is looked up in the transposed row; with as many entries below the
+  // diagonal as above, that map is a bijection and the lower ones are covered too.
   e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    for (int64_t k = row_ptr[i + 1] - 1; k >= row_ptr[i] && col_idx[k] > i; --k) {
       const int32_t j = col_idx[k];
       if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
         *code = PlanError::kInvalid;
@@ -153,6 +155,36 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     return false;
   }, msg);
   if (e != PlanError::kOk) return e;
+  {
+    std::vector<int64_t> upper(16, 0), lower(16, 0);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+      int64_t up = 0, dn = 0;                  // per-thread counts (no shared cache lines)
+      for (int64_t i = lo; i < hi; ++i) {
+        const int32_t* b = col_idx + row_ptr[i];
+        const int32_t* en = col_idx + row_ptr[i + 1];
+        const int32_t* d = std::lower_bound(b, en, int32_t(i));   // first column >= i
+        dn += d - b;
+        up += en - d - (d < en && *d == i ? 1 : 0);
+      }
+      upper[w] = up;
+      lower[w] = dn;
+    });
+    if (std::accumulate(upper.begin(), upper.end(), int64_t(0)) !=
+        std::accumulate(lower.begin(), lower.end(), int64_t(0))) {
+      // some entry below the diagonal has no transpose: report the first one
+      for (int32_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] && col_idx[k] < i; ++k) {
+          const int32_t j = col_idx[k];
+          if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
+            *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
+                       i, j);
+            return PlanError::kInvalid;
+          }
+        }
+      *msg = "K is not structurally symmetric";
+      return PlanError::kInvalid;
+    }
+  }
   // ---- validation of the tree ----------------------------------------------------------
   if (T <= 0 || parent == nullptr || dof_node == nullptr) {
     *msg = "hierarchy needs num_nodes >= 1, parent and dof_node";
@@ -403,35 +435,45 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     nkr += int64_t(lo_out[l].krow_col.size());
   }
   const int64_t nBflat = P->B_off[L];
-  P->B.clear();
-  P->shell.clear();
-  P->B.reserve(nBflat);
-  P->shell.reserve(P->shell_off[L]);
   P->kcol_ptr.assign(nBflat + 1, 0);
   P->krow_ptr.assign(nBflat + 1, 0);
-  P->kcol_row.clear();
-  P->kcol_val.clear();
-  P->krow_col.clear();
-  P->krow_val.clear();
-  P->kcol_row.reserve(nkc);
-  P->kcol_val.reserve(nkc);
-  P->krow_col.reserve(nkr);
-  P->krow_val.reserve(nkr);
-  for (int32_t l = 0; l < L; ++l) {
-    LeafOut& o = lo_out[l];
-    const int64_t base = P->B_off[l];
-    const int64_t kc0 = int64_t(P->kcol_row.size()), kr0 = int64_t(P->krow_col.size());
-    for (size_t a = 0; a < o.B.size(); ++a) {
-      P->kcol_ptr[base + a + 1] = kc0 + o.kcol_ptr[a + 1];
-      P->krow_ptr[base + a + 1] = kr0 + o.krow_ptr[a + 1];
+  {
+    // per-leaf offsets first, then every leaf's pieces copied in parallel
+    std::vector<int64_t> kc_off(size_t(L) + 1, 0), kr_off(size_t(L) + 1, 0);
+    for (int32_t l = 0; l < L; ++l) {
+      kc_off[l + 1] = kc_off[l] + int64_t(lo_out[l].kcol_row.size());
+      kr_off[l + 1] = kr_off[l] + int64_t(lo_out[l].krow_col.size());
     }
-    P->B.insert(P->B.end(), o.B.begin(), o.B.end());
-    P->shell.insert(P->shell.end(), o.shell.begin(), o.shell.end());
-    P->kcol_row.insert(P->kcol_row.end(), o.kcol_row.begin(), o.kcol_row.end());
-    P->kcol_val.insert(P->kcol_val.end(), o.kcol_val.begin(), o.kcol_val.end());
-    P->krow_col.insert(P->krow_col.end(), o.krow_col.begin(), o.krow_col.end());
-    P->krow_val.insert(P->krow_val.end(), o.krow_val.begin(), o.krow_val.end());
-    o = LeafOut();
+    P->B.resize(size_t(nBflat));
+    P->shell.resize(size_t(P->shell_off[L]));
+    P->kcol_row.resize(size_t(nkc));
+    P->kcol_val.resize(size_t(nkc));
+    P->krow_col.resize(size_t(nkr));
+    P->krow_val.resize(size_t(nkr));
+    std::atomic<int32_t> next{0};
+    std::vector<std::thread> th;
+    const int nw = std::min<int>(num_threads(), std::max(1, L));
+    for (int w = 0; w < nw; ++w)
+      th.emplace_back([&]() {
+        for (;;) {
+          const int32_t l = next++;
+          if (l >= L) break;
+          LeafOut& o = lo_out[l];
+          const int64_t base = P->B_off[l];
+          for (size_t a = 0; a < o.B.size(); ++a) {
+            P->kcol_ptr[base + a + 1] = kc_off[l] + o.kcol_ptr[a + 1];
+            P->krow_ptr[base + a + 1] = kr_off[l] + o.krow_ptr[a + 1];
+          }
+          std::copy(o.B.begin(), o.B.end(), P->B.begin() + base);
+          std::copy(o.shell.begin(), o.shell.end(), P->shell.begin() + P->shell_off[l]);
+          std::copy(o.kcol_row.begin(), o.kcol_row.end(), P->kcol_row.begin() + kc_off[l]);
+          std::copy(o.kcol_val.begin(), o.kcol_val.end(), P->kcol_val.begin() + kc_off[l]);
+          std::copy(o.krow_col.begin(), o.krow_col.end(), P->krow_col.begin() + kr_off[l]);
+          std::copy(o.krow_val.begin(), o.krow_val.end(), P->krow_val.begin() + kr_off[l]);
+          o = LeafOut();
+        }
+      });
+    for (auto& t : th) t.join();
   }
   // adjacency of interface dofs: (leaf, position in B_l), sorted by leaf
   P->adj_ptr.assign(nB + 1, 0);

@@ -111,7 +111,7 @@ def test_rejects_non_separable_map(problem_cache, lib):
 
 
 @pytest.mark.parametrize("case", ["unsorted", "col_range", "row_ptr", "parent", "dof_node",
-                                  "asymmetric"])
+                                  "asymmetric", "asymmetric_lower"])
 def test_rejects_invalid_input(problem_cache, lib, case):
     p = problem_cache("diffusion", 6, 1, 0.0, 0)
     rp, ci, par, dn = [x.copy() for x in _arrays(p)]
@@ -126,12 +126,23 @@ def test_rejects_invalid_input(problem_cache, lib, case):
     elif case == "dof_node":
         dn[0] = len(par)
     elif case == "asymmetric":
-        # drop one off-diagonal entry of row 0 (keep row 1's mirror)
+        # drop one off-diagonal entry of row 0 (keep row 1's mirror): an entry below
+        # the diagonal is left without its transpose
         k = rp[0] + 1
         ci = np.delete(ci, k)
         rp = rp.copy()
         rp[1:] -= 1
-    _expect(1, lambda: R.rsd_analyze(rp, ci, par, dn))
+    elif case == "asymmetric_lower":
+        # drop the first entry below the diagonal of row 5: an entry above the diagonal
+        # (in the row of its column) is left without its transpose
+        k = rp[5]
+        assert ci[k] < 5
+        ci = np.delete(ci, k)
+        rp = rp.copy()
+        rp[6:] -= 1
+    msg = _expect(1, lambda: R.rsd_analyze(rp, ci, par, dn))
+    if case.startswith("asymmetric"):
+        assert "structurally symmetric" in msg
 
 
 def test_setup_validates_before_device_work(problem_cache, lib):
