@@ -504,15 +504,24 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->lev_items.assign(NL, SigmaLevelItems());
     h->lev_own_items.assign(NL, SigmaLevelItems());
 
-    // Sigma products per level, split into row chunks (kSigRowsWave rows of a symmetric
-    // Sigma block, kSigRows of a general one): against the deeper levels' columns (the
-    // apply), and against the level's own columns (the S-MatVec of Alg. 1 for the levels
-    // solved with gamma GMRES steps)
+    // Sigma products per level, split into row chunks: against the deeper levels' columns
+    // (the apply), and against the level's own columns (the S-MatVec of Alg. 1 for the
+    // levels solved with gamma GMRES steps).  Symmetric Sigma blocks whose rows are short
+    // (row-weighted mean length <= kSigRowsMaxCols) go one row per lane in chunks of
+    // kSigRowsWave; longer rows (and general Sigma) go lanes over columns in chunks of
+    // kSigRows, which keeps more waves in flight per row.
     struct ItemLists { std::vector<int32_t> l, c0, c1, a0, a1; };
     std::vector<ItemLists> deep(NL), own(NL);
-    const int32_t chunk = h->opt.symmetric ? kSigRowsWave : kSigRows;
     auto items = [&](const std::vector<LevelSigmaItem>& src, bool own_cols, ItemLists* o,
                      SigmaLevelItems* li) {
+      double rows = 0.0, weighted = 0.0;
+      for (const auto& it : src) {
+        const double len = own_cols ? double(it.r1 - it.r0) : double(it.r0);
+        rows += double(it.r1 - it.r0);
+        weighted += len * double(it.r1 - it.r0);
+      }
+      const bool by_rows = h->opt.symmetric && weighted <= double(kSigRowsMaxCols) * rows;
+      const int32_t chunk = by_rows ? kSigRowsWave : kSigRows;
       for (const auto& it : src)
         for (int32_t a0 = it.r0; a0 < it.r1; a0 += chunk) {
           o->l.push_back(it.leaf);
@@ -522,7 +531,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
           o->a1.push_back(std::min(it.r1, a0 + chunk));
         }
       li->count = int32_t(o->l.size());
-      li->by_rows = h->opt.symmetric ? 1 : 0;
+      li->by_rows = by_rows ? 1 : 0;
       up.add(&li->leaf, o->l);
       up.add(&li->c0, o->c0);
       up.add(&li->c1, o->c1);

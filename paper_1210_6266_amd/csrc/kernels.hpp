@@ -154,6 +154,10 @@ hipError_t launch_schur_assemble(const DevBatch& b, const int64_t* adj_ptr,
 // (one wave, one row per lane).
 constexpr int kSigRows = 16;
 constexpr int kSigRowsWave = 64;
+// longest mean row (columns) of the items given to the one-row-per-lane product: on
+// 64^3 diffusion (rows of 721) lanes over columns ran 3x faster, on 48^3 elasticity
+// (rows of 291-428) and 256^3 Poisson (rows of at most 386) one row per lane won
+constexpr int kSigRowsMaxCols = 512;
 
 // item: rows [a0, a1) of Sigma_l (leaf l) against the columns [c0, c1) of B_l; by_rows
 // marks items of up to kSigRowsWave rows of symmetric Sigma blocks
