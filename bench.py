@@ -227,7 +227,7 @@ def bench_poisson256(a, dev):
              (rp, ci, v, p.parent.astype(np.int32), p.dof_node.astype(np.int32))]
         B = torch.as_tensor(np.ascontiguousarray(p.b.T), device=dev).t()      # n x 16
         opts = dict(leaf_prec="bf16", sigma_prec="fp32", iface_prec="fp32", root_prec="fp64",
-                    interface="hybrid", gamma=8, dense_max=12000)
+                    interface="hybrid", gamma=8, dense_max=5000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = RSD(*d, **opts)
@@ -249,7 +249,7 @@ def bench_poisson256(a, dev):
                     max_true_relres=float(rel.max()), relres_col0_scipy=rel0,
                     device_bytes=int(dev_bytes), host_generation_s=gen_s,
                     options="BF16 sub-domain inverses (formed in FP32), FP32 Sigma and level "
-                            "2-4 interface inverses, levels 0-1 (interfaces > 12,000 dofs) by "
+                            "3-4 interface inverses, levels 0-2 (interfaces > 5,000 dofs) by "
                             "8 matrix-free GMRES steps, FP64 Krylov; one cold pass",
                     workload=(f"Poisson Q1 256^3, n = {p.n}, nnz = {p.K.nnz}; octree h = 5: "
                               "32,768 sub-domains of 343 dofs; 16 right-hand sides U[-1, 1]; "
