@@ -87,6 +87,19 @@ enum { RSD_PREC_FP64 = 0, RSD_PREC_FP32 = 1, RSD_PREC_FP16 = 2, RSD_PREC_BF16 = 
  * The preconditioner is then a non-linear function of r: use FGMRES. */
 enum { RSD_IFACE_DENSE = 0, RSD_IFACE_GAMMA = 1, RSD_IFACE_HYBRID = 2 };
 
+/* Right-hand side g of each interface system in the recursion of Alg. 2.  The paper
+ * writes it for a strip, where an interface couples only to the two sub-domain
+ * interiors beside it.  In 3-D an interface also couples directly to deeper interface
+ * dofs:
+ *   RSD_COUPLING_FULL (default) -- g = f_I - K_{I,V} v over every dof V of the subtree
+ *     below the interface (sub-domain interiors and deeper interfaces): the block
+ *     elimination of the Schur complement equation with the recursive solution in
+ *     place of the exact one;
+ *   RSD_COUPLING_LEAF_ONLY -- only the couplings to sub-domain interiors (the strip
+ *     formula taken literally); it differs from FULL only where deeper interface dofs
+ *     couple to the interface (never in a strip, never with one level).            */
+enum { RSD_COUPLING_FULL = 0, RSD_COUPLING_LEAF_ONLY = 1 };
+
 typedef struct {
   int32_t struct_size;   /* sizeof(rsd_options) */
   int32_t leaf_prec;     /* inverses of the true sub-domain matrices K_ll              */
@@ -112,6 +125,16 @@ typedef struct {
                             sub-domain inverses by Gauss-Jordan with partial pivoting (at
                             most 2,048 dofs, leaf_prec FP64 or FP32) and iface_mode GAMMA,
                             i.e. every interface solved by inner GMRES steps              */
+  int32_t g_coupling;    /* RSD_COUPLING_FULL (default) or RSD_COUPLING_LEAF_ONLY          */
+  /* Optional device allocator for the handle's memory (set both or neither; default
+     NULL: the library's own cache of hipMalloc blocks).  alloc(bytes, alloc_ctx) returns
+     device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY); free(p,
+     alloc_ctx) returns a block once no queued work of the handle uses it.  Both are
+     called on the thread that calls rsd_setup, rsd_update_values, rsd_apply, rsd_spmv,
+     rsd_solve (workspace for more columns) and rsd_destroy.                         */
+  void* (*alloc)(size_t bytes, void* alloc_ctx);
+  void (*free)(void* p, void* alloc_ctx);
+  void* alloc_ctx;
 } rsd_options;
 
 /* Fills *opt with the defaults: all FP64, device pointers, no timing, exact

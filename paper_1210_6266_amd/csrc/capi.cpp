@@ -52,6 +52,10 @@ void rsd_options_default(rsd_options* o) {
   o->graphs = 1;
   o->autotune = 1;
   o->symmetric = 1;
+  o->g_coupling = RSD_COUPLING_FULL;
+  o->alloc = nullptr;
+  o->free = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analysis* out) {
@@ -102,6 +106,11 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "autotune must be 0 or 1");
     if (opt->symmetric != 0 && opt->symmetric != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "symmetric must be 0 or 1");
+    if (opt->g_coupling != RSD_COUPLING_FULL && opt->g_coupling != RSD_COUPLING_LEAF_ONLY)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "g_coupling must be RSD_COUPLING_FULL or "
+                                            "RSD_COUPLING_LEAF_ONLY");
+    if ((opt->alloc == nullptr) != (opt->free == nullptr))
+      return fail(RSD_ERR_INVALID_ARGUMENT, "alloc and free must be set together");
     if (opt->symmetric == 0 && opt->iface_mode != RSD_IFACE_GAMMA)
       return fail(RSD_ERR_UNSUPPORTED,
                   "symmetric = 0 needs iface_mode GAMMA (the interface inverses are symmetric)");

@@ -92,9 +92,21 @@ void cache_drain(BlockCache& c, bool pinned) {
   c.bytes = 0;
 }
 
+// Device blocks of the handle: from the caller's allocator when rsd_options gives one,
+// else from the process-wide cache of hipMalloc blocks.
 template <typename T>
 T* dalloc(rsd_ctx* h, size_t count) {
   const size_t want = round_block(std::max<size_t>(count, 1) * sizeof(T));
+  if (h->opt.alloc) {
+    void* p = h->opt.alloc(want, h->opt.alloc_ctx);
+    if (!p) {
+      h->err = "the allocator given in rsd_options returned NULL";
+      throw Fail{RSD_ERR_OUT_OF_MEMORY};
+    }
+    h->allocs.push_back({p, want});
+    h->device_bytes += int64_t(want);
+    return static_cast<T*>(p);
+  }
   BlockCache& c = cache_of(h->device);
   size_t got = want;
   void* p = cache_take(c, want, &got);
@@ -118,7 +130,10 @@ void dfree(rsd_ctx* h, void* p) {
   for (size_t i = 0; i < h->allocs.size(); ++i)
     if (h->allocs[i].first == p) {
       h->device_bytes -= int64_t(h->allocs[i].second);
-      cache_give(cache_of(h->device), p, h->allocs[i].second, false);
+      if (h->opt.free)
+        h->opt.free(p, h->opt.alloc_ctx);
+      else
+        cache_give(cache_of(h->device), p, h->allocs[i].second, false);
       h->allocs.erase(h->allocs.begin() + long(i));
       return;
     }
@@ -843,9 +858,10 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
                                       h->B_off, h->B, z, h->e, nv, n, nB, s), "sigma level");
       // g_t = q_t - K_{t, deeper interfaces} u - sum over adjacent leaves of e_l
       const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
-      hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segA, h->segB, h->prow, h->ell_off,
-                                   h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, nl, r0,
-                                   s), "level rhs");   // deeper levels come first: [nl, r0)
+      if (h->opt.g_coupling == RSD_COUPLING_FULL)   // the direct couplings to deeper levels
+        hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segA, h->segB, h->prow, h->ell_off,
+                                     h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, nl,
+                                     r0, s), "level rhs");   // deeper levels come first: [nl, r0)
       hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos,
                                     h->B_off, h->e, z, nv, n, nB, 1.0, s), "level adjacency");
     }
@@ -1474,7 +1490,12 @@ void engine_free(rsd_ctx* h) {
   h->ev_main = h->ev_aux = nullptr;
   h->aux = nullptr;                    // shared by the device's handles: not destroyed
   BlockCache& c = cache_of(h->device);
-  for (auto& p : h->allocs) cache_give(c, p.first, p.second, false);   // work is complete
+  for (auto& p : h->allocs) {                                           // work is complete
+    if (h->opt.free)
+      h->opt.free(p.first, h->opt.alloc_ctx);
+    else
+      cache_give(c, p.first, p.second, false);
+  }
   h->allocs.clear();
   h->device_bytes = 0;
   pfree(h, h->hhost_block);

@@ -24,6 +24,7 @@ STATUS = {0: "RSD_OK", 1: "RSD_ERR_INVALID_ARGUMENT", 2: "RSD_ERR_MAP_NOT_SEPARA
           6: "RSD_ERR_OUT_OF_MEMORY", 7: "RSD_ERR_DEVICE", 8: "RSD_ERR_UNSUPPORTED"}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 SOLVER = {"fgmres": 0, "pcg": 1}
+COUPLING = {"full": 0, "leaf_only": 1}
 IFACE = {"dense": 0, "gamma": 1, "hybrid": 2}
 TIMER_NAMES = ["setup_extract", "leaf_inverse", "leaf_update", "sigma", "iface_assembly",
                "iface_inverse", "iface_update", "root_update", "leaf_apply", "iface_apply",
@@ -39,12 +40,18 @@ class rsd_hierarchy(C.Structure):
     _fields_ = [("num_nodes", C.c_int32), ("parent", C.c_void_p), ("dof_node", C.c_void_p)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class rsd_options(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("leaf_prec", C.c_int32), ("sigma_prec", C.c_int32),
                 ("iface_prec", C.c_int32), ("root_prec", C.c_int32),
                 ("host_pointers", C.c_int32), ("timing", C.c_int32),
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
-                ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32)]
+                ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32),
+                ("g_coupling", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class rsd_solve_options(C.Structure):
@@ -271,10 +278,13 @@ class RSD:
     def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
                  sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
                  interface="dense", gamma=8, dense_max=32768, graphs=True, autotune=True,
-                 symmetric=True):
+                 symmetric=True, coupling="full", allocator=None):
         """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
         every interface system, the paper's mode) or "hybrid" (gamma steps where an
-        interface has more than dense_max dofs)."""
+        interface has more than dense_max dofs).  coupling: "full" or "leaf_only" (the
+        right-hand side of the interface systems, rsd_options.g_coupling).  allocator:
+        None (the library's own block cache) or "torch" (the handle's device memory
+        comes from PyTorch's caching allocator on the handle's stream)."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -301,6 +311,29 @@ class RSD:
         o.graphs = 1 if graphs else 0
         o.symmetric = 1 if symmetric else 0
         o.autotune = 1 if autotune else 0
+        o.g_coupling = COUPLING[coupling]
+        self._alloc_cbs = None
+        if allocator == "torch":
+            if stream is None:
+                stream_obj = torch.cuda.current_stream(dev)
+            elif isinstance(stream, int):
+                stream_obj = torch.cuda.ExternalStream(stream)
+            else:
+                stream_obj = stream
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream_obj)
+                except Exception:   # out of memory: the library reports RSD_ERR_OUT_OF_MEMORY
+                    return None
+
+            def _free(p, ctx):
+                torch.cuda.caching_allocator_delete(p)
+
+            self._alloc_cbs = (ALLOC_FN(_alloc), FREE_FN(_free))   # kept alive with the handle
+            o.alloc, o.free = self._alloc_cbs
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
         self.stream = stream
         self.handle = rsd_setup(self.row_ptr, self.col_idx, self.values, self.parent,
                                 self.dof_node, o, stream)

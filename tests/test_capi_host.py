@@ -1,6 +1,7 @@
 """Host-side tests of the C ABI (no GPU): the library loads, exports every entry
 point declared in include/rsd.h, and its host analysis validates input and
 reproduces the hierarchy counts computed independently from the matrix."""
+import ctypes
 import glob
 import os
 import re
@@ -35,9 +36,13 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
-    assert o.struct_size == 13 * 4 and o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
-    assert o.symmetric == 1 and o.autotune == 1
+    # 14 int32 fields, then the allocator's two function pointers and its context
+    assert o.struct_size == 14 * 4 + 3 * 8 == ctypes.sizeof(R.rsd_options)
+    assert R.rsd_options.alloc.offset == 14 * 4
+    assert o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
+    assert o.symmetric == 1 and o.autotune == 1 and o.g_coupling == 0
     assert o.iface_mode == 0 and o.gamma == 8 and o.dense_max == 32768
+    assert not o.alloc and not o.free and o.alloc_ctx is None
 
 
 def _arrays(p):
@@ -168,6 +173,20 @@ def test_setup_validates_before_device_work(problem_cache, lib):
         msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
                                              p.dof_node.astype(np.int32), o, stream=0))
         assert what in msg, msg
+    # coupling form; an allocator needs both functions
+    o = R.rsd_options_default()
+    o.host_pointers = 1
+    o.g_coupling = 2
+    msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
+                                         p.dof_node.astype(np.int32), o, stream=0))
+    assert "g_coupling" in msg, msg
+    o = R.rsd_options_default()
+    o.host_pointers = 1
+    only_alloc = R.ALLOC_FN(lambda nbytes, ctx: None)
+    o.alloc = only_alloc
+    msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
+                                         p.dof_node.astype(np.int32), o, stream=0))
+    assert "alloc and free" in msg, msg
     # a non-symmetric K needs the gamma interface mode and FP64 / FP32 sub-domains
     for mode, prec, code in ((0, 0, 8), (2, 0, 8), (1, 2, 8), (1, 0, None)):
         o = R.rsd_options_default()

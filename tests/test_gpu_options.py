@@ -1,0 +1,93 @@
+"""The right-hand side form of the interface systems (rsd_options.g_coupling) and a
+caller-supplied device allocator (rsd_options.alloc / free), through the C ABI.
+
+* LEAF_ONLY keeps only the couplings of an interface to sub-domain interiors (the strip
+  formula of Alg. 2 taken literally): against the oracle's "leaf_only" form to 1e-10
+  on 3-D octrees of height 2 and 3, where it differs from FULL; in a strip and with one
+  level no deeper-interface coupling exists and it gives FULL's bits.
+* allocator="torch": every device block of the handle comes from PyTorch's caching
+  allocator (closing the handle returns exactly its device bytes there; the default
+  handle's blocks are not PyTorch's), and applies and solves give the default handle's
+  bits.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import RSDOracle  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _handle(p, **kw):
+    from paper_1210_6266_amd import RSD
+    rp, ci, v = p.csr_arrays()
+    return RSD(rp, ci, v, p.parent, p.dof_node, **kw)
+
+
+def _vec(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _cm(a):
+    return torch.as_tensor(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("key", [("diffusion", 13, 2, 1.0, 2), ("diffusion", 9, 3, 0.0, 4)])
+def test_leaf_only_matches_oracle(problem_cache, key):
+    _log(f"leaf_only {key}")
+    p = problem_cache(*key)
+    r = np.random.default_rng(41).uniform(-1, 1, p.n)
+    zo = RSDOracle(p.K, p.parent, p.dof_node, coupling="leaf_only").apply(r)
+    h = _handle(p, coupling="leaf_only")
+    z = h.apply(_vec(r)).cpu().numpy()
+    h.close()
+    assert _rel(z, zo) <= 1e-10, _rel(z, zo)
+    hf = _handle(p)
+    zf = hf.apply(_vec(r)).cpu().numpy()
+    hf.close()
+    assert _rel(zf, zo) > 1e-6          # the forms differ in 3-D
+
+
+@pytest.mark.parametrize("key", [("strip", 17, 8, "poisson", 0), ("diffusion", 12, 1, 0.0, 0)])
+def test_leaf_only_equals_full_without_deeper_couplings(problem_cache, key):
+    _log(f"leaf_only = full {key}")
+    p = problem_cache(*key)
+    r = _vec(np.random.default_rng(42).uniform(-1, 1, p.n))
+    hl = _handle(p, coupling="leaf_only")
+    hf = _handle(p)
+    assert np.array_equal(hl.apply(r).cpu().numpy(), hf.apply(r).cpu().numpy())
+    hl.close()
+    hf.close()
+
+
+def test_torch_allocator(problem_cache):
+    _log("torch allocator")
+    p = problem_cache("diffusion", 13, 2, 1.0, 2)
+    rng = np.random.default_rng(43)
+    R = rng.uniform(-1, 1, size=(p.n, 3))
+    out = {}
+    for name, kw in (("default", {}), ("torch", dict(allocator="torch"))):
+        h = _handle(p, leaf_prec="fp32", **kw)
+        z = h.apply(_cm(R)).cpu().numpy()
+        X, st, info = h.solve(_cm(R), rtol=1e-10)      # solve workspace for 3 columns
+        assert st == 0
+        torch.cuda.synchronize()
+        db = h.stats()["device_bytes"]
+        m1 = torch.cuda.memory_allocated()
+        h.close()
+        m2 = torch.cuda.memory_allocated()
+        out[name] = (z, X.cpu().numpy(), db, m1 - m2)
+    assert out["torch"][2] > 0 and out["torch"][3] == out["torch"][2]
+    assert out["default"][3] == 0
+    assert np.array_equal(out["torch"][0], out["default"][0])
+    assert np.array_equal(out["torch"][1], out["default"][1])
