@@ -127,13 +127,13 @@ typedef struct {
                             i.e. every interface solved by inner GMRES steps              */
   int32_t g_coupling;    /* RSD_COUPLING_FULL (default) or RSD_COUPLING_LEAF_ONLY          */
   /* Optional device allocator for the handle's memory (set both or neither; default
-     NULL: the library's own cache of hipMalloc blocks).  alloc(bytes, alloc_ctx) returns
-     device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY); free(p,
-     alloc_ctx) returns a block once no queued work of the handle uses it.  Both are
+     NULL: the library's own cache of hipMalloc blocks).  dev_alloc(bytes, alloc_ctx)
+     returns device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY);
+     dev_free(p, alloc_ctx) returns a block once no queued work of the handle uses it.  Both are
      called on the thread that calls rsd_setup, rsd_update_values, rsd_apply, rsd_spmv,
      rsd_solve (workspace for more columns) and rsd_destroy.                         */
-  void* (*alloc)(size_t bytes, void* alloc_ctx);
-  void (*free)(void* p, void* alloc_ctx);
+  void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* p, void* alloc_ctx);
   void* alloc_ctx;
 } rsd_options;
 

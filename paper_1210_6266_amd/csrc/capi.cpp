@@ -53,8 +53,8 @@ void rsd_options_default(rsd_options* o) {
   o->autotune = 1;
   o->symmetric = 1;
   o->g_coupling = RSD_COUPLING_FULL;
-  o->alloc = nullptr;
-  o->free = nullptr;
+  o->dev_alloc = nullptr;
+  o->dev_free = nullptr;
   o->alloc_ctx = nullptr;
 }
 
@@ -109,8 +109,8 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
     if (opt->g_coupling != RSD_COUPLING_FULL && opt->g_coupling != RSD_COUPLING_LEAF_ONLY)
       return fail(RSD_ERR_INVALID_ARGUMENT, "g_coupling must be RSD_COUPLING_FULL or "
                                             "RSD_COUPLING_LEAF_ONLY");
-    if ((opt->alloc == nullptr) != (opt->free == nullptr))
-      return fail(RSD_ERR_INVALID_ARGUMENT, "alloc and free must be set together");
+    if ((opt->dev_alloc == nullptr) != (opt->dev_free == nullptr))
+      return fail(RSD_ERR_INVALID_ARGUMENT, "dev_alloc and dev_free must be set together");
     if (opt->symmetric == 0 && opt->iface_mode != RSD_IFACE_GAMMA)
       return fail(RSD_ERR_UNSUPPORTED,
                   "symmetric = 0 needs iface_mode GAMMA (the interface inverses are symmetric)");

@@ -97,8 +97,8 @@ void cache_drain(BlockCache& c, bool pinned) {
 template <typename T>
 T* dalloc(rsd_ctx* h, size_t count) {
   const size_t want = round_block(std::max<size_t>(count, 1) * sizeof(T));
-  if (h->opt.alloc) {
-    void* p = h->opt.alloc(want, h->opt.alloc_ctx);
+  if (h->opt.dev_alloc) {
+    void* p = h->opt.dev_alloc(want, h->opt.alloc_ctx);
     if (!p) {
       h->err = "the allocator given in rsd_options returned NULL";
       throw Fail{RSD_ERR_OUT_OF_MEMORY};
@@ -130,8 +130,8 @@ void dfree(rsd_ctx* h, void* p) {
   for (size_t i = 0; i < h->allocs.size(); ++i)
     if (h->allocs[i].first == p) {
       h->device_bytes -= int64_t(h->allocs[i].second);
-      if (h->opt.free)
-        h->opt.free(p, h->opt.alloc_ctx);
+      if (h->opt.dev_free)
+        h->opt.dev_free(p, h->opt.alloc_ctx);
       else
         cache_give(cache_of(h->device), p, h->allocs[i].second, false);
       h->allocs.erase(h->allocs.begin() + long(i));
@@ -1491,8 +1491,8 @@ void engine_free(rsd_ctx* h) {
   h->aux = nullptr;                    // shared by the device's handles: not destroyed
   BlockCache& c = cache_of(h->device);
   for (auto& p : h->allocs) {                                           // work is complete
-    if (h->opt.free)
-      h->opt.free(p.first, h->opt.alloc_ctx);
+    if (h->opt.dev_free)
+      h->opt.dev_free(p.first, h->opt.alloc_ctx);
     else
       cache_give(c, p.first, p.second, false);
   }

@@ -50,7 +50,7 @@ class rsd_options(C.Structure):
                 ("host_pointers", C.c_int32), ("timing", C.c_int32),
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
                 ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32),
-                ("g_coupling", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("g_coupling", C.c_int32), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -331,7 +331,7 @@ class RSD:
                 torch.cuda.caching_allocator_delete(p)
 
             self._alloc_cbs = (ALLOC_FN(_alloc), FREE_FN(_free))   # kept alive with the handle
-            o.alloc, o.free = self._alloc_cbs
+            o.dev_alloc, o.dev_free = self._alloc_cbs
         elif allocator is not None:
             raise ValueError("allocator must be None or 'torch'")
         self.stream = stream

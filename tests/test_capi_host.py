@@ -38,11 +38,11 @@ def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
     # 14 int32 fields, then the allocator's two function pointers and its context
     assert o.struct_size == 14 * 4 + 3 * 8 == ctypes.sizeof(R.rsd_options)
-    assert R.rsd_options.alloc.offset == 14 * 4
+    assert R.rsd_options.dev_alloc.offset == 14 * 4
     assert o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1
     assert o.symmetric == 1 and o.autotune == 1 and o.g_coupling == 0
     assert o.iface_mode == 0 and o.gamma == 8 and o.dense_max == 32768
-    assert not o.alloc and not o.free and o.alloc_ctx is None
+    assert not o.dev_alloc and not o.dev_free and o.alloc_ctx is None
 
 
 def _arrays(p):
@@ -183,10 +183,10 @@ def test_setup_validates_before_device_work(problem_cache, lib):
     o = R.rsd_options_default()
     o.host_pointers = 1
     only_alloc = R.ALLOC_FN(lambda nbytes, ctx: None)
-    o.alloc = only_alloc
+    o.dev_alloc = only_alloc
     msg = _expect(1, lambda: R.rsd_setup(rp, ci, v, p.parent.astype(np.int32),
                                          p.dof_node.astype(np.int32), o, stream=0))
-    assert "alloc and free" in msg, msg
+    assert "dev_alloc and dev_free" in msg, msg
     # a non-symmetric K needs the gamma interface mode and FP64 / FP32 sub-domains
     for mode, prec, code in ((0, 0, 8), (2, 0, 8), (1, 2, 8), (1, 0, None)):
         o = R.rsd_options_default()
