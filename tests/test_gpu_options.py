@@ -9,6 +9,7 @@ caller-supplied device allocator (rsd_options.alloc / free), through the C ABI.
   allocator (closing the handle returns exactly its device bytes there; the default
   handle's blocks are not PyTorch's), and applies and solves give the default handle's
   bits.
+* a handle on a caller's stream gives the default-stream handle's bits.
 """
 import numpy as np
 import pytest
@@ -91,3 +92,28 @@ def test_torch_allocator(problem_cache):
     assert out["default"][3] == 0
     assert np.array_equal(out["torch"][0], out["default"][0])
     assert np.array_equal(out["torch"][1], out["default"][1])
+
+
+def test_user_stream(problem_cache):
+    """A handle on a caller's stream (rsd_setup / apply / solve all on it, the applies
+    eager and then replayed from the captured graph): the default-stream handle's bits."""
+    _log("user stream")
+    p = problem_cache("diffusion", 13, 2, 1.0, 2)
+    R = np.random.default_rng(44).uniform(-1, 1, size=(p.n, 3))
+    hd = _handle(p)
+    zd = hd.apply(_cm(R)).cpu().numpy()
+    Xd, std, infod = hd.solve(_cm(R), rtol=1e-10)
+    Xd = Xd.cpu().numpy()
+    hd.close()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        h = _handle(p, stream=s)
+        Rs = _cm(R)
+        for rep in range(3):
+            z = h.apply(Rs).cpu().numpy()
+            X, st, info = h.solve(Rs, rtol=1e-10)
+            X = X.cpu().numpy()
+            assert np.array_equal(z, zd), rep
+            assert st == std == 0 and info == infod and np.array_equal(X, Xd), rep
+        h.close()
+    torch.cuda.synchronize()
