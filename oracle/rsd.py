@@ -23,7 +23,9 @@ What it computes (Sampath et al., "Recursive Schur Decomposition"):
   and the interface system is solved either exactly (dense Cholesky of the
   assembled S~_t: the limit of infinitely many inner iterations) or, as in the
   paper's experiments, by a fixed number gamma of unpreconditioned GMRES
-  iterations started from zero.
+  iterations started from zero.  A third mode mixes the two per level of the tree
+  (the internal nodes of one depth): the levels whose largest interface exceeds a
+  size limit take the inexact solve, the others the exact one.
 
 Readings taken where the paper describes only 2-D strips (binary trees):
 
@@ -40,7 +42,9 @@ Readings taken where the paper describes only 2-D strips (binary trees):
   "leaf_only" keeps only the C_t leaf terms (the literal 2-D formula).
 
 Parity: this module is pinned by the CPU tests (closed forms, brute-force
-dense inverses, the explicit dense form of the preconditioner, and the
+dense inverses, the explicit dense form of the preconditioner -- with either
+right-hand side, for symmetric and non-symmetric K --, a block sweep with
+minimal-residual Krylov steps for the inexact and per-level modes, and the
 paper's printed iteration counts).
 """
 from __future__ import annotations
@@ -98,17 +102,23 @@ class RSDOracle:
 
     interface: "dense"  -- solve S~_t u = g exactly (Cholesky of the assembled S~_t)
                "gamma"  -- gamma steps of unpreconditioned GMRES from zero (paper mode)
+               "hybrid" -- per level of the tree (the internal nodes of one depth):
+                           gamma steps where the level's largest interface has more
+                           than dense_max dofs, exact solves elsewhere
     coupling:  "full" | "leaf_only"  (see the module docstring)
     """
 
     def __init__(self, K, parent, dof_node, interface: str = "dense", gamma: int | None = None,
-                 coupling: str = "full"):
-        if interface not in ("dense", "gamma"):
+                 coupling: str = "full", dense_max: int | None = None):
+        if interface not in ("dense", "gamma", "hybrid"):
             raise ValueError(interface)
         if coupling not in ("full", "leaf_only"):
             raise ValueError(coupling)
-        if interface == "gamma" and (gamma is None or gamma < 1):
-            raise ValueError("gamma mode needs gamma >= 1")
+        if interface in ("gamma", "hybrid") and (gamma is None or gamma < 1):
+            raise ValueError("gamma and hybrid modes need gamma >= 1")
+        if interface == "hybrid" and (dense_max is None or dense_max < 0):
+            raise ValueError("hybrid mode needs dense_max >= 0")
+        self.dense_max = dense_max
         self.K = sp.csr_matrix(K, dtype=np.float64)
         self.n = self.K.shape[0]
         self.interface = interface
@@ -153,7 +163,19 @@ class RSDOracle:
                     self.K_Il[(t, l)] = blk
                     self.K_lI[(l, t)] = K[d][:, I]
             self.C[t] = Ct
-            if interface == "dense" and I.size:
+        # interface solve of every internal node: exact or gamma inner GMRES steps
+        internal = [t for t in range(H.T) if not H.is_leaf[t]]
+        largest = {}
+        for t in internal:
+            d = int(H.level[t])
+            largest[d] = max(largest.get(d, 0), self.I[t].size)
+        self.inexact = {}
+        for t in internal:
+            if interface == "hybrid":
+                self.inexact[t] = largest[int(H.level[t])] > dense_max
+            else:
+                self.inexact[t] = interface == "gamma"
+            if not self.inexact[t] and self.I[t].size:
                 self.S_chol[t] = self._factor(self.schur_dense(t))
 
     # -- building blocks -------------------------------------------------------------
@@ -227,7 +249,7 @@ class RSDOracle:
     def interface_solve(self, t: int, g: np.ndarray) -> np.ndarray:
         if g.size == 0:
             return g.copy()
-        if self.interface == "dense":
+        if not self.inexact[t]:
             return self._solve(self.S_chol[t], g)
         return self.inner_gmres(t, g, self.gamma)
 

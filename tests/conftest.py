@@ -15,13 +15,22 @@ def pytest_configure(config):
 
 @functools.lru_cache(maxsize=None)
 def cached_problem(kind, *args):
-    from workloads import config_problem, diffusion_problem, strip_problem
+    from workloads import (config_problem, diffusion_problem, elasticity_problem,
+                           skew_diffusion_problem, strip_problem)
     if kind == "config":
         return config_problem(*args)
     if kind == "diffusion":
         return diffusion_problem(*args)
     if kind == "strip":
         return strip_problem(*args)
+    if kind == "skew":
+        return skew_diffusion_problem(*args)
+    if kind == "diffusion_binary":           # one cut axis per depth (deeper trees)
+        return diffusion_problem(*args, tree="binary")
+    if kind == "skew_binary":
+        return skew_diffusion_problem(*args, tree="binary")
+    if kind == "elasticity":
+        return elasticity_problem(*args)
     raise KeyError(kind)
 
 

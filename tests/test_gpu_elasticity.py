@@ -58,3 +58,27 @@ def test_elasticity_eight_rhs(prec):
         xd = lu.solve(b)
         assert np.abs(X[:, j] - xd).max() <= 1e-8 * np.abs(xd).max()
     h.close()
+
+
+@pytest.mark.timeout(300)
+def test_elasticity_height3_iterations_match_oracle():
+    """Outer FGMRES(30) iteration counts on an uneven octree of height 3 (20^3 elements,
+    26,460 dofs: 512 leaves of 3-54 dofs, interfaces of 90-183, 651-930 and 3,660): the
+    GPU's count within 1 of the oracle's (rounding order only differs), both to a true
+    relative residual of 1e-10."""
+    from oracle import fgmres
+    _log("elasticity 20^3 h=3: oracle FGMRES")
+    p = elasticity_problem(20, 3, 0, nrhs=1)
+    b = p.b[:, 0]
+    o = RSDOracle(p.K, p.parent, p.dof_node)
+    xo, io = fgmres(p.K, b, o.apply, rtol=1e-10, restart=30, maxit=1000)
+    assert io["converged"]
+    h = _handle(p)
+    x, st, info = h.solve(torch.as_tensor(b).cuda(), rtol=1e-10, restart=30, maxit=1000)
+    x = x.cpu().numpy()
+    h.close()
+    its = info[0]["iterations"]
+    _log(f"elasticity 20^3 h=3: GPU {its} iterations, oracle {io['iterations']}")
+    assert st == 0
+    assert abs(its - io["iterations"]) <= 1, (its, io["iterations"])
+    assert np.linalg.norm(b - p.K @ x) <= 1e-10 * np.linalg.norm(b)

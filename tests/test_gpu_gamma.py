@@ -7,7 +7,7 @@ the inner GMRES result is a smooth function of g away from breakdown, so the app
 is 1e-8 relative (max norm).  Pins on the GPU path itself:
   * gamma >= dim(S~_t) gives back the exact interface solves (dense mode) to 1e-10;
   * the hybrid mode equals the pure modes bitwise when dense_max puts every level on
-    one side;
+    one side, and the oracle's per-level mode (same level rule) to 1e-8 otherwise;
   * the outer FGMRES iteration counts of the paper's Table 1 (Poisson) and Table 10
     (Navier-Lame) strips -- the fixtures the oracle is pinned to -- within +-2, and
     within +-1 of the oracle's own count, with the solution to 1e-8 of the
@@ -88,7 +88,8 @@ def test_gamma_at_dimension_is_exact(problem_cache):
 
 def test_hybrid_mode_selects_levels(problem_cache):
     p = problem_cache("diffusion", 13, 2, 1.0, 2)
-    r = _vec(np.random.default_rng(8).uniform(-1, 1, p.n))
+    rh = np.random.default_rng(8).uniform(-1, 1, p.n)
+    r = _vec(rh)
     z = {}
     for name, kw in (("dense", {}), ("gamma", dict(interface="gamma", gamma=3)),
                      ("hyb_all_dense", dict(interface="hybrid", gamma=3, dense_max=10 ** 6)),
@@ -99,11 +100,58 @@ def test_hybrid_mode_selects_levels(problem_cache):
         h.close()
     assert np.array_equal(z["hyb_all_dense"], z["dense"])
     assert np.array_equal(z["hyb_all_gamma"], z["gamma"])
-    # root interface (397 dofs) inexact, level-1 interfaces (61-91 dofs) exact
-    assert not np.array_equal(z["hyb_root_gamma"], z["dense"])
-    assert not np.array_equal(z["hyb_root_gamma"], z["gamma"])
     o = RSDOracle(p.K, p.parent, p.dof_node)
-    assert _rel(z["dense"], o.apply(r.cpu().numpy())) <= 1e-10
+    assert _rel(z["dense"], o.apply(rh)) <= 1e-10
+    # root interface (397 dofs) inexact, level-1 interfaces (61-91 dofs) exact: the
+    # oracle's per-level mode with the same rule
+    oh = RSDOracle(p.K, p.parent, p.dof_node, interface="hybrid", gamma=3, dense_max=200)
+    assert oh.inexact[0] and not any(oh.inexact[t] for t in oh.inexact if t != 0)
+    assert _rel(z["hyb_root_gamma"], oh.apply(rh)) <= 1e-8, _rel(z["hyb_root_gamma"], oh.apply(rh))
+
+
+HYBRID_CASES = [  # (problem, gamma, dense_max, coupling): a mix of exact and inexact levels
+    (("diffusion_binary", 12, 3, 1.0, 3), 4, 30, "full"),       # levels 0-1 gamma, 2 exact
+    (("diffusion_binary", 12, 3, 1.0, 3), 4, 30, "leaf_only"),
+    (("diffusion_binary", 12, 4, 0.5, 1), 3, 60, "full"),       # root gamma, levels 1-3 exact
+    (("diffusion", 17, 2, 1.0, 4), 5, 500, "full"),             # root of 721 dofs inexact
+]
+
+
+@pytest.mark.parametrize("key,gamma,dense_max,coupling", HYBRID_CASES)
+def test_hybrid_apply_matches_oracle(problem_cache, key, gamma, dense_max, coupling):
+    _log(f"hybrid apply {key} gamma={gamma} dense_max={dense_max} {coupling}")
+    p = problem_cache(*key)
+    o = RSDOracle(p.K, p.parent, p.dof_node, interface="hybrid", gamma=gamma,
+                  dense_max=dense_max, coupling=coupling)
+    assert any(o.inexact.values()) and not all(o.inexact.values())
+    R = np.random.default_rng(19).uniform(-1, 1, size=(p.n, 3))
+    h = _handle(p, interface="hybrid", gamma=gamma, dense_max=dense_max, coupling=coupling)
+    Z = h.apply(_cm(R)).cpu().numpy()
+    for j in range(3):
+        zo = o.apply(R[:, j])
+        assert _rel(Z[:, j], zo) <= 1e-8, (j, _rel(Z[:, j], zo))
+    h.close()
+
+
+@pytest.mark.parametrize("key,gamma", [(("skew", 13, 2, 0.3, 1), 4),
+                                       (("skew_binary", 12, 3, 0.3, 5), 3)])
+def test_nonsymmetric_3d_gamma_matches_oracle(problem_cache, key, gamma):
+    """A non-symmetric K in 3-D (Poisson plus a random antisymmetric part on its
+    pattern): general sub-domain inverses and gamma inner steps at every level, against
+    the oracle's LU path."""
+    _log(f"non-symmetric 3-D gamma {key}")
+    p = problem_cache(*key)
+    o = RSDOracle(p.K, p.parent, p.dof_node, interface="gamma", gamma=gamma)
+    assert not o.symmetric
+    r = np.random.default_rng(23).uniform(-1, 1, p.n)
+    h = _handle(p, interface="gamma", gamma=gamma, symmetric=False)
+    z = h.apply(_vec(r)).cpu().numpy()
+    assert _rel(z, o.apply(r)) <= 1e-8, _rel(z, o.apply(r))
+    x, st, info = h.solve(_vec(p.b[:, 0]), rtol=1e-10)
+    x = x.cpu().numpy()
+    assert st == 0
+    assert np.linalg.norm(p.b[:, 0] - p.K @ x) <= 1e-10 * np.linalg.norm(p.b[:, 0])
+    h.close()
 
 
 def _golden_rows():

@@ -14,6 +14,8 @@ Instances
 * ``config_problem("adjoint32")`` -- 32^3, k_e = exp(theta_e), theta_e ~ N(0, 0.5^2),
   octree of height 2; b ~ U[-1,1] and a target x_t ~ U[-1,1].
 * ``diffusion_problem(ne, height, ...)`` -- any size, for parity cases.
+* ``skew_diffusion_problem(ne, height, ...)`` -- a non-symmetric K on the same
+  pattern (Poisson plus a random antisymmetric part), for pins of the general path.
 * ``strip_problem(N, P, ...)`` -- the paper's 2-D strip workloads (Section 4):
   P sub-domains of N x N nodes in a binary tree, manufactured right-hand side
   b = K x_true with x_true ~ U[-1,1].
@@ -51,8 +53,11 @@ class Problem:
 
 
 def diffusion_problem(ne: int, height: int, sigma: float = 0.0, seed: int = 0,
-                      nrhs: int = 1, name: str | None = None, cut_fn=None) -> Problem:
-    """-div(k grad u) = f on ne^3 Q1 hexahedra with an octree of the given height.
+                      nrhs: int = 1, name: str | None = None, cut_fn=None,
+                      tree: str = "octree") -> Problem:
+    """-div(k grad u) = f on ne^3 Q1 hexahedra with a cut-plane tree of the given height:
+    tree = "octree" cuts every box along all three axes, tree = "binary" along one axis
+    per depth (x, y, z, x, ...), which gives deeper trees on small meshes.
 
     sigma = 0 gives Poisson (k = 1, no coefficient draw); otherwise
     k_e = exp(sigma * z_e) with z_e ~ N(0, 1) drawn first.  f ~ U[-1,1] per free
@@ -65,12 +70,15 @@ def diffusion_problem(ne: int, height: int, sigma: float = 0.0, seed: int = 0,
         theta = sigma * rng.standard_normal(ne ** 3)
         k = np.exp(theta)
     sysm = assemble_diffusion_3d(ne, k)
-    tree = build_box_tree(sysm.shape_nodes, height, cut_fn=cut_fn)
-    dof_node = dof_node_map(tree, sysm.free_ijk, 1)
+    if tree not in ("octree", "binary"):
+        raise ValueError(tree)
+    axes = None if tree == "octree" else (lambda d: (d % 3,))
+    box = build_box_tree(sysm.shape_nodes, height, axes_per_level=axes, cut_fn=cut_fn)
+    dof_node = dof_node_map(box, sysm.free_ijk, 1)
     b = rng.uniform(-1.0, 1.0, size=(sysm.K.shape[0], nrhs))
-    return Problem(name or f"diffusion{ne}_h{height}", sysm.K, tree.parent, dof_node, b,
+    return Problem(name or f"diffusion{ne}_h{height}", sysm.K, box.parent, dof_node, b,
                    meta=dict(ne=ne, height=height, sigma=sigma, seed=seed, k_elem=k,
-                             theta=theta, free_ijk=sysm.free_ijk, tree=tree))
+                             theta=theta, free_ijk=sysm.free_ijk, tree=box))
 
 
 def diffusion_fe_map(p: Problem) -> dict:
@@ -99,6 +107,26 @@ def config_problem(name: str, seed: int = 0, nrhs: int = 1) -> Problem:
         p.meta["x_target"] = rng.uniform(-1.0, 1.0, size=p.n)
         return p
     raise KeyError(name)
+
+
+def skew_diffusion_problem(ne: int, height: int, skew: float = 0.3, seed: int = 0,
+                           nrhs: int = 1, tree: str = "octree") -> Problem:
+    """A non-symmetric K on the 3-D diffusion pattern: K_d + skew (N - N^T), where K_d is
+    Poisson on ne^3 Q1 hexahedra and N holds, on the entries of K_d above the diagonal,
+    |K_d,ij| times U[-1, 1] drawn from `seed` (then f ~ U[-1, 1], nrhs columns).  The
+    symmetric part is K_d, so every principal block and Schur complement is
+    non-singular; the pattern stays symmetric."""
+    base = diffusion_problem(ne, height, 0.0, seed, 1, tree=tree)
+    rng = np.random.default_rng(seed)
+    Kd = base.K.tocsr()
+    U = sp.triu(Kd, k=1).tocoo()
+    N = sp.coo_matrix((np.abs(U.data) * rng.uniform(-1.0, 1.0, U.nnz), (U.row, U.col)),
+                      shape=Kd.shape)
+    K = (Kd + skew * (N - N.T)).tocsr()
+    K.sort_indices()
+    b = rng.uniform(-1.0, 1.0, size=(K.shape[0], nrhs))
+    return Problem(f"skew_diffusion{ne}_h{height}", K, base.parent, base.dof_node, b,
+                   meta=dict(ne=ne, height=height, skew=skew, seed=seed))
 
 
 def uneven_cuts(seed: int, lo_frac: float = 0.45, hi_frac: float = 0.55):
