@@ -1,8 +1,9 @@
 /*
  * rsd.h -- C ABI of the MI355X Recursive Schur Decomposition (RSD) solver library.
  *
- * The library solves K u = f for a sparse symmetric positive definite
- * finite-element matrix K with a Krylov method preconditioned by RSD
+ * The library solves K u = f for a sparse finite-element matrix K -- symmetric
+ * positive definite by default, or non-symmetric with a symmetric sparsity pattern
+ * (rsd_options.symmetric = 0) -- with a Krylov method preconditioned by RSD
  * (Sampath, Philip, Allu, Simunovic, "Recursive Schur Decomposition"; the
  * problem statement opens Section 3).  The caller describes K in CSR form and
  * the hierarchical domain decomposition of Section 2 as a tree whose leaves
@@ -15,10 +16,19 @@
  *     HIP device pointers owned by the caller; the library never frees them and
  *     keeps no reference after the call returns.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
- *     device work of a call is enqueued on it, in order.
+ *     device work of a call is enqueued on it, in order.  Calls on one handle are
+ *     ordered even across streams: each call records an event of the handle on its
+ *     stream when it returns, and a call on a different stream first makes its stream
+ *     wait for that event (every call on a handle shares the handle's work buffers).
+ *     Calls made while their stream is being captured into a graph skip both steps:
+ *     inside a capture the caller orders them.
  *   - Vectors are FP64, column-major n x nrhs blocks with leading dimension
  *     ld >= n, in the caller's dof numbering.
- *   - Handles are not thread-safe; distinct handles may be used concurrently.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently (each
+ *     holds its own streams, events and device memory).
+ *   - Process-wide caches: device blocks and pinned staging buffers released by
+ *     handles, and the auxiliary streams of destroyed handles, are kept for the next
+ *     handle (up to 48 GiB of device blocks per device) until rsd_release_cache.
  */
 #ifndef RSD_H_
 #define RSD_H_
@@ -49,7 +59,8 @@ typedef struct rsd_ctx* rsd_handle;
 
 /* Sparse matrix K (n x n) in CSR form: row_ptr[n+1] (row_ptr[0] = 0,
  * non-decreasing, row_ptr[n] = nnz), col_idx[nnz] strictly increasing within a
- * row, values[nnz].  K must be symmetric (structure checked, values assumed). */
+ * row, values[nnz].  The sparsity pattern must be symmetric (checked); the values
+ * must be too unless rsd_options.symmetric = 0 (not checked). */
 typedef struct {
   int32_t n;
   int64_t nnz;
@@ -280,8 +291,15 @@ typedef struct {
  * reset = 1 clears the accumulated times and launch counts afterwards. */
 rsd_status rsd_get_stats(rsd_handle h, rsd_stats* out, int32_t reset, void* stream);
 
-/* Frees the handle and its device memory (after its pending work completes). */
+/* Frees the handle and its device memory (after its pending work completes: the host
+ * waits for the handle's last call, not for the whole device). */
 void rsd_destroy(rsd_handle h);
+
+/* Returns to the HIP runtime the device blocks and pinned host buffers that destroyed
+ * handles left in the library's caches, and destroys the idle auxiliary streams, on
+ * `device` (every device when device < 0).  Memory and streams held by live handles are
+ * not touched.  Safe to call at any time from any thread; later set-ups refill the caches. */
+void rsd_release_cache(int32_t device);
 
 /* Message of the last error on h; with h = NULL, of the last failed rsd_setup
  * or rsd_analyze on the calling thread.  Never NULL. */

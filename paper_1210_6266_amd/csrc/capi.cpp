@@ -285,6 +285,13 @@ void rsd_destroy(rsd_handle h) {
   delete h;
 }
 
+void rsd_release_cache(int32_t device) {
+  try {
+    rsd::release_cache(device);
+  } catch (...) {
+  }
+}
+
 const char* rsd_last_error(rsd_handle h) {
   if (h) return h->err.c_str();
   return g_last_error.c_str();

@@ -154,15 +154,69 @@ void pfree(rsd_ctx* h, Pinned& b) {
   b.p = nullptr;
 }
 
-// The auxiliary (look-ahead) stream of a device, shared by the handles on it (default
-// priority; ordering between streams is carried by each handle's own events).
-hipStream_t aux_stream(rsd_ctx* h) {
-  static std::mutex mu;
-  static std::map<int, hipStream_t> streams;
-  std::lock_guard<std::mutex> lock(mu);
-  hipStream_t& s = streams[h->device];
-  if (!s) hip_check(h, hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
-  return s;
+// Auxiliary (look-ahead) streams: each handle holds one exclusively from set-up to
+// destroy, so the set-ups of distinct handles never share a stream; streams released by
+// destroyed handles wait in a per-device pool for the next handle (creating a stream is
+// not free) until release_cache.  Default priority; ordering between a handle's streams
+// is carried by its own events.
+struct AuxPool {
+  std::mutex mu;
+  std::map<int, std::vector<hipStream_t>> idle;   // device -> streams no handle holds
+};
+AuxPool& aux_pool() {
+  static AuxPool* p = new AuxPool();
+  return *p;
+}
+
+hipStream_t take_aux(rsd_ctx* h) {
+  AuxPool& p = aux_pool();
+  {
+    std::lock_guard<std::mutex> lock(p.mu);
+    std::vector<hipStream_t>& v = p.idle[h->device];
+    if (!v.empty()) {
+      hipStream_t st = v.back();
+      v.pop_back();
+      return st;
+    }
+  }
+  hipStream_t st = nullptr;
+  hip_check(h, hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+  return st;
+}
+
+void give_aux(int device, hipStream_t st) {
+  AuxPool& p = aux_pool();
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.idle[device].push_back(st);
+}
+
+// ---- ordering of a handle's calls across streams ------------------------------------------
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st == hipStreamCaptureStatusActive;
+}
+
+// start of a call on s: wait for the handle's previous call when it ran on another stream
+void enter(rsd_ctx* h, hipStream_t s) {
+  if (h->has_last && h->last_s != s && !capturing(s))
+    hip_check(h, hipStreamWaitEvent(s, h->ev_last, 0), "hipStreamWaitEvent");
+}
+
+// end of a call on s
+void leave(rsd_ctx* h, hipStream_t s) {
+  if (capturing(s)) return;
+  hip_check(h, hipEventRecord(h->ev_last, s), "hipEventRecord");
+  h->last_s = s;
+  h->has_last = true;
+}
+
+// the host waits until every call made on the handle so far has completed
+void wait_idle(rsd_ctx* h) {
+  if (h->has_last) hip_check(h, hipEventSynchronize(h->ev_last), "hipEventSynchronize");
 }
 
 // Packs many host arrays into one device allocation and one host-to-device copy from
@@ -205,7 +259,7 @@ struct Timer {
   hipEvent_t a = nullptr;
   Timer(rsd_ctx* h_, int cls_, hipStream_t s_) : h(h_), cls(cls_), s(s_) {
     h->launches[cls]++;
-    if (!h->opt.timing) return;
+    if (!h->opt.timing || h->no_events) return;
     a = take();
     hip_check(h, hipEventRecord(a, s), "hipEventRecord");
   }
@@ -417,10 +471,12 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->setup_wall[0] = ms_since(w0);
     const auto w1 = std::chrono::steady_clock::now();
     hip_check(h, hipGetDevice(&h->device), "hipGetDevice");
-    // auxiliary stream (shared, default priority) and events of the inversion look-ahead
-    h->aux = aux_stream(h);
+    // auxiliary stream (the handle's own, default priority), events of the inversion
+    // look-ahead and of the ordering between calls
+    h->aux = take_aux(h);
     hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
+    hip_check(h, hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming), "hipEventCreate");
     const Plan& P = h->P;
     h->group = 0;
     if (const char* g = std::getenv("RSD_SWEEP_GROUP")) {
@@ -629,6 +685,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     for (const DevBatch& d : h->lev) part_bytes = std::max(part_bytes, symv_part_bytes(d));
     // (levels solved matrix-free have num_items = 0: no symmetric product)
     h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
+    h->sympart_bytes = part_bytes;
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     up.done(h);
     h->setup_wall[1] = ms_since(w1);
@@ -644,6 +701,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
 rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
   try {
     h->cur = s;
+    enter(h, s);   // applies queued on another stream may still read the old blocks
     const auto w2 = std::chrono::steady_clock::now();
     const Plan& P = h->P;
     {
@@ -730,6 +788,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       hip_check(h, hipMemcpyAsync(fl.data(), h->flags, fl.size() * 4, hipMemcpyDeviceToHost, s),
                 "flags D2H");
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    leave(h, s);
     dfree(h, W);
     dfree(h, pbuf);
     for (int i = 0; i < 2; ++i) {
@@ -771,7 +830,7 @@ namespace {
 // u written to z at the level's rows.  Each product w = S~_t v is Alg. 1's S-MatVec with
 // the Sigma blocks: the own-node columns of K_tt, minus Sigma_l[I_t, I_t] v over every
 // leaf adjacent to t (the e buffer is free again once the level's g is formed).
-void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
+void gamma_solve(rsd_ctx* h, const ApplyWork& wk, size_t q, int nv, double* z, hipStream_t s) {
   const Plan& P = h->P;
   const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
@@ -788,39 +847,56 @@ void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
   a.item_b = G.item_b;
   a.item_e = G.item_e;
   a.sys_first = G.sys_first;
-  a.V = h->gm_V;
-  a.beta = h->gm_beta;
-  a.H = h->gm_H;
-  a.steps = h->gm_steps;
-  a.stop = h->gm_stop;
-  a.part = h->gm_part;
-  a.coef = h->gm_coef;
+  a.V = wk.gm_V;
+  a.beta = wk.gm_beta;
+  a.H = wk.gm_H;
+  a.steps = wk.gm_steps;
+  a.stop = wk.gm_stop;
+  a.part = wk.gm_part;
+  a.coef = wk.gm_coef;
   if (G.chunked)
     hip_check(h, launch_gmc(a, 0, 0, z, nullptr, s), "gmres start");
   else
-    hip_check(h, launch_gm_start(b, g, nv, z, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
-                                 h->gm_stop, s), "gmres start");
+    hip_check(h, launch_gm_start(b, g, nv, z, n, wk.gm_V, wk.gm_beta, wk.gm_H, wk.gm_steps,
+                                 wk.gm_stop, s), "gmres start");
   for (int j = 0; j < g; ++j) {
-    const double* vj = h->gm_V + int64_t(j) * nv * n;
-    double* w = h->gm_V + int64_t(j + 1) * nv * n;
+    const double* vj = wk.gm_V + int64_t(j) * nv * n;
+    double* w = wk.gm_V + int64_t(j + 1) * nv * n;
     hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segB, h->segC, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, vj, nullptr, 1.0, w, nv, n, h->xil, r0, r1, s),
+                                 h->ell_val, vj, nullptr, 1.0, w, nv, n, wk.xil, r0, r1, s),
               "S-MatVec K_tt");
     hip_check(h, launch_sigma_level(h->lev_own_items[q], h->sigma, h->sigma_fp32, h->sig_off_d,
-                                    h->B_off, h->B, vj, h->e, nv, n, nB, s), "S-MatVec Sigma");
+                                    h->B_off, h->B, vj, wk.e, nv, n, nB, s), "S-MatVec Sigma");
     hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos, h->B_off,
-                                  h->e, w, nv, n, nB, -1.0, s), "S-MatVec sum");
+                                  wk.e, w, nv, n, nB, -1.0, s), "S-MatVec sum");
     if (G.chunked)
       hip_check(h, launch_gmc(a, 1, j, nullptr, nullptr, s), "gmres step");
     else
-      hip_check(h, launch_gm_orth(b, g, nv, j, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps,
-                                  h->gm_stop, s), "gmres step");
+      hip_check(h, launch_gm_orth(b, g, nv, j, n, wk.gm_V, wk.gm_beta, wk.gm_H, wk.gm_steps,
+                                  wk.gm_stop, s), "gmres step");
   }
   if (G.chunked)
     hip_check(h, launch_gmc(a, 2, 0, nullptr, z, s), "gmres finish");
   else
-    hip_check(h, launch_gm_finish(b, g, nv, n, h->gm_V, h->gm_beta, h->gm_H, h->gm_steps, z, s),
+    hip_check(h, launch_gm_finish(b, g, nv, n, wk.gm_V, wk.gm_beta, wk.gm_H, wk.gm_steps, z, s),
               "gmres finish");
+}
+
+// the handle's own work buffers (sized for h->nvec vectors)
+ApplyWork own_work(const rsd_ctx* h) {
+  ApplyWork w;
+  w.e = h->e;
+  w.t = h->t;
+  w.xil = h->xil;
+  w.sympart = h->sympart;
+  w.gm_V = h->gm_V;
+  w.gm_beta = h->gm_beta;
+  w.gm_H = h->gm_H;
+  w.gm_part = h->gm_part;
+  w.gm_coef = h->gm_coef;
+  w.gm_steps = h->gm_steps;
+  w.gm_stop = h->gm_stop;
+  return w;
 }
 
 // z = M^{-1} r on internal-order vectors (Alg. 2 with exact interface solves):
@@ -832,14 +908,15 @@ void gamma_solve(rsd_ctx* h, size_t q, int nv, double* z, hipStream_t s) {
 // vectors that a kernel holds, and each vector's result is the one it has alone.
 void set_vec_pass(rsd_ctx* h, int nv);
 
-void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
+void core_apply(rsd_ctx* h, const ApplyWork& wk, int nv, const double* r, double* z,
+                hipStream_t s) {
   const Plan& P = h->P;
   set_vec_pass(h, nv);
   const int64_t n = P.n, nl = P.n_leaf, nB = std::max<int64_t>(1, int64_t(P.B.size()));
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
     if (h->opt.symmetric)    // tiles hold -K_ll^{-1}
-      hip_check(h, launch_symv(h->leaf_apply, r, h->sympart, -1.0, nullptr, z, nv, n, s),
+      hip_check(h, launch_symv(h->leaf_apply, r, wk.sympart, -1.0, nullptr, z, nv, n, s),
                 "leaf symv");
     else
       hip_check(h, launch_gen_matvec(h->gen, r, 1.0, z, nv, n, s), "leaf matvec");
@@ -848,29 +925,29 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
     Timer tm(h, RSD_T_COUPLING, s);
     // interface rows: q_B = r_B - K_{B,leaves} y
     hip_check(h, launch_ell_spmv(nl, n - nl, h->prow, h->segA, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, z, nv, n, h->xil, 0, nl, s), "condense");
-    hip_check(h, launch_fill(h->e, nB * nv, 0.0, s), "fill e");
+                                 h->ell_val, z, r, -1.0, z, nv, n, wk.xil, 0, nl, s), "condense");
+    hip_check(h, launch_fill(wk.e, nB * nv, 0.0, s), "fill e");
   }
   for (size_t q = 0; q < h->lev.size(); ++q) {
     {
       Timer tm(h, RSD_T_COUPLING, s);
       hip_check(h, launch_sigma_level(h->lev_items[q], h->sigma, h->sigma_fp32, h->sig_off_d,
-                                      h->B_off, h->B, z, h->e, nv, n, nB, s), "sigma level");
+                                      h->B_off, h->B, z, wk.e, nv, n, nB, s), "sigma level");
       // g_t = q_t - K_{t, deeper interfaces} u - sum over adjacent leaves of e_l
       const int64_t r0 = P.level_dof_begin[q], r1 = P.level_dof_end[q];
       if (h->opt.g_coupling == RSD_COUPLING_FULL)   // the direct couplings to deeper levels
         hip_check(h, launch_ell_spmv(r0, r1 - r0, h->segA, h->segB, h->prow, h->ell_off,
-                                     h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, h->xil, nl,
+                                     h->ell_col, h->ell_val, z, z, -1.0, z, nv, n, wk.xil, nl,
                                      r0, s), "level rhs");   // deeper levels come first: [nl, r0)
       hip_check(h, launch_level_adj(r0, r1 - r0, nl, h->adj_ptr, h->adj_leaf, h->adj_pos,
-                                    h->B_off, h->e, z, nv, n, nB, 1.0, s), "level adjacency");
+                                    h->B_off, wk.e, z, nv, n, nB, 1.0, s), "level adjacency");
     }
     {
       Timer tm(h, RSD_T_IFACE_APPLY, s);
       if (h->gam_level[q])      // u = gamma GMRES steps on S~ u = g (paper mode)
-        gamma_solve(h, q, nv, z, s);
+        gamma_solve(h, wk, q, nv, z, s);
       else                      // u = S~^{-1} g (tiles hold -S~^{-1})
-        hip_check(h, launch_symv(h->lev[q], z, h->sympart, -1.0, nullptr, z, nv, n, s),
+        hip_check(h, launch_symv(h->lev[q], z, wk.sympart, -1.0, nullptr, z, nv, n, s),
                   "interface symv");
     }
   }
@@ -878,16 +955,16 @@ void core_apply(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
     Timer tm(h, RSD_T_COUPLING, s);
     // leaf rows: r_l - K_{l,B} u_B
     hip_check(h, launch_ell_spmv(0, nl, h->segA, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, h->t, nv, n, h->xil, nl, n, s),
+                                 h->ell_val, z, r, -1.0, wk.t, nv, n, wk.xil, nl, n, s),
               "back-substitution rhs");
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
     if (h->opt.symmetric)
-      hip_check(h, launch_symv(h->leaf_apply, h->t, h->sympart, -1.0, nullptr, z, nv, n, s),
+      hip_check(h, launch_symv(h->leaf_apply, wk.t, wk.sympart, -1.0, nullptr, z, nv, n, s),
                 "leaf symv");
     else
-      hip_check(h, launch_gen_matvec(h->gen, h->t, 1.0, z, nv, n, s), "leaf matvec");
+      hip_check(h, launch_gen_matvec(h->gen, wk.t, 1.0, z, nv, n, s), "leaf matvec");
   }
 }
 
@@ -999,7 +1076,7 @@ void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s
   if (h->opt.autotune && nv >= 2 && nv <= kRhsGroup && !h->tuned[size_t(nv)])
     autotune_apply(h, nv, s);            // before this nv's graph is captured
   if (!h->opt.graphs || h->opt.timing) {
-    core_apply(h, nv, r, z, s);
+    core_apply(h, own_work(h), nv, r, z, s);
     return;
   }
   const size_t bytes = sizeof(double) * size_t(nv) * size_t(h->P.n);
@@ -1014,7 +1091,7 @@ void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s
     hip_check(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal),
               "begin capture");
     try {
-      core_apply(h, nv, h->rin, h->zin, h->cap);
+      core_apply(h, own_work(h), nv, h->rin, h->zin, h->cap);
     } catch (...) {
       (void)hipStreamEndCapture(h->cap, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -1033,7 +1110,7 @@ void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s
 // Apply work vectors (e, t, rin, zin, xil, the inner GMRES scratch) for nv vectors.
 void ensure_vectors(rsd_ctx* h, int nv) {
   if (h->nvec >= nv) return;
-  hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
+  wait_idle(h);                         // the handle's queued work may use the old buffers
   drop_graphs(h);                       // they refer to the buffers replaced here
   ensure_gamma(h, nv);
   for (double* p : {h->e, h->t, h->rin, h->zin, h->xil}) dfree(h, p);
@@ -1049,7 +1126,7 @@ void ensure_vectors(rsd_ctx* h, int nv) {
 // Krylov work space for restart length m and nr right-hand sides in lockstep.
 void ensure_krylov(rsd_ctx* h, int m, int nr) {
   if (h->kry_m >= m && h->kry_nr >= nr && h->V) return;
-  if (h->V) hip_check(h, hipDeviceSynchronize(), "hipDeviceSynchronize");   // before reuse
+  if (h->V) wait_idle(h);               // the handle's queued work may use the old buffers
   for (double* p : {h->V, h->Z, h->w, h->hdev, h->tmp, h->part, h->scal, h->bint, h->xint})
     dfree(h, p);
   pfree(h, h->hhost_block);
@@ -1368,6 +1445,7 @@ rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, doub
                         int64_t ldz, hipStream_t s) {
   try {
     const int64_t n = h->P.n;
+    enter(h, s);
     for (int j0 = 0; j0 < nrhs; j0 += kRhsGroup) {
       const int c = std::min(kRhsGroup, nrhs - j0);
       ensure_vectors(h, c);
@@ -1375,6 +1453,7 @@ rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, doub
       apply_vectors(h, c, h->rin, h->zin, s);
       permute(h, c, h->zin, n, z + size_t(j0) * ldz, ldz, 1, s);
     }
+    leave(h, s);
     return RSD_OK;
   } catch (const Fail& f) {
     return f.st;
@@ -1385,6 +1464,7 @@ rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, doubl
                        int64_t ldy, hipStream_t s) {
   try {
     const int64_t n = h->P.n;
+    enter(h, s);
     for (int j0 = 0; j0 < nrhs; j0 += kRhsGroup) {
       const int c = std::min(kRhsGroup, nrhs - j0);
       ensure_vectors(h, c);
@@ -1392,6 +1472,7 @@ rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, doubl
       core_spmv(h, c, h->rin, nullptr, 1.0, h->zin, s);
       permute(h, c, h->zin, n, y + size_t(j0) * ldy, ldy, 1, s);
     }
+    leave(h, s);
     return RSD_OK;
   } catch (const Fail& f) {
     return f.st;
@@ -1415,6 +1496,7 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
     }
     const bool pcg = o.method == RSD_SOLVER_PCG;
     const int group = pcg ? 1 : std::min(kRhsGroup, std::max(nrhs, 1));
+    enter(h, s);
     ensure_krylov(h, pcg ? 4 : o.restart, group);
     ensure_vectors(h, group);
     const int64_t n = h->P.n;
@@ -1439,6 +1521,7 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
       }
     }
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+    leave(h, s);
     if (worst == RSD_ERR_NOT_CONVERGED) h->err = "Krylov iteration reached maxit";
     if (worst == RSD_ERR_BREAKDOWN) h->err = "NaN/Inf or breakdown in the Krylov recurrence";
     return worst;
@@ -1476,7 +1559,9 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
 
 void engine_free(rsd_ctx* h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  // every call of the handle ends with its work joined onto the call's stream and ev_last
+  // recorded there (set-up and solves also synchronise), so this waits for all of it
+  if (h->has_last) (void)hipEventSynchronize(h->ev_last);
   drop_graphs(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   h->cap = nullptr;
@@ -1487,8 +1572,11 @@ void engine_free(rsd_ctx* h) {
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ev_main) (void)hipEventDestroy(h->ev_main);
   if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
-  h->ev_main = h->ev_aux = nullptr;
-  h->aux = nullptr;                    // shared by the device's handles: not destroyed
+  if (h->ev_last) (void)hipEventDestroy(h->ev_last);
+  h->ev_main = h->ev_aux = h->ev_last = nullptr;
+  h->has_last = false;
+  if (h->aux) give_aux(h->device, h->aux);   // idle: its work was joined and completed
+  h->aux = nullptr;
   BlockCache& c = cache_of(h->device);
   for (auto& p : h->allocs) {                                           // work is complete
     if (h->opt.dev_free)
@@ -1500,6 +1588,26 @@ void engine_free(rsd_ctx* h) {
   h->device_bytes = 0;
   pfree(h, h->hhost_block);
   h->hhost = nullptr;
+}
+
+void release_cache(int device) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return;
+  for (int d = 0; d < count; ++d) {
+    if (device >= 0 && d != device) continue;
+    if (hipSetDevice(d) != hipSuccess) continue;
+    {
+      AuxPool& p = aux_pool();
+      std::lock_guard<std::mutex> lock(p.mu);
+      for (hipStream_t st : p.idle[d]) (void)hipStreamDestroy(st);
+      p.idle[d].clear();
+    }
+    cache_drain(cache_of(d), false);
+    cache_drain(cache_of(-1 - d), true);
+  }
+  (void)hipSetDevice(cur);
 }
 
 }  // namespace rsd

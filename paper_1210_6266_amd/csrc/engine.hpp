@@ -18,6 +18,15 @@ struct Pinned {
   void* p = nullptr;
   size_t bytes = 0;
 };
+// Work buffers of one preconditioner application (internal order, nv vectors): the
+// handle's own (grown on demand), or carved from caller-independent static memory.
+struct ApplyWork {
+  double *e = nullptr, *t = nullptr, *xil = nullptr;   // xil: only for nv > 1
+  void* sympart = nullptr;                             // symmetric-product partials
+  double *gm_V = nullptr, *gm_beta = nullptr, *gm_H = nullptr, *gm_part = nullptr,
+         *gm_coef = nullptr;                           // inexact interface solves
+  int32_t *gm_steps = nullptr, *gm_stop = nullptr;
+};
 }  // namespace rsd
 
 struct rsd_ctx {
@@ -27,6 +36,13 @@ struct rsd_ctx {
   int device = 0;
 
   hipStream_t cur = nullptr;      // stream of the running call
+  // Ordering between calls on different streams: every call records ev_last on its
+  // stream when it ends; a call on another stream first waits for it (calls made while
+  // their stream is being captured into a graph are left to the caller's ordering).
+  hipEvent_t ev_last = nullptr;
+  hipStream_t last_s = nullptr;
+  bool has_last = false;
+  int no_events = 0;              // 1: the timers count launches but create no events
   // every device allocation of the handle (block, size as allocated)
   std::vector<std::pair<void*, size_t>> allocs;
   int64_t device_bytes = 0;
@@ -54,7 +70,7 @@ struct rsd_ctx {
   std::vector<rsd::SigmaLevelItems> lev_items;       // Sigma products against deeper levels
   std::vector<rsd::SigmaLevelItems> lev_own_items;   // and against the level itself (gamma)
   int32_t* flags = nullptr;  // one per leaf, then one per interface
-  hipStream_t aux = nullptr;          // look-ahead stream of the inversions
+  hipStream_t aux = nullptr;          // look-ahead stream of the inversions (held exclusively)
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int group = 0;             // pivot tiles per sweep step (0: by batch size)
 
@@ -89,6 +105,7 @@ struct rsd_ctx {
   int32_t last_tuned = 0;
   double *gm_part = nullptr, *gm_coef = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
+  size_t sympart_bytes = 0;
 
   // Krylov work space (grown on demand)
   int kry_m = 0, kry_nr = 0;   // restart length, right-hand sides in lockstep
@@ -122,6 +139,9 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
                         hipStream_t s);
 rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s);
 void engine_free(rsd_ctx* h);
+// frees the cached device blocks, pinned staging buffers and idle auxiliary streams
+// of `device` (every device when device < 0) that no live handle holds
+void release_cache(int device);
 void fill_analysis(const Plan& P, rsd_analysis* a);
 
 }  // namespace rsd

@@ -1,7 +1,8 @@
 """ctypes binding of the C ABI in include/rsd.h (argument marshalling only).
 
 The functions keep the C names (rsd_setup, rsd_apply, rsd_solve, rsd_spmv,
-rsd_update_values, rsd_get_stats, rsd_destroy, rsd_last_error, rsd_analyze).
+rsd_update_values, rsd_get_stats, rsd_destroy, rsd_last_error, rsd_release_cache,
+rsd_analyze).
 Device arrays are PyTorch tensors on the current HIP device; PyTorch only
 provides the device memory and the stream.  Every step of the method runs in
 librsd.so; when the library is missing, loading raises instead of falling back.
@@ -90,7 +91,7 @@ COEF = {"linear": 0, "exp": 1}
 
 EXPORTS = ["rsd_options_default", "rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv",
            "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_destroy", "rsd_last_error",
-           "rsd_fe_assemble", "rsd_fe_grad"]
+           "rsd_release_cache", "rsd_fe_assemble", "rsd_fe_grad"]
 
 
 def library_path() -> str:
@@ -125,6 +126,8 @@ def load():
     lib.rsd_destroy.restype = None
     lib.rsd_last_error.argtypes = [vp]
     lib.rsd_last_error.restype = C.c_char_p
+    lib.rsd_release_cache.argtypes = [i32]
+    lib.rsd_release_cache.restype = None
     lib.rsd_fe_assemble.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp]
     lib.rsd_fe_grad.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp, vp, vp]
     for f in ["rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv", "rsd_solve",
@@ -267,6 +270,12 @@ def rsd_destroy(handle):
         load().rsd_destroy(handle)
 
 
+def rsd_release_cache(device: int = -1):
+    """Returns the library's cached device blocks, pinned buffers and idle streams to the
+    runtime (device < 0: every device)."""
+    load().rsd_release_cache(int(device))
+
+
 # ------------------------------------------------------------------ convenience
 def torch_empty_like(t):
     return t.new_empty(t.shape)
@@ -284,7 +293,10 @@ class RSD:
         interface has more than dense_max dofs).  coupling: "full" or "leaf_only" (the
         right-hand side of the interface systems, rsd_options.g_coupling).  allocator:
         None (the library's own block cache) or "torch" (the handle's device memory
-        comes from PyTorch's caching allocator on the handle's stream)."""
+        comes from PyTorch's caching allocator, tied to the stream given here or, without
+        one, to the stream current at construction: blocks the handle grows later come
+        from that stream's pool too).  stream: None (torch's current stream at each
+        call) or a fixed stream; calls on other streams are ordered by the library."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 

@@ -117,3 +117,38 @@ def test_user_stream(problem_cache):
             assert st == std == 0 and info == infod and np.array_equal(X, Xd), rep
         h.close()
     torch.cuda.synchronize()
+
+
+def test_calls_on_two_streams_are_ordered(problem_cache):
+    """Two applies on one handle from different streams with no synchronisation between
+    them share the handle's work buffers: the library makes the second stream wait for
+    the first call, so both give the single-stream results bitwise.  Then an update of
+    the values on a third stream waits for the applies still reading the old blocks."""
+    _log("calls on two streams")
+    p = problem_cache("diffusion", 20, 2, 1.0, 3)
+    h = _handle(p)
+    rng = np.random.default_rng(4)
+    R = [torch.as_tensor(rng.uniform(-1, 1, p.n)).cuda() for _ in range(2)]
+    ref = [h.apply(r).clone() for r in R]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out = [torch.empty_like(R[0]) for _ in range(2)]
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            h.apply(R[0], out=out[0])
+        with torch.cuda.stream(s2):
+            h.apply(R[1], out=out[1])
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+    # values scaled by 2 on a third stream right behind an apply on s1: z halves exactly
+    rp, ci, v = p.csr_arrays()
+    v2 = torch.as_tensor(2.0 * v).cuda()
+    s3 = torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        h.apply(R[0], out=out[0])
+    with torch.cuda.stream(s3):
+        h.update_values(v2)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], ref[0])
+    assert torch.equal(h.apply(R[0]), 0.5 * ref[0])
+    h.close()
