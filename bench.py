@@ -89,6 +89,12 @@ def update_flops(sizes):
     return tot
 
 
+def potrf_flops(sizes):
+    """The set-up rows' unit of work: one Cholesky factorisation, n^3 / 3 flops per
+    matrix of order n (the sweep inversion executes about three times as many)."""
+    return sum(float(n) ** 3 / 3.0 for n in sizes)
+
+
 def measured_traffic(key):
     """HBM bytes per launch of kernel `key` (FETCH_SIZE + WRITE_SIZE, each scaled by
     what the counter reads for a plain copy of known size), as recorded by the
@@ -258,6 +264,37 @@ def bench_poisson256(a, dev):
         return dict(error=repr(e))
 
 
+def bf16_shape_error(a, dev):
+    """The 256^3 block's option set (BF16 sub-domain inverses formed in FP32, FP32 Sigma
+    and interface inverses, 8 matrix-free GMRES steps on interfaces above 5,000 dofs) on
+    the same tree shape at 64^3 -- octree of height 3, sub-domains of 8^3 elements (343
+    dofs), interfaces of 631 / 2,791 / 11,719 dofs -- applied to one right-hand side and
+    compared with the FP64 oracle's per-level mode: the error of the 16-bit path at the
+    largest size the oracle follows (the 256^3 tree itself is beyond it)."""
+    import torch
+
+    from oracle import RSDOracle
+    from paper_1210_6266_amd import RSD
+    from workloads import diffusion_problem
+    try:
+        p = diffusion_problem(64, 3, 0.0, a.seed)
+        rp, ci, v = p.csr_arrays()
+        opts = dict(leaf_prec="bf16", sigma_prec="fp32", iface_prec="fp32", root_prec="fp64",
+                    interface="hybrid", gamma=8, dense_max=5000)
+        h = RSD(rp, ci, v, p.parent, p.dof_node, **opts)
+        r = p.b[:, 0]
+        zg = h.apply(torch.as_tensor(r, device=dev)).cpu().numpy()
+        h.close()
+        zo = RSDOracle(p.K, p.parent, p.dof_node, interface="hybrid", gamma=8,
+                       dense_max=5000).apply(r)
+        return dict(max_rel=float(np.abs(zg - zo).max() / np.abs(zo).max()),
+                    l2_rel=float(np.linalg.norm(zg - zo) / np.linalg.norm(zo)),
+                    workload="Poisson 64^3, octree height 3 (512 sub-domains of 343 dofs; "
+                             "interfaces of 631, 2,791, 11,719 dofs), the poisson256 options")
+    except Exception as e:  # a report, not the product
+        return dict(error=repr(e))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -349,6 +386,19 @@ def main():
                          launches={kk: vv / k for kk, vv in nl.items()}, relres=relres,
                          device_bytes=last["device_bytes"], host_ms=last["host_analysis_ms"],
                          setup_wall_ms=last["setup_wall_ms"], steps=k)
+    # the same steps without the per-kernel HIP events (the library's defaults, graphs on)
+    plain_ms = {}
+    for name in variants:
+        prec = MIXED if name == "mixed" else FP64
+        k = res[name]["steps"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            h = RSD(d_rp, d_ci, d_v, d_par, d_dn, **prec)
+            _, st, _ = h.solve(b, rtol=1e-10, restart=30, maxit=1000)
+            h.close()
+        torch.cuda.synchronize()
+        plain_ms[name] = 1e3 * (time.perf_counter() - t0) / k
     reuse_sps = {}
     if a.reuse_solves > 0:
         for name in variants:
@@ -369,22 +419,26 @@ def main():
         "leaf_apply": ms.get("leaf_apply", 0.0),
     }
     dom = max(cand, key=cand.get)
-    if dom == "leaf_update":
-        flops = update_flops(leaf_sizes)
-        per_launch = flops / nlch["leaf_update"]
-        dur = ms["leaf_update"] / nlch["leaf_update"] * 1e-3
-        peak = PEAK["fp32_TFLOPs"] if fp32_leaf else PEAK["fp64_TFLOPs"]
-        roof = dict(kernel="k_sweep_update2 (sub-domain batch)", bound="mfma",
-                    achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s",
-                    profile_key="k_sweep_update2<%s, %d>" % ("float" if fp32_leaf else "double",
-                                                             group_tiles(ana["max_leaf_dofs"])))
-    elif dom == "root_update":
-        flops = update_flops([ana["max_iface_dofs"]])
-        per_launch = flops / nlch["root_update"]
-        dur = ms["root_update"] / nlch["root_update"] * 1e-3
-        roof = dict(kernel="k_sweep_update2<double> (root interface)", bound="mfma",
-                    achieved=per_launch / dur / 1e12, peak=PEAK["fp64_TFLOPs"], unit="TFLOP/s",
-                    profile_key="k_sweep_update2<double, %d>" % group_tiles(ana["max_iface_dofs"]))
+    if dom in ("leaf_update", "root_update"):
+        # achieved: n^3/3 per matrix (a Cholesky factorisation, the set-up rows' unit)
+        # spread over the inversion's MFMA update launches; executed: the flops those
+        # launches perform (the sweep inverts in place: about n^3 per matrix)
+        sizes = leaf_sizes if dom == "leaf_update" else [ana["max_iface_dofs"]]
+        fp32 = fp32_leaf and dom == "leaf_update"
+        nl = nlch[dom]
+        dur = ms[dom] / nl * 1e-3
+        per_launch = potrf_flops(sizes) / nl
+        executed = update_flops(sizes) / nl
+        peak = PEAK["fp32_TFLOPs"] if fp32 else PEAK["fp64_TFLOPs"]
+        roof = dict(kernel=("k_sweep_update2 (sub-domain batch)" if dom == "leaf_update"
+                            else "k_sweep_update2<double> (root interface)"),
+                    bound="mfma", achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s",
+                    work_unit="n^3/3 flops per matrix (Cholesky-equivalent) over the "
+                              "inversion's update launches",
+                    executed_TFLOPs=executed / dur / 1e12,
+                    executed_frac=executed / dur / 1e12 / peak,
+                    profile_key="k_sweep_update2<%s, %d>" % ("float" if fp32 else "double",
+                                                             group_tiles(max(sizes))))
     else:
         es = 4 if fp32_leaf else 8
         per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
@@ -406,43 +460,61 @@ def main():
         # row, x (gathered, read once from HBM at best) and y 8 B per row
         sb = 12 * p.K.nnz + 24 * p.n
         extra["spmv_GBps"] = sb / (ms["spmv"] / nlch["spmv"] * 1e-3) / 1e9
-    if R0["launches"].get("root_update"):
-        fl = update_flops([ana["max_iface_dofs"]])
-        extra["root_update_TFLOPs_fp64"] = fl / (ms["root_update"] * 1e-3) / 1e12
-    if R0["launches"].get("leaf_update"):
-        fl = update_flops(leaf_sizes)
-        extra["leaf_update_TFLOPs"] = fl / (ms["leaf_update"] * 1e-3) / 1e12
+    for cls, sizes in (("root_update", [ana["max_iface_dofs"]]), ("leaf_update", leaf_sizes)):
+        if R0["launches"].get(cls):
+            sec_cls = ms[cls] * 1e-3
+            extra[cls + "_TFLOPs_potrf_unit"] = potrf_flops(sizes) / sec_cls / 1e12
+            extra[cls + "_TFLOPs_executed"] = update_flops(sizes) / sec_cls / 1e12
 
     blocks = set(a.blocks.split(","))
     adjoint = bench_adjoint(a, dev) if "adjoint32" in blocks and a.only is None else None
     elastic = bench_elasticity(a, dev) if "elasticity48" in blocks and a.only is None else None
     big = bench_poisson256(a, dev) if "poisson256" in blocks and a.only is None else None
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload, and the
+    # error of every non-FP64 result against it
     cpu = None
+    errors = None
     if not a.no_cpu_baseline and a.only is None:
         try:
             from threadpoolctl import threadpool_info
 
             from oracle import RSDOracle
             threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-            t0 = time.perf_counter()
+            c0, t0 = time.process_time(), time.perf_counter()
             orc = RSDOracle(p.K, p.parent, p.dof_node)
             t1 = time.perf_counter()
             z = orc.apply(p.b[:, 0])
             t2 = time.perf_counter()
             _ = p.K @ z
             t3 = time.perf_counter()
+            c1 = time.process_time()
             beta = float(np.mean(res["fp64"]["its"])) if "fp64" in res else float(np.mean(R0["its"]))
             sec_solve = (t1 - t0) + beta * ((t2 - t1) + (t3 - t2))
             cpu = dict(value=1.0 / sec_solve, unit="solves/s", cores=threads, kind="oracle",
-                       sample=(f"FP64 oracle set-up ({t1 - t0:.1f} s) and one RSD apply "
-                               f"({t2 - t1:.2f} s) on the full 64^3 problem; time per solve = "
-                               f"set-up + {beta:.0f} x (apply + SpMV), beta = the FP64 FGMRES "
-                               f"iteration count"))
+                       estimate=True, effective_cores=(c1 - c0) / (t3 - t0),
+                       sample=(f"measured: FP64 oracle set-up ({t1 - t0:.1f} s), one RSD apply "
+                               f"({t2 - t1:.2f} s) and one SpMV on the full 64^3 problem; "
+                               f"estimated time per solve = set-up + {beta:.0f} x (apply + SpMV), "
+                               f"beta = the FP64 FGMRES iteration count on the GPU.  cores = "
+                               f"the BLAS thread pool (dense factorisations and solves); the "
+                               f"recursion itself is one Python thread (effective_cores = CPU "
+                               f"time / wall time of the sample)"))
+            # apply error of each variant against the FP64 oracle (same right-hand side)
+            errors = {}
+            for name in variants:
+                h = RSD(d_rp, d_ci, d_v, d_par, d_dn, **(MIXED if name == "mixed" else FP64))
+                zg = h.apply(b).cpu().numpy()
+                h.close()
+                errors[name] = dict(max_rel=float(np.abs(zg - z).max() / np.abs(z).max()),
+                                    l2_rel=float(np.linalg.norm(zg - z) / np.linalg.norm(z)))
+            errors["workload"] = "diffusion 64^3 (the headline problem): z = M^{-1} b"
         except Exception as e:  # the baseline is a report, not the product
             cpu = dict(value=None, unit="solves/s", cores=None, kind="oracle",
                        sample=f"failed: {e!r}")
+        if "poisson256" in set(a.blocks.split(",")):
+            errors = errors if errors is not None else {}
+            errors["bf16_hybrid_256cube_tree_shape"] = bf16_shape_error(a, dev)
 
     out = {
         "metric": METRIC,
@@ -476,6 +548,9 @@ def main():
         "elasticity48": elastic,
         "poisson256": big,
         "cpu_baseline": cpu,
+        "timing_instrumented": True,
+        "ms_per_step_uninstrumented": plain_ms,
+        "apply_error_vs_fp64_oracle": errors,
     }
     if "mixed" in res and "fp64" in res:
         out["mixed_vs_fp64_speedup"] = res["fp64"]["sec"] / res["mixed"]["sec"]

@@ -115,10 +115,12 @@ def test_rejects_non_separable_map(problem_cache, lib):
     assert "root-to-leaf" in msg
 
 
-@pytest.mark.parametrize("case", ["unsorted", "col_range", "row_ptr", "parent", "dof_node",
-                                  "asymmetric", "asymmetric_lower"])
-def test_rejects_invalid_input(problem_cache, lib, case):
-    p = problem_cache("diffusion", 6, 1, 0.0, 0)
+INVALID_CASES = ["unsorted", "col_range", "row_ptr", "parent", "dof_node", "asymmetric",
+                 "asymmetric_lower"]
+
+
+def invalid_case(p, case):
+    """(row_ptr, col_idx, parent, dof_node) of the 6^3 one-level problem with one defect."""
     rp, ci, par, dn = [x.copy() for x in _arrays(p)]
     if case == "unsorted":
         ci[rp[3]], ci[rp[3] + 1] = ci[rp[3] + 1], ci[rp[3]]
@@ -145,6 +147,13 @@ def test_rejects_invalid_input(problem_cache, lib, case):
         ci = np.delete(ci, k)
         rp = rp.copy()
         rp[6:] -= 1
+    return rp, ci, par, dn
+
+
+@pytest.mark.parametrize("case", INVALID_CASES)
+def test_rejects_invalid_input(problem_cache, lib, case):
+    p = problem_cache("diffusion", 6, 1, 0.0, 0)
+    rp, ci, par, dn = invalid_case(p, case)
     msg = _expect(1, lambda: R.rsd_analyze(rp, ci, par, dn))
     if case.startswith("asymmetric"):
         assert "structurally symmetric" in msg
