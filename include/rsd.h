@@ -225,6 +225,25 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
 rsd_status rsd_apply(rsd_handle h, int32_t nrhs, const double* r, int64_t ldr, double* z,
                      int64_t ldz, void* stream);
 
+/* rsd_apply for callers that cannot allocate device memory: code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * results as rsd_apply (each column bitwise what rsd_apply gives it), but every work
+ * buffer of the application comes from one static device area of 256 MiB per GPU
+ * (allocated with the library's code on each GPU it runs on and held until the process
+ * ends) instead of the handle's memory: the call allocates nothing, replays no graph,
+ * runs no autotuning and never waits on the host.  Columns go through in passes of up to
+ * 8, fewer when 8 do not fit the area.
+ * Ordering: all calls on one GPU share its area.  The library orders them (each call
+ * records a per-GPU event; a call on another stream first waits for it), except calls
+ * made while their stream is being captured into a graph: such calls, and every replay
+ * of the graphs they were captured into, race with any other use of the area on that GPU
+ * that can overlap them -- the caller must serialise those.
+ * Errors: INVALID_ARGUMENT (as rsd_apply; the handle's device is not current; a single
+ * column of this handle needs more than the 256 MiB area, rsd_last_error gives the
+ * size), DEVICE. */
+rsd_status rsd_apply_noalloc(rsd_handle h, int32_t nrhs, const double* r, int64_t ldr,
+                             double* z, int64_t ldz, void* stream);
+
 /* y = K x with the handle's matrix (the Krylov MatVec), x and y device arrays
  * (n x nrhs), not overlapping.  Asynchronous.  Errors: INVALID_ARGUMENT, DEVICE. */
 rsd_status rsd_spmv(rsd_handle h, int32_t nrhs, const double* x, int64_t ldx, double* y,

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "librsd.so")
-SOURCES = ["kernels.hip", "engine.cpp", "capi.cpp", "plan.cpp", "fe.hip"]
+SOURCES = ["kernels.hip", "engine.cpp", "capi.cpp", "plan.cpp", "fe.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

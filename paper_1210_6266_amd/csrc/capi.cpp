@@ -123,6 +123,7 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
     h = new rsd_ctx();
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = rsd::engine_init(h, csr, hier, opt, s);
+    if (st == RSD_OK) rsd::noalloc_register(h->device);
     if (st == RSD_OK) {
       const double* vals = csr->values;
       double* tmp = nullptr;

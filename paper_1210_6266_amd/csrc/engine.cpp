@@ -1460,6 +1460,90 @@ rsd_status engine_apply(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, doub
   }
 }
 
+namespace {
+
+// consecutive 256-byte aligned pieces of one block (sizes only while base is null)
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// the apply work of nv vectors laid out in a Carver: the permuted input and output, then
+// the buffers of ApplyWork sized as ensure_vectors / ensure_gamma size the handle's own
+void carve_apply(const rsd_ctx* h, int nv, Carver& c, double** rin, double** zin,
+                 ApplyWork* w) {
+  const size_t n = size_t(h->P.n), nB = std::max<size_t>(1, h->P.B.size());
+  *rin = c.take<double>(n * size_t(nv));
+  *zin = c.take<double>(n * size_t(nv));
+  w->t = c.take<double>(n * size_t(nv));
+  w->e = c.take<double>(nB * size_t(nv));
+  w->xil = nv > 1 ? c.take<double>(n * size_t(kEllVec)) : nullptr;
+  w->sympart = c.take<char>(h->sympart_bytes);
+  if (h->any_gamma) {
+    int32_t maxc = 1;
+    for (const DevBatch& b : h->lev) maxc = std::max(maxc, b.count);
+    const size_t g = size_t(h->opt.gamma), sl = size_t(nv) * size_t(maxc);
+    w->gm_V = c.take<double>((g + 1) * size_t(nv) * n);
+    w->gm_beta = c.take<double>(sl);
+    w->gm_H = c.take<double>(sl * (g + 1) * g);
+    w->gm_steps = c.take<int32_t>(sl);
+    w->gm_stop = c.take<int32_t>(sl);
+    w->gm_part = c.take<double>(size_t(nv) * size_t(std::max(1, h->gm_max_items)) * (g + 1));
+    w->gm_coef = c.take<double>(sl * (g + 2));
+  }
+}
+
+}  // namespace
+
+size_t apply_static_bytes(const rsd_ctx* h, int nv) {
+  Carver c;
+  double *rin = nullptr, *zin = nullptr;
+  ApplyWork w;
+  carve_apply(h, nv, c, &rin, &zin, &w);
+  return c.off;
+}
+
+rsd_status engine_apply_static(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, double* z,
+                               int64_t ldz, void* area, size_t cap, hipStream_t s) {
+  try {
+    int c = std::min(kRhsGroup, nrhs);
+    while (c > 1 && apply_static_bytes(h, c) > cap) --c;
+    const size_t need = apply_static_bytes(h, c);
+    if (need > cap) {
+      h->err = "rsd_apply_noalloc: one column of this handle needs " + std::to_string(need) +
+               " bytes of work memory; the static area holds " + std::to_string(cap);
+      return RSD_ERR_INVALID_ARGUMENT;
+    }
+    const int64_t n = h->P.n;
+    enter(h, s);
+    h->no_events = 1;   // the timers count launches only: no event objects are created
+    for (int j0 = 0; j0 < nrhs; j0 += c) {
+      const int cc = std::min(c, nrhs - j0);
+      Carver cv;
+      cv.base = static_cast<char*>(area);
+      double *rin = nullptr, *zin = nullptr;
+      ApplyWork w;
+      carve_apply(h, cc, cv, &rin, &zin, &w);
+      permute(h, cc, r + size_t(j0) * ldr, ldr, rin, n, 0, s);
+      core_apply(h, w, cc, rin, zin, s);
+      permute(h, cc, zin, n, z + size_t(j0) * ldz, ldz, 1, s);
+    }
+    h->no_events = 0;
+    leave(h, s);
+    return RSD_OK;
+  } catch (const Fail& f) {
+    h->no_events = 0;
+    return f.st;
+  }
+}
+
 rsd_status engine_spmv(rsd_ctx* h, int nrhs, const double* x, int64_t ldx, double* y,
                        int64_t ldy, hipStream_t s) {
   try {

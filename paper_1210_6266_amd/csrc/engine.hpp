@@ -138,10 +138,20 @@ rsd_status engine_solve(rsd_ctx* h, int nrhs, const double* b, int64_t ldb, doub
                         int64_t ldx, const rsd_solve_options* opt, rsd_solve_info* info,
                         hipStream_t s);
 rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s);
+// rsd_apply on caller-independent memory: every work buffer carved from [area, area +
+// cap) (device memory of the handle's device), no allocation, no graph, no autotuning,
+// no host synchronisation.  Passes of as many columns (up to 8) as fit;
+// RSD_ERR_INVALID_ARGUMENT when one column does not fit.
+rsd_status engine_apply_static(rsd_ctx* h, int nrhs, const double* r, int64_t ldr, double* z,
+                               int64_t ldz, void* area, size_t cap, hipStream_t s);
+// bytes engine_apply_static needs for passes of nv columns
+size_t apply_static_bytes(const rsd_ctx* h, int nv);
 void engine_free(rsd_ctx* h);
 // frees the cached device blocks, pinned staging buffers and idle auxiliary streams
 // of `device` (every device when device < 0) that no live handle holds
 void release_cache(int device);
 void fill_analysis(const Plan& P, rsd_analysis* a);
+// looks up the static work area of rsd_apply_noalloc on `device` (current)
+void noalloc_register(int device);
 
 }  // namespace rsd

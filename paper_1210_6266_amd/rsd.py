@@ -2,7 +2,7 @@
 
 The functions keep the C names (rsd_setup, rsd_apply, rsd_solve, rsd_spmv,
 rsd_update_values, rsd_get_stats, rsd_destroy, rsd_last_error, rsd_release_cache,
-rsd_analyze).
+rsd_apply_noalloc, rsd_analyze).
 Device arrays are PyTorch tensors on the current HIP device; PyTorch only
 provides the device memory and the stream.  Every step of the method runs in
 librsd.so; when the library is missing, loading raises instead of falling back.
@@ -91,7 +91,7 @@ COEF = {"linear": 0, "exp": 1}
 
 EXPORTS = ["rsd_options_default", "rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv",
            "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_destroy", "rsd_last_error",
-           "rsd_release_cache", "rsd_fe_assemble", "rsd_fe_grad"]
+           "rsd_release_cache", "rsd_apply_noalloc", "rsd_fe_assemble", "rsd_fe_grad"]
 
 
 def library_path() -> str:
@@ -117,6 +117,7 @@ def load():
     lib.rsd_setup.argtypes = [C.POINTER(rsd_csr), C.POINTER(rsd_hierarchy), C.POINTER(rsd_options),
                               vp, C.POINTER(vp)]
     lib.rsd_apply.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    lib.rsd_apply_noalloc.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     lib.rsd_spmv.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     lib.rsd_solve.argtypes = [vp, i32, vp, i64, vp, i64, C.POINTER(rsd_solve_options),
                               C.POINTER(rsd_solve_info), vp]
@@ -130,8 +131,9 @@ def load():
     lib.rsd_release_cache.restype = None
     lib.rsd_fe_assemble.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp]
     lib.rsd_fe_grad.argtypes = [C.POINTER(rsd_fe_map), vp, i32, vp, vp, vp, vp]
-    for f in ["rsd_analyze", "rsd_setup", "rsd_apply", "rsd_spmv", "rsd_solve",
-              "rsd_update_values", "rsd_get_stats", "rsd_fe_assemble", "rsd_fe_grad"]:
+    for f in ["rsd_analyze", "rsd_setup", "rsd_apply", "rsd_apply_noalloc", "rsd_spmv",
+              "rsd_solve", "rsd_update_values", "rsd_get_stats", "rsd_fe_assemble",
+              "rsd_fe_grad"]:
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -224,6 +226,14 @@ def rsd_apply(handle, r, z, stream=None):
     nrhs, ldr = _cols(r, r.shape[0])
     _, ldz = _cols(z, z.shape[0])
     _check(load().rsd_apply(handle, nrhs, _ptr(r), ldr, _ptr(z), ldz, _stream(stream)), handle)
+
+
+def rsd_apply_noalloc(handle, r, z, stream=None):
+    """rsd_apply on the library's static work area (no device allocation)."""
+    nrhs, ldr = _cols(r, r.shape[0])
+    _, ldz = _cols(z, z.shape[0])
+    _check(load().rsd_apply_noalloc(handle, nrhs, _ptr(r), ldr, _ptr(z), ldz, _stream(stream)),
+           handle)
 
 
 def rsd_spmv(handle, x, y, stream=None):
