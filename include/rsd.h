@@ -129,14 +129,23 @@ typedef struct {
   int32_t autotune;      /* 1: before the first application to 2..8 columns, time the
                             candidate numbers of vectors per pass (1, 2, 4) of every dense
                             batch's symmetric product on the handle's own blocks and keep
-                            the fastest (results do not depend on the choice); the choices
-                            are remembered per process for batches of the same shape      */
+                            the fastest; and on the first set-ups of each batch shape, time
+                            in turn the inversion schedules (look-ahead or serial steps;
+                            128 x 128 or 256 x 256 update super-tiles for BF16-split
+                            batches) and keep the fastest.  Results do not depend on any
+                            choice; the choices are remembered per process for batches of
+                            the same shape                                                   */
   int32_t symmetric;     /* 1: K is symmetric (sub-domains inverted by symmetric sweeps).
                             0: K may be non-symmetric (pattern still symmetric): dense
                             sub-domain inverses by Gauss-Jordan with partial pivoting (at
                             most 2,048 dofs, leaf_prec FP64 or FP32) and iface_mode GAMMA,
                             i.e. every interface solved by inner GMRES steps              */
   int32_t g_coupling;    /* RSD_COUPLING_FULL (default) or RSD_COUPLING_LEAF_ONLY          */
+  int32_t bf16_split;    /* FP32 blocks (leaf_prec, iface_prec FP32 or 16-bit): 1 (default)
+                            runs their inversions' trailing updates on the BF16 matrix cores,
+                            each FP32 operand split exactly into three BF16 parts and six
+                            products accumulated in FP32 (errors of FP32 order); 0 on the
+                            FP32 matrix cores.  The FP64 blocks are unaffected.             */
   /* Optional device allocator for the handle's memory (set both or neither; default
      NULL: the library's own cache of hipMalloc blocks).  dev_alloc(bytes, alloc_ctx)
      returns device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY);
@@ -150,7 +159,7 @@ typedef struct {
 
 /* Fills *opt with the defaults: all FP64, device pointers, no timing, exact
  * (dense) interface solves, gamma = 8, dense_max = 32768, graphs on, autotune on,
- * symmetric. */
+ * symmetric, full interface right-hand sides, BF16-split FP32 updates. */
 void rsd_options_default(rsd_options* opt);
 
 enum { RSD_SOLVER_FGMRES = 0, RSD_SOLVER_PCG = 1 };
@@ -304,6 +313,11 @@ typedef struct {
   int32_t vec_pass[8];     /* vectors per pass of the symmetric products chosen by the
                               autotuner (0: not tuned): [0] sub-domains, then the dense
                               interface levels, deepest first                  */
+  int32_t setup_variant[8]; /* inversion schedule of the last set-up, same batches:
+                              0 none, 1 look-ahead, 2 serial steps, 3 look-ahead with
+                              256 x 256 update super-tiles, 4 serial with them (the
+                              set-up autotuner's choice, or the candidate it was timing;
+                              every variant gives the same bits)              */
 } rsd_stats;
 
 /* Copies the handle's statistics (synchronises `stream` when timing is on).

@@ -53,6 +53,7 @@ void rsd_options_default(rsd_options* o) {
   o->autotune = 1;
   o->symmetric = 1;
   o->g_coupling = RSD_COUPLING_FULL;
+  o->bf16_split = 1;
   o->dev_alloc = nullptr;
   o->dev_free = nullptr;
   o->alloc_ctx = nullptr;
@@ -106,6 +107,8 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "autotune must be 0 or 1");
     if (opt->symmetric != 0 && opt->symmetric != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "symmetric must be 0 or 1");
+    if (opt->bf16_split != 0 && opt->bf16_split != 1)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "bf16_split must be 0 or 1");
     if (opt->g_coupling != RSD_COUPLING_FULL && opt->g_coupling != RSD_COUPLING_LEAF_ONLY)
       return fail(RSD_ERR_INVALID_ARGUMENT, "g_coupling must be RSD_COUPLING_FULL or "
                                             "RSD_COUPLING_LEAF_ONLY");

@@ -312,6 +312,7 @@ void upload_batch(rsd_ctx* h, Uploader& up, DevBatch* d, const SymBatch& b, bool
   up.add(&d->item_BJ, b.item_BJ);
   up.add(&d->item_base, b.item_base);
   d->fp32 = fp32 ? 1 : 0;
+  d->split16 = fp32 ? h->split16 : 0;
   if (!tiles) d->num_items = 0;
   if (tiles && b.total_elems > 0) {
     if (fp32)
@@ -336,10 +337,10 @@ int group_for(const rsd_ctx* h, const DevBatch& b) {
 }
 
 void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void* bbuf[2],
-                  int32_t* flags, int upd, hipStream_t s) {
+                  int32_t* flags, int upd, bool lookahead, hipStream_t s) {
   const int G = group_for(h, b);
   if (b.count == 0 || b.max_nt == 0) return;
-  if (G < 2) {
+  if (G < 2 || !lookahead) {
     for (int c0 = 0; c0 < b.max_nt; c0 += G) {
       hip_check(h, launch_sweep_step(b, c0, 0, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep pivot");
       hip_check(h, launch_sweep_step(b, c0, 1, pbuf, cbuf[0], bbuf[0], flags, G, s), "sweep panel");
@@ -378,6 +379,61 @@ void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void
               "sweep panel");
     hip_check(h, hipEventRecord(h->ev_aux, a), "hipEventRecord");
     hip_check(h, hipStreamWaitEvent(s, h->ev_aux, 0), "hipStreamWaitEvent");
+  }
+}
+
+// ---- set-up autotuner: the schedule and update shape of each batch's inversion ----------
+// Candidates, all with bitwise the same results (every tile receives the same updates from
+// the same operands in the same order): 0 look-ahead steps (the next pivot and panel run
+// beside the bulk update on the auxiliary stream), 1 serial steps (pivot, panel, whole
+// update); for BF16-split batches in four-tile groups also 2 / 3, the same with 256 x 256
+// update super-tiles.  The first set-ups of a batch shape in the process try the candidates
+// in turn, each timed with HIP events around the batch's inversion (read back after the
+// set-up's final synchronisation); once all are timed the fastest is kept for the shape (a
+// tie keeps the lower index).  With rsd_options.autotune = 0, candidate 0 throughout.
+struct InvTune {
+  std::vector<float> ms;
+  int32_t best = -1;
+};
+std::mutex g_inv_mu;
+std::unordered_map<std::string, InvTune> g_inv;
+
+int inv_candidates(const DevBatch& b, int G) {
+  if (G < 2) return 1;
+  return b.split16 && b.fp32 && G == 4 ? 4 : 2;
+}
+
+std::string inv_key(const SymBatch& sb, const DevBatch& d, int G) {
+  uint64_t hsh = 1469598103934665603ull;                 // FNV-1a over the sizes
+  for (int32_t v : sb.n) {
+    hsh ^= uint64_t(uint32_t(v));
+    hsh *= 1099511628211ull;
+  }
+  return std::to_string(d.fp32) + ":" + std::to_string(d.split16) + ":" + std::to_string(G) +
+         ":" + std::to_string(sb.count) + ":" + std::to_string(hsh);
+}
+
+// the candidate for this set-up of the batch; *tuning: time it
+int inv_pick(rsd_ctx* h, const std::string& key, int ncand, bool* tuning) {
+  *tuning = false;
+  if (ncand < 2) return 0;
+  std::lock_guard<std::mutex> lk(g_inv_mu);
+  InvTune& t = g_inv[key];
+  if (t.best >= 0) return t.best;
+  if (!h->opt.autotune) return 0;
+  *tuning = true;
+  return int(t.ms.size());
+}
+
+void inv_record(const std::string& key, int ncand, int cand, float ms) {
+  std::lock_guard<std::mutex> lk(g_inv_mu);
+  InvTune& t = g_inv[key];
+  if (t.best >= 0 || int(t.ms.size()) != cand) return;   // another handle timed it first
+  t.ms.push_back(ms);
+  if (int(t.ms.size()) == ncand) {
+    t.best = 0;
+    for (int c = 1; c < ncand; ++c)
+      if (t.ms[size_t(c)] < t.ms[size_t(t.best)]) t.best = c;
   }
 }
 
@@ -483,6 +539,7 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       const int v = std::atoi(g);
       h->group = (v == 1 || v == 2 || v == 4) ? v : 0;
     }
+    h->split16 = h->opt.bf16_split ? 1 : 0;
     // ---- upload structure (one allocation, one copy)
     Uploader up;
     up.add(&h->prow, P.prow);
@@ -738,10 +795,38 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     char* pbuf = dalloc<char>(h, need_p);
     void* cbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
     void* bbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
+    // one batch's inversion with the autotuner's candidate (timed while tuning)
+    struct Pending {
+      std::string key;
+      int ncand, cand;
+      hipEvent_t a, b;
+    };
+    std::vector<Pending> tuned;
+    auto invert = [&](DevBatch bb, const SymBatch& sb, int32_t* fl, int upd, int slot) {
+      const int G = group_for(h, bb);
+      const int ncand = inv_candidates(bb, G);
+      const std::string key = inv_key(sb, bb, G);
+      bool tuning = false;
+      const int cand = inv_pick(h, key, ncand, &tuning);
+      bb.wide = cand >= 2 ? 1 : 0;
+      if (slot < 8) h->setup_variant[slot] = cand + 1;
+      hipEvent_t a = nullptr, b = nullptr;
+      if (tuning) {
+        hip_check(h, hipEventCreate(&a), "hipEventCreate");
+        hip_check(h, hipEventCreate(&b), "hipEventCreate");
+        hip_check(h, hipEventRecord(a, s), "hipEventRecord");
+      }
+      invert_batch(h, bb, pbuf, cbuf, bbuf, fl, upd, (cand & 1) == 0, s);
+      if (tuning) {
+        hip_check(h, hipEventRecord(b, s), "hipEventRecord");
+        tuned.push_back({key, ncand, cand, a, b});
+      }
+    };
+    for (int32_t& v : h->setup_variant) v = 0;
     {
       Timer tm(h, RSD_T_LEAF_INVERSE, s);
       if (h->opt.symmetric)
-        invert_batch(h, h->leaf, pbuf, cbuf, bbuf, h->flags, RSD_T_LEAF_UPDATE, s);
+        invert(h->leaf, P.leaf_batch, h->flags, RSD_T_LEAF_UPDATE, 0);
       else
         hip_check(h, launch_gen_invert(h->gen, h->prow, h->segA, h->pcol, h->pval, h->flags, s),
                   "general sub-domain inverses");
@@ -777,8 +862,8 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       }
       {
         Timer tm(h, RSD_T_IFACE_INVERSE, s);
-        invert_batch(h, h->lev[q], pbuf, cbuf, bbuf, iflags + P.level_iface_begin[q],
-                     P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, s);
+        invert(h->lev[q], P.level_batch[q], iflags + P.level_iface_begin[q],
+               P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, int(1 + q));
       }
     }
     h->setup_wall[2] = ms_since(w2);
@@ -789,6 +874,12 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
                 "flags D2H");
     hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
     leave(h, s);
+    for (Pending& t : tuned) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) inv_record(t.key, t.ncand, t.cand, ms);
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
     dfree(h, W);
     dfree(h, pbuf);
     for (int i = 0; i < 2; ++i) {
@@ -1631,6 +1722,7 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
     for (int i = 0; i < 4; ++i) out->setup_wall_ms[i] = h->setup_wall[i];
     if (h->last_tuned > 0)
       for (int i = 0; i < 8; ++i) out->vec_pass[i] = h->vec_pass[size_t(h->last_tuned)][size_t(i)];
+    for (int i = 0; i < 8; ++i) out->setup_variant[i] = h->setup_variant[i];
     if (reset) {
       std::memset(h->time_ms, 0, sizeof(h->time_ms));
       std::memset(h->launches, 0, sizeof(h->launches));

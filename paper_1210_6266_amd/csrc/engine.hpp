@@ -73,6 +73,7 @@ struct rsd_ctx {
   hipStream_t aux = nullptr;          // look-ahead stream of the inversions (held exclusively)
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int group = 0;             // pivot tiles per sweep step (0: by batch size)
+  int split16 = 0;           // FP32 batches: sweep updates on the BF16 matrix cores (bf16_split)
 
   // apply work vectors (internal order)
   double *e = nullptr, *t = nullptr, *rin = nullptr, *zin = nullptr;   // nvec vectors each
@@ -103,6 +104,7 @@ struct rsd_ctx {
   std::vector<std::array<int32_t, 9>> vec_pass;
   std::array<bool, 9> tuned{};
   int32_t last_tuned = 0;
+  int32_t setup_variant[8] = {};            // set-up autotuner's candidate + 1 per batch
   double *gm_part = nullptr, *gm_coef = nullptr;
   double* sympart = nullptr;                // partial sums of the symmetric products
   size_t sympart_bytes = 0;

@@ -48,3 +48,29 @@ def test_autotuned_applies_match_untuned(opts):
     assert st == su == 0 and it == iu and np.array_equal(Xt.cpu().numpy(), Xu.cpu().numpy())
     ht.close()
     hu.close()
+
+
+@pytest.mark.parametrize("opts", [dict(leaf_prec="fp32", iface_prec="fp32", root_prec="fp64"),
+                                  dict()])
+def test_setup_autotuner_variants_bitwise(problem_cache, opts):
+    """The set-up autotuner: successive set-ups of one batch shape time every inversion
+    schedule (look-ahead or serial steps; for BF16-split batches in four-tile groups also
+    128 x 128 or 256 x 256 update super-tiles) and then keep the fastest.  Every schedule
+    gives the same bits: each handle's apply equals that of an untuned handle (look-ahead,
+    128 x 128) bitwise.  Tuning state is per process, so earlier tests may have timed some
+    candidates of this shape already; after at most four set-ups the choice is fixed."""
+    p = problem_cache("diffusion", 48, 2, 1.0, 6)      # leaves of 1,331 dofs (21 tiles)
+    r = torch.as_tensor(np.random.default_rng(14).uniform(-1, 1, p.n)).cuda()
+    hu = _handle(p, autotune=False, **opts)
+    zu = hu.apply(r)
+    assert hu.stats()["setup_variant"][0] == 1          # untuned: look-ahead, 128 x 128
+    hu.close()
+    seen = []
+    for _ in range(6):
+        h = _handle(p, autotune=True, **opts)
+        assert torch.equal(h.apply(r), zu)
+        seen.append(h.stats()["setup_variant"][0])
+        h.close()
+    ncand = 4 if opts else 2                            # BF16-split FP32 leaves: 4 candidates
+    assert all(1 <= v <= ncand for v in seen), seen
+    assert seen[-1] == seen[-2], seen                   # settled

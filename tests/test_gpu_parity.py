@@ -174,6 +174,35 @@ def test_mixed_precision_factors(problem_cache):
     h.close()
 
 
+@pytest.mark.parametrize("ne", [32, 48])
+def test_bf16_split_updates(problem_cache, ne):
+    """FP32 sub-domain and level-1 interface blocks inverted with their trailing updates on
+    the BF16 matrix cores (operands split exactly into three BF16 parts: the default,
+    rsd_options.bf16_split = 1) or on the FP32 ones: both within the FP32 bar of the FP64
+    oracle, different bits (the BF16 path ran), iteration counts within 1 of each other.
+    32^3: leaves of 343 dofs (two-tile pivot groups); 48^3: 1,331 (four-tile groups)."""
+    _log(f"bf16 split updates {ne}^3")
+    p = problem_cache("diffusion", ne, 2, 1.0, 6)
+    o = RSDOracle(p.K, p.parent, p.dof_node)
+    r = np.random.default_rng(21).uniform(-1, 1, p.n)
+    zo = o.apply(r)
+    b = p.b[:, 0]
+    res = {}
+    for split in (True, False):
+        h = _handle(p, leaf_prec="fp32", iface_prec="fp32", root_prec="fp64", bf16_split=split)
+        z = h.apply(_dev(r, torch.float64)).cpu().numpy()
+        err = np.abs(z - zo).max() / np.abs(zo).max()
+        _log(f"  bf16_split={split}: apply error vs oracle {err:.2e}")
+        assert 1e-9 < err <= 2e-4, (split, err)
+        x, st, info = h.solve(_dev(b, torch.float64), rtol=1e-10)
+        x = x.cpu().numpy()
+        assert st == 0 and np.linalg.norm(b - p.K @ x) / np.linalg.norm(b) <= 1e-10
+        res[split] = (z, info[0]["iterations"])
+        h.close()
+    assert not np.array_equal(res[True][0], res[False][0])
+    assert abs(res[True][1] - res[False][1]) <= 1
+
+
 def test_update_values(problem_cache):
     p1 = problem_cache("diffusion", 13, 2, 1.0, 2)
     p2 = problem_cache("diffusion", 13, 2, 1.0, 3)   # same pattern, new coefficients
