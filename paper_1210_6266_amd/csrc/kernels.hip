@@ -59,6 +59,13 @@ __host__ __device__ __forceinline__ void band_ij(int64_t s, int n, int* I, int* 
   }
 }
 
+// a load of data streamed once per use (matrix tiles, Sigma blocks, sparse slots): the
+// non-temporal hint keeps it from displacing reused data in the caches
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // element (r, c) of the symmetric matrix whose lower tiles start at base
 template <typename T>
 __device__ __forceinline__ T sym_elem(const T* base, int r, int c) {
@@ -224,8 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_ell_spmv(
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t kk = kb + u < k1 ? kb + u : k0;
-      ci[u] = c[kk * kEllSlice];
-      vi[u] = kb + u < k1 ? v[kk * kEllSlice] : 0.0;
+      ci[u] = ld_stream(c + kk * kEllSlice);
+      vi[u] = kb + u < k1 ? ld_stream(v + kk * kEllSlice) : 0.0;
     }
     if constexpr (IL) {
       typedef double D2 __attribute__((ext_vector_type(2)));
@@ -1536,7 +1543,7 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int h = 0; h < LPC; ++h) a[u][h] = *(const V*)(tl + 16 * u * TS + 32 * h);
+          for (int h = 0; h < LPC; ++h) a[u][h] = ld_stream((const V*)(tl + 16 * u * TS + 32 * h));
         P cf[KV][4];                           // column parts of this tile, columns g + 16 u
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -1797,7 +1804,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     for (; b + 64 < nb; b += 128) {
 #pragma unroll
       for (int q = 0; q < RW; ++q) {
-        const double s0 = double(col[q][b]), s1 = double(col[q][b + 64]);
+        const double s0 = double(ld_stream(col[q] + b)), s1 = double(ld_stream(col[q] + b + 64));
 #pragma unroll
         for (int k = 0; k < KV; ++k) acc[q][k] += s0 * ub[k][b] + s1 * ub[k][b + 64];
       }
@@ -1805,7 +1812,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma_level(
     if (b < nb) {
 #pragma unroll
       for (int q = 0; q < RW; ++q) {
-        const double s0 = double(col[q][b]);
+        const double s0 = double(ld_stream(col[q] + b));
 #pragma unroll
         for (int k = 0; k < KV; ++k) acc[q][k] += s0 * ub[k][b];
       }
@@ -1865,14 +1872,14 @@ __global__ __launch_bounds__(kBlock) void k_sigma_rows(
     for (; j + 8 <= nb; j += 8) {
       S sv[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sv[q] = col[int64_t(j + q) * m];
+      for (int q = 0; q < 8; ++q) sv[q] = ld_stream(col + int64_t(j + q) * m);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
 #pragma unroll
         for (int k = 0; k < KV; ++k) acc[k] = fma(double(sv[q]), u[j + q][k], acc[k]);
     }
     for (; j < nb; ++j) {
-      const double sv = double(col[int64_t(j) * m]);
+      const double sv = double(ld_stream(col + int64_t(j) * m));
 #pragma unroll
       for (int k = 0; k < KV; ++k) acc[k] = fma(sv, u[j][k], acc[k]);
     }
