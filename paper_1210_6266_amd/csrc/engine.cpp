@@ -808,7 +808,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       const std::string key = inv_key(sb, bb, G);
       bool tuning = false;
       const int cand = inv_pick(h, key, ncand, &tuning);
-      bb.wide = cand >= 2 ? 1 : 0;
+      bb.upd_shape = cand / 2;
       if (slot < 8) h->setup_variant[slot] = cand + 1;
       hipEvent_t a = nullptr, b = nullptr;
       if (tuning) {

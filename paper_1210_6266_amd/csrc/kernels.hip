@@ -1116,16 +1116,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int
 }
 
 // (3'') the update of an FP32 batch on the BF16 matrix cores.  Same super-tiles, XCD
-// dealing, band order, look-ahead parts and FP32 operand ring (direct global-to-LDS loads,
-// padded k-rows) as k_sweep_update2<float>, with 32-deep k-chunks and a two-stage ring (two
-// workgroups per compute unit).  Each operand value x read from LDS is split exactly into
-// three BF16 parts (split_bf3; BF16 has FP32's exponent range, so no scaling is needed),
-// and each 16 x 16 x 32 block takes six MFMAs, hi hi + hi mid + mid hi + hi lo + mid mid +
-// lo hi, accumulated in FP32 from A_ij; the three dropped products (mid lo, lo mid, lo lo)
-// are below 2^-21 of |x y|.  Lane group lk of an MFMA operand holds
-// the k-values lk, lk + 4, ..., lk + 28 of the chunk (the same permutation of k for both
-// operands leaves the sum unchanged): the four groups then read consecutive padded
-// k-rows, which lie in distinct LDS banks.
+// dealing, band order and look-ahead parts as k_sweep_update2<float>, 32-deep k-chunks.
+// Each operand value x is split exactly into three BF16 parts (split_bf3; BF16 has FP32's
+// exponent range, so no scaling is needed), and each 16 x 16 x 32 block takes six MFMAs,
+// hi hi + hi mid + mid hi + hi lo + mid mid + lo hi, accumulated in FP32 from A_ij; the
+// three dropped products (mid lo, lo mid, lo lo) are below 2^-21 of |x y|.  Lane group lk
+// of an MFMA operand holds the k-values lk, lk + 4, ..., lk + 28 of the chunk (the same
+// permutation of k for both operands leaves the sum unchanged).
 using bf8 = __bf16 __attribute__((ext_vector_type(8)));
 using f4v = float __attribute__((ext_vector_type(4)));
 
@@ -1141,160 +1138,6 @@ __device__ __forceinline__ void split_bf3(const float (&x)[8], bf8& h, bf8& m, b
     m[e] = __builtin_bit_cast(__bf16, uint16_t(__float_as_uint(b) >> 16));
     l[e] = __builtin_bit_cast(__bf16, uint16_t(__float_as_uint(r - b) >> 16));
   }
-}
-
-template <int G>
-__global__ __launch_bounds__(kBlock, 2) void k_sweep_update_bf3(float* tiles, const int64_t* tile_off,
-                                                             const int32_t* nt_arr, int c0,
-                                                             const float* cbuf, const float* bbuf,
-                                                             int64_t stride, int64_t per_xcd,
-                                                             int part, int count) {
-  constexpr int PB = G * TS, KC = 32, LD = 144, NCH = PB / KC, NS = 2;
-  constexpr int GS = G / 2;
-  int m;
-  int64_t s = 0;
-  if (part != 1 && count >= 8) {
-    const int64_t q = blockIdx.x / 8;
-    m = int(8 * (q / per_xcd)) + int(blockIdx.x % 8);
-    s = q % per_xcd;
-    if (m >= count) return;
-  } else {
-    m = blockIdx.y;
-    s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  }
-  const int nt = nt_arr[m];
-  if (c0 >= nt) return;
-  const int nsb = (nt + 1) / 2;
-  const int gN = c0 / 2 + GS;
-  auto in_next = [&](int X) { return X >= gN && X < gN + GS; };
-  int BI, BJ;
-  if (part == 1) {
-    const int t = blockIdx.x / GS, sub = blockIdx.x % GS;
-    const int gx = gN + sub;
-    if (t >= nsb || gx >= nsb) return;
-    BI = t <= gx ? gx : t;
-    BJ = t <= gx ? t : gx;
-    if (t < gx && t >= gN) return;
-  } else {
-    if (s >= tri(nsb)) return;
-    band_ij(s, nsb, &BI, &BJ);
-    if (part == 2 && (in_next(BI) || in_next(BJ))) return;
-  }
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ti = 2 * BI + (w >> 1), tj = 2 * BJ + (w & 1);
-  const bool valid = ti < nt && tj <= ti;
-  const float* Bb = bbuf + int64_t(m) * stride;
-  const float* Cb = cbuf + int64_t(m) * stride;
-  float* base = tiles + tile_off[m];
-  const int gB = c0 / 2;
-  auto in_cur = [&](int X) { return X >= gB && X < gB + GS; };
-  if (in_cur(BI) || in_cur(BJ)) {
-    const bool ii = ti >= c0 && ti < c0 + G, jj = tj >= c0 && tj < c0 + G;
-    if (ii && jj) return;
-    if (!valid) return;
-    float* A = base + tile_index(ti, tj) * TT;
-    if (ii) {
-      const float* Bj = Bb + int64_t(tj) * TS * PB + int64_t(ti - c0) * TS * TS;
-      for (int e = lane; e < TT; e += 64) A[e] = Bj[(e / TS) + (e % TS) * TS];
-    } else {
-      const float* Bi = Bb + int64_t(ti) * TS * PB + int64_t(tj - c0) * TS * TS;
-      for (int e = lane; e < TT; e += 64) A[e] = Bi[e];
-    }
-    return;
-  }
-  // operand ring: one padded k-row (128 rows) per wave load instruction and tile half
-  constexpr int PERW = 2 * KC * 2 / 4;         // load instructions per wave and chunk
-  __shared__ __attribute__((aligned(16))) float ring[NS][2][KC * LD];
-  auto issue = [&](int ch) {
-    const int st = ch % NS;
-#pragma unroll
-    for (int u = 0; u < KC * 2 / 4; ++u) {
-      const int idx = w + 4 * u, kk = idx / 2, hf = idx % 2, k = ch * KC + kk;
-      const int r = 64 * hf + lane;
-      const int iA = 2 * BI + r / 64 < nt ? 2 * BI + r / 64 : 2 * BI;
-      const int iB = 2 * BJ + r / 64 < nt ? 2 * BJ + r / 64 : 2 * BJ;
-      const void* ga = Bb + int64_t(iA) * TS * PB + (r % 64) + int64_t(k) * TS;
-      const void* gb = Cb + int64_t(iB) * TS * PB + (r % 64) + int64_t(k) * TS;
-      auto la = (__attribute__((address_space(3))) void*)&ring[st][0][kk * LD + 64 * hf];
-      auto lb = (__attribute__((address_space(3))) void*)&ring[st][1][kk * LD + 64 * hf];
-      __builtin_amdgcn_global_load_lds(ga, la, 4, 0, 0);
-      __builtin_amdgcn_global_load_lds(gb, lb, 4, 0, 0);
-    }
-  };
-  const int li = lane & 15, lk = lane >> 4, g = lane >> 4;
-  float* At = base + tile_index(valid ? ti : 0, valid ? tj : 0) * TT;
-  f4v acc[4][4];
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        acc[bi][bj][v] = valid ? At[(16 * bi + li) + (16 * bj + 4 * g + v) * TS] : 0.0f;
-  const int oa = 64 * (w >> 1) + li, ob = 64 * (w & 1) + li;
-#pragma unroll
-  for (int c = 0; c < NS - 1; ++c)
-    if (c < NCH) issue(c);
-  for (int ch = 0; ch < NCH; ++ch) {
-    wait_ring<PERW, NS>(min(NS - 2, NCH - 1 - ch));
-    __syncthreads();
-    if (ch + NS - 1 < NCH) issue(ch + NS - 1);
-    const float* A_ = ring[ch % NS][0];
-    const float* B_ = ring[ch % NS][1];
-    // two halves of the tile's row blocks at a time (register budget): the B_i rows
-    // (negated: the MFMA's B operand) of the half, then the C_j row blocks (its A
-    // operand) two at a time; the six products of four blocks are interleaved so that
-    // consecutive MFMAs never accumulate into the same block
-#pragma unroll
-    for (int hb = 0; hb < 2; ++hb) {
-      bf8 bh[2], bm[2], bl[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        float x[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = -A_[(lk + 4 * e) * LD + oa + 16 * (2 * hb + q)];
-        split_bf3(x, bh[q], bm[q], bl[q]);
-      }
-#pragma unroll
-      for (int bp = 0; bp < 2; ++bp) {
-        bf8 ch[2], cm[2], cl[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          float x[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = B_[(lk + 4 * e) * LD + ob + 16 * (2 * bp + j)];
-          split_bf3(x, ch[j], cm[j], cl[j]);
-        }
-        f4v c[2][2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) c[q][j] = acc[2 * hb + q][2 * bp + j];
-#define RSD_BF3_TERM(CA, BB)                                                                    \
-  _Pragma("unroll") for (int q = 0; q < 2; ++q)                                                 \
-  _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                 \
-      c[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CA[j], BB[q], c[q][j], 0, 0, 0);
-        RSD_BF3_TERM(cl, bh)
-        RSD_BF3_TERM(cm, bm)
-        RSD_BF3_TERM(ch, bl)
-        RSD_BF3_TERM(cm, bh)
-        RSD_BF3_TERM(ch, bm)
-        RSD_BF3_TERM(ch, bh)
-#undef RSD_BF3_TERM
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[2 * hb + q][2 * bp + j] = c[q][j];
-      }
-    }
-  }
-  if (!valid) return;
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) At[(16 * bi + li) + (16 * bj + 4 * g + v) * TS] = acc[bi][bj][v];
 }
 
 // (3w) the BF16-split update of an FP32 batch for four-tile pivot groups by 256 x 256
@@ -1446,6 +1289,156 @@ __global__ __launch_bounds__(512, 1) void k_sweep_update_bf3w(float* tiles, cons
         for (int v = 0; v < 4; ++v)
           At[h][(16 * bi + li) + (16 * bj + 4 * g + v) * TS] = acc[h][bi][bj][v];
   }
+}
+
+// (3s) the BF16-split update by 128 x 128 super-tiles, each operand value split once per
+// workgroup (its four waves read every panel row twice; splitting where the values are
+// read cost three times the vector instructions and ran 25% slower).  Per 32-deep chunk
+// each thread loads eight k-values of one panel row (value e of k-group q is k = q + 4 e)
+// into registers, one chunk ahead;
+// after the previous chunk's products the workgroup splits them and writes the three
+// BF16 parts straight into the MFMA operand layout in LDS ([panel][part][row block]
+// [k-group][row] of 16-byte fragments), so each MFMA operand is one conflict-free 16-byte
+// LDS read.  48 KB of LDS, one stage.
+template <int G>
+__global__ __launch_bounds__(kBlock, 2) void k_sweep_update_bf3s(float* tiles, const int64_t* tile_off,
+                                                              const int32_t* nt_arr, int c0,
+                                                              const float* cbuf, const float* bbuf,
+                                                              int64_t stride, int64_t per_xcd,
+                                                              int part, int count) {
+  constexpr int PB = G * TS, KC = 32, NCH = PB / KC;
+  constexpr int GS = G / 2;
+  int m;
+  int64_t s = 0;
+  if (part != 1 && count >= 8) {
+    const int64_t q = blockIdx.x / 8;
+    m = int(8 * (q / per_xcd)) + int(blockIdx.x % 8);
+    s = q % per_xcd;
+    if (m >= count) return;
+  } else {
+    m = blockIdx.y;
+    s = int64_t(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  }
+  const int nt = nt_arr[m];
+  if (c0 >= nt) return;
+  const int nsb = (nt + 1) / 2;
+  const int gN = c0 / 2 + GS;
+  auto in_next = [&](int X) { return X >= gN && X < gN + GS; };
+  int BI, BJ;
+  if (part == 1) {
+    const int t = blockIdx.x / GS, sub = blockIdx.x % GS;
+    const int gx = gN + sub;
+    if (t >= nsb || gx >= nsb) return;
+    BI = t <= gx ? gx : t;
+    BJ = t <= gx ? t : gx;
+    if (t < gx && t >= gN) return;
+  } else {
+    if (s >= tri(nsb)) return;
+    band_ij(s, nsb, &BI, &BJ);
+    if (part == 2 && (in_next(BI) || in_next(BJ))) return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = 2 * BI + (w >> 1), tj = 2 * BJ + (w & 1);
+  const bool valid = ti < nt && tj <= ti;
+  const float* Bb = bbuf + int64_t(m) * stride;
+  const float* Cb = cbuf + int64_t(m) * stride;
+  float* base = tiles + tile_off[m];
+  const int gB = c0 / 2;
+  auto in_cur = [&](int X) { return X >= gB && X < gB + GS; };
+  if (in_cur(BI) || in_cur(BJ)) {
+    const bool ii = ti >= c0 && ti < c0 + G, jj = tj >= c0 && tj < c0 + G;
+    if (ii && jj) return;
+    if (!valid) return;
+    float* A = base + tile_index(ti, tj) * TT;
+    if (ii) {
+      const float* Bj = Bb + int64_t(tj) * TS * PB + int64_t(ti - c0) * TS * TS;
+      for (int e = lane; e < TT; e += 64) A[e] = Bj[(e / TS) + (e % TS) * TS];
+    } else {
+      const float* Bi = Bb + int64_t(ti) * TS * PB + int64_t(tj - c0) * TS * TS;
+      for (int e = lane; e < TT; e += 64) A[e] = Bi[e];
+    }
+    return;
+  }
+  // this thread's panel row r (the same for both panels) and k-groups kq, kq + 2; a tile
+  // row past the matrix reads the super-row's first tile (finite data reaching only tiles
+  // never stored)
+  const int r = threadIdx.x & 127, kq = threadIdx.x >> 7;
+  const int iA = 2 * BI + r / 64 < nt ? 2 * BI + r / 64 : 2 * BI;
+  const int iB = 2 * BJ + r / 64 < nt ? 2 * BJ + r / 64 : 2 * BJ;
+  const float* gp[2] = {Bb + int64_t(iA) * TS * PB + (r % 64),
+                        Cb + int64_t(iB) * TS * PB + (r % 64)};
+  float pre[4][8];                             // [panel * 2 + k-group half][e]
+  auto load = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        pre[u][e] = gp[u >> 1][int64_t(ch * KC + kq + 2 * (u & 1) + 4 * e) * TS];
+  };
+  // operand fragments: [panel][part][row block][k-group][row in block]
+  __shared__ bf8 frag[2 * 3 * 8 * 4 * 16];
+  auto fidx = [](int pp, int pt, int rb, int q, int ri) {
+    return (((pp * 3 + pt) * 8 + rb) * 4 + q) * 16 + ri;
+  };
+  const int li = lane & 15, lk = lane >> 4, g = lane >> 4;
+  float* At = base + tile_index(valid ? ti : 0, valid ? tj : 0) * TT;
+  f4v acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[bi][bj][v] = valid ? At[(16 * bi + li) + (16 * bj + 4 * g + v) * TS] : 0.0f;
+  const int ra = 4 * (w >> 1), rbb = 4 * (w & 1);   // the wave's first row block per panel
+  load(0);
+  for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (u >> 1) == 0 ? -pre[u][e] : pre[u][e];
+      bf8 h, md, lo;
+      split_bf3(x, h, md, lo);
+      const int pp = u >> 1, q = kq + 2 * (u & 1);
+      frag[fidx(pp, 0, r >> 4, q, r & 15)] = h;
+      frag[fidx(pp, 1, r >> 4, q, r & 15)] = md;
+      frag[fidx(pp, 2, r >> 4, q, r & 15)] = lo;
+    }
+    __syncthreads();
+    if (ch + 1 < NCH) load(ch + 1);
+    bf8 bh[4], bm[4], bl[4];                   // the wave's B_i row blocks (negated)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bh[q] = frag[fidx(0, 0, ra + q, lk, li)];
+      bm[q] = frag[fidx(0, 1, ra + q, lk, li)];
+      bl[q] = frag[fidx(0, 2, ra + q, lk, li)];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {              // C row block j
+      const bf8 chh = frag[fidx(1, 0, rbb + j, lk, li)];
+      const bf8 cmm = frag[fidx(1, 1, rbb + j, lk, li)];
+      const bf8 cll = frag[fidx(1, 2, rbb + j, lk, li)];
+#define RSD_BF3S_TERM(CA, BB)                                                                   \
+  _Pragma("unroll") for (int q = 0; q < 4; ++q)                                                 \
+      acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CA, BB[q], acc[q][j], 0, 0, 0);
+      RSD_BF3S_TERM(cll, bh)
+      RSD_BF3S_TERM(cmm, bm)
+      RSD_BF3S_TERM(chh, bl)
+      RSD_BF3S_TERM(cmm, bh)
+      RSD_BF3S_TERM(chh, bm)
+      RSD_BF3S_TERM(chh, bh)
+#undef RSD_BF3S_TERM
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) At[(16 * bi + li) + (16 * bj + 4 * g + v) * TS] = acc[bi][bj][v];
 }
 
 // ---- symmetric products y = base + alpha A x -------------------------------------------
@@ -2607,7 +2600,7 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
     const dim3 grid = part == 1 ? dim3(unsigned(nsb * (group / 2)), b.count)
                       : major   ? dim3(unsigned(8 * ((b.count + 7) / 8) * ns), 1)
                                 : dim3(unsigned(8 * per_xcd), b.count);
-    if (group == 4 && b.wide) {
+    if (group == 4 && b.upd_shape == 1) {
       const int64_t nsw = (b.max_nt + 3) / 4, nw = nsw * (nsw + 1) / 2;
       const int64_t pxw = major ? nw : (nw + 7) / 8;
       const dim3 gw = part == 1 ? dim3(unsigned(nsw), b.count)
@@ -2617,13 +2610,13 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
                                                 (const float*)cbuf, (const float*)bbuf, stride, pxw,
                                                 part, b.count);
     } else if (group == 4)
-      k_sweep_update_bf3<4><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.nt, c0,
-                                                    (const float*)cbuf, (const float*)bbuf, stride,
-                                                    per_xcd, part, b.count);
+      k_sweep_update_bf3s<4><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.nt, c0,
+                                                     (const float*)cbuf, (const float*)bbuf, stride,
+                                                     per_xcd, part, b.count);
     else
-      k_sweep_update_bf3<2><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.nt, c0,
-                                                    (const float*)cbuf, (const float*)bbuf, stride,
-                                                    per_xcd, part, b.count);
+      k_sweep_update_bf3s<2><<<grid, kBlock, 0, s>>>((float*)b.tiles, b.tile_off, b.nt, c0,
+                                                     (const float*)cbuf, (const float*)bbuf, stride,
+                                                     per_xcd, part, b.count);
     return hipGetLastError();
   }
 #define RSD_STEP(T, G)                                                                          \

@@ -33,9 +33,10 @@ struct DevBatch {
   int32_t half = 0;       // apply-side 16-bit copy of FP32 tiles: 1 FP16, 2 BF16 (0: none)
   int32_t vec_pass = 0;   // vectors per pass of the symmetric product (0: symv_vectors)
   int32_t split16 = 0;    // FP32 batches: sweep updates on the BF16 matrix cores, operands
-                          // split exactly into three BF16 parts (k_sweep_update_bf3)
-  int32_t wide = 0;       // with split16 and four-tile groups: 256 x 256 super-tiles
-                          // (k_sweep_update_bf3w; bitwise the 128 x 128 results)
+                          // split exactly into three BF16 parts (k_sweep_update_bf3s)
+  int32_t upd_shape = 0;  // split16 update form, bitwise alike: 0 128 x 128 super-tiles
+                          // (k_sweep_update_bf3s), 1 256 x 256 super-tiles in four-tile
+                          // groups (k_sweep_update_bf3w)
 };
 
 // ---- sparse / vector ------------------------------------------------------------------
