@@ -232,8 +232,9 @@ struct Uploader {
   std::vector<Item> items;
   size_t total = 0;
   Pinned stage;
-  template <typename T, typename P>
-  void add(P** dst, const std::vector<T>& v) {
+  template <typename V, typename P>
+  void add(P** dst, const V& v) {
+    using T = typename V::value_type;
     const size_t off = (total + 255) & ~size_t(255);
     total = off + std::max<size_t>(1, v.size()) * sizeof(T);
     items.push_back({reinterpret_cast<void**>(const_cast<typename std::remove_const<P>::type**>(dst)),

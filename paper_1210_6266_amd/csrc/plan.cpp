@@ -1,10 +1,14 @@
 // Host analysis of the hierarchical decomposition: see plan.hpp.
 #include "plan.hpp"
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdio>
 #include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <utility>
@@ -26,49 +30,89 @@ int num_threads() {
   return int(std::max(1u, std::min(16u, hc)));
 }
 
+// Process-wide worker threads for the analysis' parallel loops, started on first use (a
+// forked child starts its own).  run(nw, fn) calls fn(w) for w in [0, nw), w = 0 on the
+// calling thread, and returns when every call has returned; concurrent callers take
+// turns.  Starting threads per loop cost about 1 ms per set-up at 16 threads.
+class Pool {
+ public:
+  static Pool& get() {
+    static std::mutex mu;
+    static Pool* pool = nullptr;               // never destroyed: its threads are detached
+    std::lock_guard<std::mutex> lk(mu);
+    if (pool == nullptr || pool->pid_ != getpid()) pool = new Pool(num_threads() - 1);
+    return *pool;
+  }
+  int size() const { return int(nworkers_) + 1; }
+  void run(int nw, const std::function<void(int)>& fn) {
+    std::lock_guard<std::mutex> turn(run_mu_);
+    nw = std::min(nw, size());
+    if (nw <= 1) {
+      fn(0);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      nw_ = nw;
+      pending_ = nw - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    fn(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return pending_ == 0; });
+  }
+
+ private:
+  explicit Pool(int nworkers) : pid_(getpid()), nworkers_(std::max(0, nworkers)) {
+    for (int w = 1; w <= nworkers_; ++w) std::thread([this, w] { loop(w); }).detach();
+  }
+  void loop(int w) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* fn;
+      int nw;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        fn = fn_;
+        nw = nw_;
+      }
+      if (w >= nw) continue;                   // not needed for this loop
+      (*fn)(w);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  const pid_t pid_;
+  const int nworkers_;
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int nw_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+};
+
 // Runs fn(lo, hi, worker) over [0, count) split into contiguous chunks, one per worker.
 void parallel_for(int64_t count, const std::function<void(int64_t, int64_t, int)>& fn) {
-  const int nt = int(std::min<int64_t>(num_threads(), std::max<int64_t>(1, count / 4096 + 1)));
-  if (nt <= 1) {
-    fn(0, count, 0);
-    return;
-  }
-  std::vector<std::thread> th;
+  Pool& pool = Pool::get();
+  const int nt = int(std::min<int64_t>(pool.size(), std::max<int64_t>(1, count / 4096 + 1)));
   const int64_t chunk = (count + nt - 1) / nt;
-  for (int w = 0; w < nt; ++w) {
+  pool.run(nt, [&](int w) {
     const int64_t lo = std::min(count, int64_t(w) * chunk), hi = std::min(count, lo + chunk);
-    th.emplace_back(fn, lo, hi, w);
-  }
-  for (auto& t : th) t.join();
+    fn(lo, hi, w);
+  });
 }
 
-typedef std::vector<std::pair<int64_t, std::pair<PlanError, std::string>>> ErrList;
-
-// Runs a row check in parallel; the error of the lowest failing row is reported, so
-// the message does not depend on the thread schedule.
-PlanError check_rows(int64_t n, const std::function<bool(int64_t, PlanError*, std::string*)>& bad,
-                     std::string* msg) {
-  std::vector<ErrList> per(16);
-  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
-    for (int64_t i = lo; i < hi; ++i) {
-      PlanError e;
-      std::string m;
-      if (bad(i, &e, &m)) {
-        per[w].push_back({i, {e, m}});
-        return;
-      }
-    }
+// Runs fn(item, worker) for every item in [0, count), items taken in turn by the workers.
+void parallel_items(int64_t count, const std::function<void(int64_t, int)>& fn) {
+  Pool& pool = Pool::get();
+  std::atomic<int64_t> next{0};
+  pool.run(int(std::min<int64_t>(pool.size(), std::max<int64_t>(1, count))), [&](int w) {
+    for (int64_t i = next++; i < count; i = next++) fn(i, w);
   });
-  int64_t best = INT64_MAX;
-  PlanError code = PlanError::kOk;
-  for (auto& p : per)
-    for (auto& f : p)
-      if (f.first < best) {
-        best = f.first;
-        code = f.second.first;
-        *msg = f.second.second;
-      }
-  return code;
 }
 
 }  // namespace
@@ -123,98 +167,33 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       *msg = fmt("row_ptr decreases at row %lld", i);
       return PlanError::kInvalid;
     }
-  PlanError e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-      const int32_t c = col_idx[k];
-      if (c < 0 || c >= n) {
-        *code = PlanError::kInvalid;
-        *m = fmt("column index %lld out of range in row %lld", c, i);
-        return true;
-      }
-      if (k > row_ptr[i] && c <= col_idx[k - 1]) {
-        *code = PlanError::kInvalid;
-        *m = fmt("columns of row %lld not strictly increasing", i);
-        return true;
-      }
-    }
-    return false;
-  }, msg);
-  if (e != PlanError::kOk) return e;
-  // structural symmetry: (i, j) present => (j, i) present.  Each entry above the
-  // diagonal is looked up in the transposed row; with as many entries below the
-  // diagonal as above, that map is a bijection and the lower ones are covered too.
-  e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
-    for (int64_t k = row_ptr[i + 1] - 1; k >= row_ptr[i] && col_idx[k] > i; --k) {
-      const int32_t j = col_idx[k];
-      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
-        *code = PlanError::kInvalid;
-        *m = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing", i, j);
-        return true;
-      }
-    }
-    return false;
-  }, msg);
-  if (e != PlanError::kOk) return e;
-  {
-    std::vector<int64_t> upper(16, 0), lower(16, 0);
-    parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
-      int64_t up = 0, dn = 0;                  // per-thread counts (no shared cache lines)
-      for (int64_t i = lo; i < hi; ++i) {
-        const int32_t* b = col_idx + row_ptr[i];
-        const int32_t* en = col_idx + row_ptr[i + 1];
-        const int32_t* d = std::lower_bound(b, en, int32_t(i));   // first column >= i
-        dn += d - b;
-        up += en - d - (d < en && *d == i ? 1 : 0);
-      }
-      upper[w] = up;
-      lower[w] = dn;
-    });
-    if (std::accumulate(upper.begin(), upper.end(), int64_t(0)) !=
-        std::accumulate(lower.begin(), lower.end(), int64_t(0))) {
-      // some entry below the diagonal has no transpose: report the first one
-      for (int32_t i = 0; i < n; ++i)
-        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] && col_idx[k] < i; ++k) {
-          const int32_t j = col_idx[k];
-          if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
-            *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
-                       i, j);
-            return PlanError::kInvalid;
-          }
-        }
-      *msg = "K is not structurally symmetric";
-      return PlanError::kInvalid;
-    }
-  }
-  // ---- validation of the tree ----------------------------------------------------------
+  // ---- validation of the tree (reported after the CSR's errors) ---------------------
+  std::string tree_msg;
   if (T <= 0 || parent == nullptr || dof_node == nullptr) {
-    *msg = "hierarchy needs num_nodes >= 1, parent and dof_node";
-    return PlanError::kInvalid;
+    tree_msg = "hierarchy needs num_nodes >= 1, parent and dof_node";
+  } else if (parent[0] != -1) {
+    tree_msg = "parent[0] must be -1";
+  } else {
+    for (int32_t t = 1; t < T && tree_msg.empty(); ++t)
+      if (parent[t] < 0 || parent[t] >= t)
+        tree_msg = fmt("parent[%lld] = %lld must lie in [0, %lld)", t, parent[t], t);
+    for (int32_t i = 0; i < n && tree_msg.empty(); ++i)
+      if (dof_node[i] < 0 || dof_node[i] >= T)
+        tree_msg = fmt("dof_node[%lld] = %lld out of range", i, dof_node[i]);
   }
-  if (parent[0] != -1) { *msg = "parent[0] must be -1"; return PlanError::kInvalid; }
-  for (int32_t t = 1; t < T; ++t)
-    if (parent[t] < 0 || parent[t] >= t) {
-      *msg = fmt("parent[%lld] = %lld must lie in [0, %lld)", t, parent[t], t);
-      return PlanError::kInvalid;
-    }
-  for (int32_t i = 0; i < n; ++i)
-    if (dof_node[i] < 0 || dof_node[i] >= T) {
-      *msg = fmt("dof_node[%lld] = %lld out of range", i, dof_node[i]);
-      return PlanError::kInvalid;
-    }
-
-  P->n = n;
-  P->nnz = nnz;
-  P->T = T;
-  P->parent.assign(parent, parent + T);
-  P->depth.assign(T, 0);
-  P->children.assign(T, {});
-  for (int32_t t = 1; t < T; ++t) {
-    P->depth[t] = P->depth[parent[t]] + 1;
-    P->children[parent[t]].push_back(t);
-  }
+  const bool tree_ok = tree_msg.empty();
   // Euler tour for ancestor tests (parent[t] < t: ids are topologically ordered)
-  std::vector<int32_t> tin(T), tout(T);
-  {
+  std::vector<int32_t> tin, tout;
+  if (tree_ok) {
+    P->parent.assign(parent, parent + T);
+    P->depth.assign(T, 0);
+    P->children.assign(T, {});
+    for (int32_t t = 1; t < T; ++t) {
+      P->depth[t] = P->depth[parent[t]] + 1;
+      P->children[parent[t]].push_back(t);
+    }
+    tin.assign(T, 0);
+    tout.assign(T, 0);
     int32_t clock = 0;
     std::vector<std::pair<int32_t, size_t>> st;
     st.push_back({0, 0});
@@ -234,21 +213,161 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   auto anc = [&](int32_t a, int32_t b) {  // a is an ancestor of b, or a == b
     return tin[a] <= tin[b] && tout[b] <= tout[a];
   };
-  // separability: every coupling joins nodes on one root-to-leaf path
-  e = check_rows(n, [&](int64_t i, PlanError* code, std::string* m) {
-    const int32_t a = dof_node[i];
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-      const int32_t b = dof_node[col_idx[k]];
-      if (!anc(a, b) && !anc(b, a)) {
-        *code = PlanError::kNotSeparable;
-        *m = fmt("K couples dof %lld and dof %lld whose tree nodes are not on one root-to-leaf "
-                 "path (node %lld)", i, col_idx[k], a);
+  // ---- one parallel pass over the rows --------------------------------------------------
+  // Per row: columns in range and strictly increasing; each entry above the diagonal
+  // matched with its transpose (structural symmetry: with as many entries below the
+  // diagonal as above, that map is a bijection and the lower ones are covered too); the
+  // counts of both; separability (every coupling joins nodes on one root-to-leaf path).
+  // A worker's rows come in increasing order, so the transposes it looks for in a row j
+  // come in increasing column order: one cursor per row j (within the worker's window of
+  // rows) replaces a search.  If a cursor finds anything else, the exact search runs over
+  // all rows afterwards to name the first missing transpose.  Each check reports its lowest
+  // failing row, so messages do not depend on the thread schedule; the checks are
+  // reported in that order, the tree's errors before separability.
+  struct RowErr {
+    int64_t row = INT64_MAX;
+    std::string msg;
+  };
+  struct Worker {
+    RowErr col, sym, sep;
+    int64_t up = 0, dn = 0;
+    bool asym = false;                         // a cursor met something other than a transpose
+  };
+  auto sym_error = [&](int64_t i, RowErr* e) {   // the first missing transpose of row i
+    for (int64_t k = row_ptr[i + 1] - 1; k >= row_ptr[i] && col_idx[k] > i; --k) {
+      const int32_t j = col_idx[k];
+      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
+        *e = {i, fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
+                     i, j)};
         return true;
       }
     }
     return false;
-  }, msg);
-  if (e != PlanError::kOk) return e;
+  };
+  std::vector<Worker> wk(size_t(Pool::get().size()));
+  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+    Worker& o = wk[size_t(w)];
+    // window of rows whose transposes this worker looks for: [lo, jmax]
+    int64_t jmax = lo;
+    bool cursors = true;
+    for (int64_t i = lo; i < hi && cursors; ++i)
+      if (row_ptr[i + 1] > row_ptr[i]) {
+        const int32_t c = col_idx[row_ptr[i + 1] - 1];
+        if (c < 0 || c >= n) cursors = false;  // reported by the row checks below
+        jmax = std::max<int64_t>(jmax, c);
+      }
+    cursors = cursors && jmax - lo < std::max<int64_t>(4 * (hi - lo), int64_t(1) << 20);
+    std::vector<int32_t> cur;                  // per row of the window: next position, or -1
+    if (cursors) cur.assign(size_t(jmax - lo + 1), -1);
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t b = row_ptr[i], en = row_ptr[i + 1];
+      for (int64_t k = b; k < en; ++k) {
+        const int32_t c = col_idx[k];
+        if (c < 0 || c >= n) {
+          o.col = {i, fmt("column index %lld out of range in row %lld", c, i)};
+          return;
+        }
+        if (k > b && c <= col_idx[k - 1]) {
+          o.col = {i, fmt("columns of row %lld not strictly increasing", i)};
+          return;
+        }
+      }
+      const int32_t* cb = col_idx + b;
+      const int32_t* ce = col_idx + en;
+      const int32_t* d = std::lower_bound(cb, ce, int32_t(i));   // first column >= i
+      o.dn += d - cb;
+      const int32_t* u = d < ce && *d == i ? d + 1 : d;          // first column > i
+      o.up += ce - u;
+      if (cursors) {
+        if (!o.asym)
+          for (const int32_t* q = u; q < ce; ++q) {
+            const int32_t j = *q;
+            const int64_t rj = row_ptr[j];
+            int32_t& cj = cur[size_t(j - lo)];
+            if (cj < 0)
+              cj = int32_t(std::lower_bound(col_idx + rj, col_idx + row_ptr[j + 1], int32_t(lo)) -
+                           (col_idx + rj));
+            if (rj + cj < row_ptr[j + 1] && col_idx[rj + cj] == i) {
+              ++cj;
+            } else {
+              o.asym = true;
+              break;
+            }
+          }
+      } else if (o.sym.row == INT64_MAX) {
+        sym_error(i, &o.sym);
+      }
+      if (tree_ok && o.sep.row == INT64_MAX) {
+        const int32_t a = dof_node[i];
+        int32_t ok = a;                        // last node seen on a's path
+        for (int64_t k = b; k < en; ++k) {
+          const int32_t bn = dof_node[col_idx[k]];
+          if (bn == ok) continue;
+          if (!anc(a, bn) && !anc(bn, a)) {
+            o.sep = {i, fmt("K couples dof %lld and dof %lld whose tree nodes are not on one "
+                            "root-to-leaf path (node %lld)", i, col_idx[k], a)};
+            break;
+          }
+          ok = bn;
+        }
+      }
+    }
+  });
+  auto lowest = [&](RowErr Worker::*f) {
+    const RowErr* best = nullptr;
+    for (const Worker& o : wk)
+      if ((o.*f).row != INT64_MAX && (best == nullptr || (o.*f).row < best->row)) best = &(o.*f);
+    return best;
+  };
+  if (const RowErr* r = lowest(&Worker::col)) {
+    *msg = r->msg;
+    return PlanError::kInvalid;
+  }
+  bool asym = false;
+  for (const Worker& o : wk) asym = asym || o.asym;
+  if (asym) {                                  // name the first missing transpose, if any
+    for (Worker& o : wk) o.sym = RowErr();
+    parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+      for (int64_t i = lo; i < hi; ++i)
+        if (sym_error(i, &wk[size_t(w)].sym)) return;
+    });
+  }
+  if (const RowErr* r = lowest(&Worker::sym)) {
+    *msg = r->msg;
+    return PlanError::kInvalid;
+  }
+  {
+    int64_t up = 0, dn = 0;
+    for (const Worker& o : wk) {
+      up += o.up;
+      dn += o.dn;
+    }
+    if (up != dn) {
+      // some entry below the diagonal has no transpose: report the first one
+      for (int32_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] && col_idx[k] < i; ++k) {
+          const int32_t j = col_idx[k];
+          if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
+            *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
+                       i, j);
+            return PlanError::kInvalid;
+          }
+        }
+      *msg = "K is not structurally symmetric";
+      return PlanError::kInvalid;
+    }
+  }
+  if (!tree_ok) {
+    *msg = tree_msg;
+    return PlanError::kInvalid;
+  }
+  if (const RowErr* r = lowest(&Worker::sep)) {
+    *msg = r->msg;
+    return PlanError::kNotSeparable;
+  }
+  P->n = n;
+  P->nnz = nnz;
+  P->T = T;
 
   // ---- orderings ---------------------------------------------------------------------
   std::vector<int64_t> own_ptr(size_t(T) + 1, 0);
@@ -318,7 +437,8 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     for (int64_t d = P->iface_off[s]; d < P->iface_off[s] + P->iface_n[s]; ++d)
       P->skel_own_end[d - P->n_leaf] = int32_t(P->iface_off[s] + P->iface_n[s]);
   // row pointers of K in internal order
-  P->prow.assign(size_t(n) + 1, 0);
+  P->prow.resize(size_t(n) + 1);
+  P->prow[0] = 0;
   for (int32_t r = 0; r < n; ++r) {
     const int32_t o = P->perm[r];
     P->prow[r + 1] = P->prow[r] + (row_ptr[o + 1] - row_ptr[o]);
@@ -335,146 +455,118 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   }
 
   // ---- per leaf: B_l, shell_l, K_{l,B_l} by columns, K_{B_l,l} by rows ----------------
-  // (read from the caller's CSR; value positions are the caller's)
-  struct LeafOut {
-    std::vector<int32_t> B, shell, kcol_row, krow_col;
-    std::vector<int64_t> kcol_ptr, kcol_val, krow_ptr, krow_val;
-  };
-  std::vector<LeafOut> lo_out(L);
-  {
-    std::atomic<int32_t> next{0};
-    std::vector<std::thread> th;
-    const int nw = std::min<int>(num_threads(), std::max(1, L));
-    for (int w = 0; w < nw; ++w)
-      th.emplace_back([&]() {
-        std::vector<int32_t> posB(size_t(std::max<int64_t>(1, nB)), -1);
-        std::vector<int32_t> shell_idx;
-        for (;;) {
-          const int32_t l = next++;
-          if (l >= L) break;
-          LeafOut& o = lo_out[l];
-          const int64_t off = P->leaf_off[l], nl = P->leaf_n[l];
-          shell_idx.assign(size_t(nl), -1);
-          // B_l and the shell (posB tags the interface dofs already seen in this leaf)
-          for (int64_t r = 0; r < nl; ++r) {
-            const int32_t orow = P->perm[off + r];
-            bool coupled = false;
-            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
-              const int32_t c = P->iperm[col_idx[k]];
-              if (c < P->n_leaf) continue;
-              coupled = true;
-              if (posB[c - P->n_leaf] != -2) {
-                posB[c - P->n_leaf] = -2;
-                o.B.push_back(c);
-              }
-            }
-            if (coupled) {
-              shell_idx[r] = int32_t(o.shell.size());
-              o.shell.push_back(int32_t(r));
-            }
-          }
-          std::sort(o.B.begin(), o.B.end());
-          const int64_t m = int64_t(o.B.size());
-          for (int64_t a = 0; a < m; ++a) posB[o.B[a] - P->n_leaf] = int32_t(a);
-          // columns of K_{l,B}
-          o.kcol_ptr.assign(size_t(m) + 1, 0);
-          for (int64_t r = 0; r < nl; ++r) {
-            const int32_t orow = P->perm[off + r];
-            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
-              const int32_t c = P->iperm[col_idx[k]];
-              if (c >= P->n_leaf) o.kcol_ptr[posB[c - P->n_leaf] + 1]++;
-            }
-          }
-          for (int64_t a = 0; a < m; ++a) o.kcol_ptr[a + 1] += o.kcol_ptr[a];
-          o.kcol_row.assign(size_t(o.kcol_ptr[m]), 0);
-          o.kcol_val.assign(size_t(o.kcol_ptr[m]), 0);
-          {
-            std::vector<int64_t> fill(o.kcol_ptr.begin(), o.kcol_ptr.end() - 1);
-            for (int64_t r = 0; r < nl; ++r) {
-              const int32_t orow = P->perm[off + r];
-              for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
-                const int32_t c = P->iperm[col_idx[k]];
-                if (c < P->n_leaf) continue;
-                const int64_t f = fill[posB[c - P->n_leaf]]++;
-                o.kcol_row[f] = int32_t(r);
-                o.kcol_val[f] = k;
-              }
-            }
-          }
-          // rows of K_{B,l}
-          o.krow_ptr.assign(size_t(m) + 1, 0);
-          for (int64_t a = 0; a < m; ++a) {
-            const int32_t orow = P->perm[o.B[a]];
-            for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
-              const int32_t c = P->iperm[col_idx[k]];
-              if (c < off || c >= off + nl) continue;
-              o.krow_col.push_back(shell_idx[c - off]);
-              o.krow_val.push_back(k);
-            }
-            o.krow_ptr[a + 1] = int64_t(o.krow_col.size());
-          }
-          for (int64_t a = 0; a < m; ++a) posB[o.B[a] - P->n_leaf] = -1;
-        }
-      });
-    for (auto& t : th) t.join();
-  }
-  for (int32_t l = 0; l < L; ++l)
-    for (int32_t v : lo_out[l].krow_col)
-      if (v < 0) {
-        *msg = "internal error: interface row couples to a non-shell interior dof";
-        return PlanError::kInvalid;
+  // (read from the caller's CSR; value positions are the caller's).  Pass 1 finds B_l and
+  // the shell and counts the couplings; pass 2 writes both coupling blocks straight into
+  // their final place.  K_{B_l,l} has as many entries as K_{l,B_l} (structural symmetry).
+  std::vector<std::vector<int32_t>> Bl(L), shl(L), cntl(L);
+  std::vector<int64_t> ncpl(size_t(L), 0);
+  const int nwk = Pool::get().size();
+  std::vector<std::vector<int32_t>> posB_w(static_cast<size_t>(nwk));
+  parallel_items(L, [&](int64_t l, int w) {
+    std::vector<int32_t>& cntB = posB_w[size_t(w)];   // couplings per interface dof, this leaf
+    if (cntB.empty()) cntB.assign(size_t(std::max<int64_t>(1, nB)), 0);
+    std::vector<int32_t>& B = Bl[size_t(l)];
+    std::vector<int32_t>& sh = shl[size_t(l)];
+    const int64_t off = P->leaf_off[l], nl = P->leaf_n[l];
+    int64_t cnt = 0;
+    for (int64_t r = 0; r < nl; ++r) {
+      const int32_t orow = P->perm[off + r];
+      const int64_t c0 = cnt;
+      for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+        const int32_t c = P->iperm[col_idx[k]];
+        if (c < P->n_leaf) continue;
+        ++cnt;
+        if (cntB[c - P->n_leaf]++ == 0) B.push_back(c);
       }
-  // concatenate the per-leaf pieces
+      if (cnt > c0) sh.push_back(int32_t(r));
+    }
+    std::sort(B.begin(), B.end());
+    std::vector<int32_t>& cn = cntl[size_t(l)];
+    cn.resize(B.size());
+    for (size_t a = 0; a < B.size(); ++a) {
+      cn[a] = cntB[B[a] - P->n_leaf];
+      cntB[B[a] - P->n_leaf] = 0;
+    }
+    ncpl[size_t(l)] = cnt;
+  });
   P->B_off.assign(L + 1, 0);
   P->shell_off.assign(L + 1, 0);
-  int64_t nkc = 0, nkr = 0;
+  std::vector<int64_t> kc_off(size_t(L) + 1, 0);
   for (int32_t l = 0; l < L; ++l) {
-    P->B_off[l + 1] = P->B_off[l] + int64_t(lo_out[l].B.size());
-    P->shell_off[l + 1] = P->shell_off[l] + int64_t(lo_out[l].shell.size());
-    nkc += int64_t(lo_out[l].kcol_row.size());
-    nkr += int64_t(lo_out[l].krow_col.size());
+    P->B_off[l + 1] = P->B_off[l] + int64_t(Bl[l].size());
+    P->shell_off[l + 1] = P->shell_off[l] + int64_t(shl[l].size());
+    kc_off[l + 1] = kc_off[l] + ncpl[l];
   }
-  const int64_t nBflat = P->B_off[L];
+  const int64_t nBflat = P->B_off[L], nkc = kc_off[L];
+  P->B.resize(size_t(nBflat));
+  P->shell.resize(size_t(P->shell_off[L]));
   P->kcol_ptr.assign(nBflat + 1, 0);
   P->krow_ptr.assign(nBflat + 1, 0);
-  {
-    // per-leaf offsets first, then every leaf's pieces copied in parallel
-    std::vector<int64_t> kc_off(size_t(L) + 1, 0), kr_off(size_t(L) + 1, 0);
-    for (int32_t l = 0; l < L; ++l) {
-      kc_off[l + 1] = kc_off[l] + int64_t(lo_out[l].kcol_row.size());
-      kr_off[l + 1] = kr_off[l] + int64_t(lo_out[l].krow_col.size());
+  P->kcol_row.resize(size_t(nkc));
+  P->kcol_val.resize(size_t(nkc));
+  P->krow_col.resize(size_t(nkc));
+  P->krow_val.resize(size_t(nkc));
+  std::atomic<bool> bad{false};
+  std::vector<std::vector<int32_t>> shidx_w(static_cast<size_t>(nwk));
+  std::vector<std::vector<int64_t>> fill_w(static_cast<size_t>(nwk));
+  parallel_items(L, [&](int64_t l, int w) {
+    std::vector<int32_t>& posB = posB_w[size_t(w)];   // position in B_l of the leaf's columns
+    if (posB.empty()) posB.resize(size_t(std::max<int64_t>(1, nB)));
+    std::vector<int32_t>& shell_idx = shidx_w[size_t(w)];
+    std::vector<int64_t>& fill = fill_w[size_t(w)];
+    const std::vector<int32_t>& B = Bl[size_t(l)];
+    const std::vector<int32_t>& sh = shl[size_t(l)];
+    const int64_t off = P->leaf_off[l], nl = P->leaf_n[l], m = int64_t(B.size());
+    const int64_t base = P->B_off[l];
+    std::copy(B.begin(), B.end(), P->B.begin() + base);
+    std::copy(sh.begin(), sh.end(), P->shell.begin() + P->shell_off[l]);
+    for (int64_t a = 0; a < m; ++a) posB[B[a] - P->n_leaf] = int32_t(a);
+    shell_idx.assign(size_t(nl), -1);
+    for (size_t q = 0; q < sh.size(); ++q) shell_idx[sh[q]] = int32_t(q);
+    // columns of K_{l,B}: offsets from the counts of pass 1, then the entries in row order
+    const std::vector<int32_t>& cn = cntl[size_t(l)];
+    fill.resize(size_t(m) + 1);
+    fill[0] = kc_off[l];
+    for (int64_t a = 0; a < m; ++a) {
+      fill[a + 1] = fill[a] + cn[size_t(a)];
+      P->kcol_ptr[base + a + 1] = fill[a + 1];
     }
-    P->B.resize(size_t(nBflat));
-    P->shell.resize(size_t(P->shell_off[L]));
-    P->kcol_row.resize(size_t(nkc));
-    P->kcol_val.resize(size_t(nkc));
-    P->krow_col.resize(size_t(nkr));
-    P->krow_val.resize(size_t(nkr));
-    std::atomic<int32_t> next{0};
-    std::vector<std::thread> th;
-    const int nw = std::min<int>(num_threads(), std::max(1, L));
-    for (int w = 0; w < nw; ++w)
-      th.emplace_back([&]() {
-        for (;;) {
-          const int32_t l = next++;
-          if (l >= L) break;
-          LeafOut& o = lo_out[l];
-          const int64_t base = P->B_off[l];
-          for (size_t a = 0; a < o.B.size(); ++a) {
-            P->kcol_ptr[base + a + 1] = kc_off[l] + o.kcol_ptr[a + 1];
-            P->krow_ptr[base + a + 1] = kr_off[l] + o.krow_ptr[a + 1];
-          }
-          std::copy(o.B.begin(), o.B.end(), P->B.begin() + base);
-          std::copy(o.shell.begin(), o.shell.end(), P->shell.begin() + P->shell_off[l]);
-          std::copy(o.kcol_row.begin(), o.kcol_row.end(), P->kcol_row.begin() + kc_off[l]);
-          std::copy(o.kcol_val.begin(), o.kcol_val.end(), P->kcol_val.begin() + kc_off[l]);
-          std::copy(o.krow_col.begin(), o.krow_col.end(), P->krow_col.begin() + kr_off[l]);
-          std::copy(o.krow_val.begin(), o.krow_val.end(), P->krow_val.begin() + kr_off[l]);
-          o = LeafOut();
+    for (int64_t r = 0; r < nl; ++r) {
+      const int32_t orow = P->perm[off + r];
+      for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+        const int32_t c = P->iperm[col_idx[k]];
+        if (c < P->n_leaf) continue;
+        const int64_t f = fill[posB[c - P->n_leaf]]++;
+        P->kcol_row[f] = int32_t(r);
+        P->kcol_val[f] = k;
+      }
+    }
+    // rows of K_{B,l}
+    int64_t q = kc_off[l];
+    for (int64_t a = 0; a < m; ++a) {
+      const int32_t orow = P->perm[B[a]];
+      for (int64_t k = row_ptr[orow]; k < row_ptr[orow + 1]; ++k) {
+        const int32_t c = P->iperm[col_idx[k]];
+        if (c < off || c >= off + nl) continue;
+        if (q >= kc_off[l + 1] || shell_idx[c - off] < 0) {
+          bad = true;
+          break;
         }
-      });
-    for (auto& t : th) t.join();
+        P->krow_col[q] = shell_idx[c - off];
+        P->krow_val[q] = k;
+        ++q;
+      }
+      P->krow_ptr[base + a + 1] = q;
+    }
+    if (q != kc_off[l + 1]) bad = true;
+  });
+  if (bad) {
+    *msg = "internal error: interface row couples to a non-shell interior dof";
+    return PlanError::kInvalid;
   }
+  Bl.clear();
+  shl.clear();
+  cntl.clear();
   // adjacency of interface dofs: (leaf, position in B_l), sorted by leaf
   P->adj_ptr.assign(nB + 1, 0);
   for (int32_t p : P->B) P->adj_ptr[p - P->n_leaf + 1]++;

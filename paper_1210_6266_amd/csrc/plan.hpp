@@ -18,7 +18,10 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace rsd {
@@ -29,6 +32,24 @@ constexpr int kEllSlice = 64;  // rows per ELL slice (one wave)
 
 // A batch of symmetric matrices stored as packed lower tiles (tile (I, J) with
 // I >= J; column-major kTile x kTile each; diagonal tiles hold both triangles).
+// A std::vector whose resize() leaves new elements of a trivial type uninitialised.  The
+// analysis' large arrays are written in full by their (parallel) producers, which then also
+// take the first-touch page faults, instead of a serial zero fill before them.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind { using other = NoInitAlloc<U>; };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept { ::new (static_cast<void*>(p)) U; }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) { ::new (static_cast<void*>(p)) U(std::forward<A>(a)...); }
+};
+template <typename T>
+using hvec = std::vector<T, NoInitAlloc<T>>;
+
 struct SymBatch {
   int32_t count = 0;
   std::vector<int32_t> n;          // order of each matrix
@@ -70,11 +91,11 @@ struct Plan {
   std::vector<int32_t> dof_level;            // per interface dof (index - n_leaf): level
 
   // ordering
-  std::vector<int32_t> perm, iperm;          // internal -> caller, caller -> internal
+  hvec<int32_t> perm, iperm;          // internal -> caller, caller -> internal
 
   // K in internal order: row pointers here; the columns, the map to the caller's
   // value positions and the row segments are built on the device from perm/iperm
-  std::vector<int64_t> prow;
+  hvec<int64_t> prow;
   // the same rows as sliced ELL for the SpMV: slices of kEllSlice consecutive rows,
   // slice s padded to its longest row; entry k of row r at ell_off[s] + k kEllSlice + r % kEllSlice
   std::vector<int64_t> ell_off;
@@ -83,7 +104,7 @@ struct Plan {
 
   // leaf boundaries B_l (internal interface dof indices)
   std::vector<int64_t> B_off;                // per leaf, size num_leaves + 1
-  std::vector<int32_t> B;
+  hvec<int32_t> B;
   std::vector<int64_t> sig_off;              // element offset of Sigma_l (m_l x m_l)
   int64_t sig_total = 0;
   // adjacency of interface dofs: (leaf, position in B_l), sorted by leaf
@@ -93,15 +114,15 @@ struct Plan {
   // Sigma_l = K_{B l} K_ll^{-1} K_{l B}:
   //   shell_l = interior rows of l coupled to B_l (local indices)
   std::vector<int64_t> shell_off;
-  std::vector<int32_t> shell;
+  hvec<int32_t> shell;
   //   columns of K_{l B}: per flat column (B_off[l] + b): (local row j, caller position)
   std::vector<int64_t> kcol_ptr;
-  std::vector<int32_t> kcol_row;
-  std::vector<int64_t> kcol_val;
+  hvec<int32_t> kcol_row;
+  hvec<int64_t> kcol_val;
   //   rows of K_{B l}: per flat row (B_off[l] + a): (shell index, caller position)
   std::vector<int64_t> krow_ptr;
-  std::vector<int32_t> krow_col;
-  std::vector<int64_t> krow_val;
+  hvec<int32_t> krow_col;
+  hvec<int64_t> krow_val;
   std::vector<int64_t> w_off;                // element offset of W_l (shell_l x m_l)
   int64_t w_total = 0;
 
