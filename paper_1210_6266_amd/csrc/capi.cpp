@@ -66,9 +66,9 @@ rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analys
     if (st != RSD_OK) return st;
     rsd::Plan P;
     std::string msg;
-    const rsd::PlanError e = rsd::build_plan(csr->n, csr->nnz, csr->row_ptr, csr->col_idx,
-                                             hier->num_nodes, hier->parent, hier->dof_node, &P,
-                                             &msg);
+    rsd::PlanError e = rsd::build_plan(csr->n, csr->nnz, csr->row_ptr, csr->col_idx,
+                                       hier->num_nodes, hier->parent, hier->dof_node, &P, &msg);
+    if (e == rsd::PlanError::kOk) e = rsd::build_plan_couplings(csr->row_ptr, csr->col_idx, &P, &msg);
     if (e == rsd::PlanError::kNotSeparable) return fail(RSD_ERR_MAP_NOT_SEPARABLE, msg);
     if (e != rsd::PlanError::kOk) return fail(RSD_ERR_INVALID_ARGUMENT, msg);
     rsd::fill_analysis(P, out);

@@ -520,7 +520,9 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     std::string msg;
     const PlanError pe = build_plan(n, nnz, rpp, cip, T, parp, dnp, &h->P, &msg);
     h->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    pfree(h, stage);
+    h->csr_stage = stage;                      // read again by build_plan_couplings
+    h->ana_rp = rpp;
+    h->ana_ci = cip;
     if (pe != PlanError::kOk) {
       h->err = msg;
       return pe == PlanError::kNotSeparable ? RSD_ERR_MAP_NOT_SEPARABLE : RSD_ERR_INVALID_ARGUMENT;
@@ -557,33 +559,6 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->segB = dalloc<int64_t>(h, size_t(n));
     h->segC = dalloc<int64_t>(h, size_t(n));
     h->pval = dalloc<double>(h, size_t(nnz));
-    up.add(&h->B_off, P.B_off);
-    up.add(&h->B, P.B);
-    up.add(&h->adj_ptr, P.adj_ptr);
-    up.add(&h->adj_leaf, P.adj_leaf);
-    up.add(&h->adj_pos, P.adj_pos);
-    up.add(&h->sig_off_d, P.sig_off);
-    SigmaArgs& a = h->sig;
-    a.num_leaves = int32_t(P.leaf_node.size());
-    a.max_m = P.max_m;
-    up.add(&a.shell_off, P.shell_off);
-    up.add(&a.shell, P.shell);
-    up.add(&a.kcol_ptr, P.kcol_ptr);
-    up.add(&a.kcol_row, P.kcol_row);
-    up.add(&h->kcol_pos, P.kcol_val);
-    up.add(&a.krow_ptr, P.krow_ptr);
-    up.add(&a.krow_col, P.krow_col);
-    up.add(&h->krow_pos, P.krow_val);
-    up.add(&a.w_off, P.w_off);
-    h->kcol_v = dalloc<double>(h, P.kcol_val.size());
-    h->krow_v = dalloc<double>(h, P.krow_val.size());
-    a.kcol_v = h->kcol_v;
-    a.krow_v = h->krow_v;
-    h->sigma_fp32 = h->opt.sigma_prec == RSD_PREC_FP32;
-    if (h->sigma_fp32)
-      h->sigma = dalloc<float>(h, size_t(P.sig_total));
-    else
-      h->sigma = dalloc<double>(h, size_t(P.sig_total));
     const bool general = h->opt.symmetric == 0;
     upload_batch(h, up, &h->leaf, P.leaf_batch, h->opt.leaf_prec != RSD_PREC_FP64, !general);
     // a K that is not symmetric: dense sub-domain inverses (Gauss-Jordan, partial pivoting)
@@ -630,49 +605,10 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
                         (h->opt.iface_mode == RSD_IFACE_HYBRID && maxn > h->opt.dense_max);
       h->any_gamma = h->any_gamma || h->gam_level[q];
     }
-    h->lev_items.assign(NL, SigmaLevelItems());
-    h->lev_own_items.assign(NL, SigmaLevelItems());
-
-    // Sigma products per level, split into row chunks: against the deeper levels' columns
-    // (the apply), and against the level's own columns (the S-MatVec of Alg. 1 for the
-    // levels solved with gamma GMRES steps).  Symmetric Sigma blocks whose rows are short
-    // (row-weighted mean length <= kSigRowsMaxCols) go one row per lane in chunks of
-    // kSigRowsWave; longer rows (and general Sigma) go lanes over columns in chunks of
-    // kSigRows, which keeps more waves in flight per row.
-    struct ItemLists { std::vector<int32_t> l, c0, c1, a0, a1; };
-    std::vector<ItemLists> deep(NL), own(NL);
-    auto items = [&](const std::vector<LevelSigmaItem>& src, bool own_cols, ItemLists* o,
-                     SigmaLevelItems* li) {
-      double rows = 0.0, weighted = 0.0;
-      for (const auto& it : src) {
-        const double len = own_cols ? double(it.r1 - it.r0) : double(it.r0);
-        rows += double(it.r1 - it.r0);
-        weighted += len * double(it.r1 - it.r0);
-      }
-      const bool by_rows = h->opt.symmetric && weighted <= double(kSigRowsMaxCols) * rows;
-      const int32_t chunk = by_rows ? kSigRowsWave : kSigRows;
-      for (const auto& it : src)
-        for (int32_t a0 = it.r0; a0 < it.r1; a0 += chunk) {
-          o->l.push_back(it.leaf);
-          o->c0.push_back(own_cols ? it.r0 : 0);
-          o->c1.push_back(own_cols ? it.r1 : it.r0);
-          o->a0.push_back(a0);
-          o->a1.push_back(std::min(it.r1, a0 + chunk));
-        }
-      li->count = int32_t(o->l.size());
-      li->by_rows = by_rows ? 1 : 0;
-      up.add(&li->leaf, o->l);
-      up.add(&li->c0, o->c0);
-      up.add(&li->c1, o->c1);
-      up.add(&li->a0, o->a0);
-      up.add(&li->a1, o->a1);
-    };
     for (int q = 0; q < NL; ++q) {
       const bool root = P.level_depth[q] == 0;
       const int prec = root ? h->opt.root_prec : h->opt.iface_prec;
       upload_batch(h, up, &h->lev[q], P.level_batch[q], prec == RSD_PREC_FP32, !h->gam_level[q]);
-      items(P.level_sigma[q], false, &deep[q], &h->lev_items[q]);
-      if (h->gam_level[q]) items(P.level_sigma_own[q], true, &own[q], &h->lev_own_items[q]);
     }
     // work items of the chunked inner GMRES: levels with a system above one chunk
     h->gm_lev.assign(NL, rsd_ctx::GmLevel());
@@ -727,12 +663,8 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     hip_check(h, launch_permute_csr(n, P.n_leaf, h->perm, h->iperm, d_rp, d_ci, h->prow,
                                     h->skel_lvl_begin, h->skel_own_end, h->pcol, h->pmap,
                                     h->segA, h->segB, h->segC, s), "permute csr");
-    a.B_off = h->B_off;
-    a.B = h->B;
-    a.sig_off = h->sig_off_d;
     const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
     h->flags = dalloc<int32_t>(h, size_t(nflags));
-    h->e = dalloc<double>(h, std::max<size_t>(1, P.B.size()));
     h->t = dalloc<double>(h, size_t(n));
     h->rin = dalloc<double>(h, size_t(n));
     h->zin = dalloc<double>(h, size_t(n));
@@ -744,13 +676,113 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     // (levels solved matrix-free have num_items = 0: no symmetric product)
     h->sympart = dalloc<double>(h, (part_bytes + 7) / 8);
     h->sympart_bytes = part_bytes;
-    hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
-    up.done(h);
+    h->held.push_back(up.stage);               // released after the set-up's final sync
+    up.stage = Pinned();
     h->setup_wall[1] = ms_since(w1);
     return RSD_OK;
   } catch (const Fail& f) {
     return f.st;
   }
+}
+
+// The second part of the analysis (build_plan_couplings: per-leaf coupling blocks, adjacency,
+// Sigma layout and apply schedule) and its upload, queued on s.  A set-up runs it after
+// queueing the sub-domain inversions, so the host work overlaps them.
+void upload_couplings(rsd_ctx* h, hipStream_t s) {
+  if (h->couplings_on_device) return;          // a refresh of the values: same structure
+  const Plan& P = h->P;
+  if (!P.coupled) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string msg;
+    const PlanError pe = build_plan_couplings(h->ana_rp, h->ana_ci, &h->P, &msg);
+    h->host_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    pfree(h, h->csr_stage);
+    h->ana_rp = nullptr;
+    h->ana_ci = nullptr;
+    if (pe != PlanError::kOk) {
+      (void)hipStreamSynchronize(s);           // queued work still reads the handle's blocks
+      (void)hipStreamSynchronize(h->aux);
+      h->err = msg;
+      throw Fail{RSD_ERR_INVALID_ARGUMENT};
+    }
+  }
+  const int NL = int(P.level_depth.size());
+  Uploader up;
+  up.add(&h->B_off, P.B_off);
+  up.add(&h->B, P.B);
+  up.add(&h->adj_ptr, P.adj_ptr);
+  up.add(&h->adj_leaf, P.adj_leaf);
+  up.add(&h->adj_pos, P.adj_pos);
+  up.add(&h->sig_off_d, P.sig_off);
+  SigmaArgs& a = h->sig;
+  a.num_leaves = int32_t(P.leaf_node.size());
+  a.max_m = P.max_m;
+  up.add(&a.shell_off, P.shell_off);
+  up.add(&a.shell, P.shell);
+  up.add(&a.kcol_ptr, P.kcol_ptr);
+  up.add(&a.kcol_row, P.kcol_row);
+  up.add(&h->kcol_pos, P.kcol_val);
+  up.add(&a.krow_ptr, P.krow_ptr);
+  up.add(&a.krow_col, P.krow_col);
+  up.add(&h->krow_pos, P.krow_val);
+  up.add(&a.w_off, P.w_off);
+  h->kcol_v = dalloc<double>(h, P.kcol_val.size());
+  h->krow_v = dalloc<double>(h, P.krow_val.size());
+  a.kcol_v = h->kcol_v;
+  a.krow_v = h->krow_v;
+  h->sigma_fp32 = h->opt.sigma_prec == RSD_PREC_FP32;
+  if (h->sigma_fp32)
+    h->sigma = dalloc<float>(h, size_t(P.sig_total));
+  else
+    h->sigma = dalloc<double>(h, size_t(P.sig_total));
+  h->lev_items.assign(NL, SigmaLevelItems());
+  h->lev_own_items.assign(NL, SigmaLevelItems());
+  // Sigma products per level, split into row chunks: against the deeper levels' columns
+  // (the apply), and against the level's own columns (the S-MatVec of Alg. 1 for the
+  // levels solved with gamma GMRES steps).  Symmetric Sigma blocks whose rows are short
+  // (row-weighted mean length <= kSigRowsMaxCols) go one row per lane in chunks of
+  // kSigRowsWave; longer rows (and general Sigma) go lanes over columns in chunks of
+  // kSigRows, which keeps more waves in flight per row.
+  struct ItemLists { std::vector<int32_t> l, c0, c1, a0, a1; };
+  std::vector<ItemLists> deep(NL), own(NL);
+  auto items = [&](const std::vector<LevelSigmaItem>& src, bool own_cols, ItemLists* o,
+                   SigmaLevelItems* li) {
+    double rows = 0.0, weighted = 0.0;
+    for (const auto& it : src) {
+      const double len = own_cols ? double(it.r1 - it.r0) : double(it.r0);
+      rows += double(it.r1 - it.r0);
+      weighted += len * double(it.r1 - it.r0);
+    }
+    const bool by_rows = h->opt.symmetric && weighted <= double(kSigRowsMaxCols) * rows;
+    const int32_t chunk = by_rows ? kSigRowsWave : kSigRows;
+    for (const auto& it : src)
+      for (int32_t a0 = it.r0; a0 < it.r1; a0 += chunk) {
+        o->l.push_back(it.leaf);
+        o->c0.push_back(own_cols ? it.r0 : 0);
+        o->c1.push_back(own_cols ? it.r1 : it.r0);
+        o->a0.push_back(a0);
+        o->a1.push_back(std::min(it.r1, a0 + chunk));
+      }
+    li->count = int32_t(o->l.size());
+    li->by_rows = by_rows ? 1 : 0;
+    up.add(&li->leaf, o->l);
+    up.add(&li->c0, o->c0);
+    up.add(&li->c1, o->c1);
+    up.add(&li->a0, o->a0);
+    up.add(&li->a1, o->a1);
+  };
+  for (int q = 0; q < NL; ++q) {
+    items(P.level_sigma[q], false, &deep[q], &h->lev_items[q]);
+    if (h->gam_level[q]) items(P.level_sigma_own[q], true, &own[q], &h->lev_own_items[q]);
+  }
+  up.commit(h, s);
+  h->held.push_back(up.stage);                 // released after the set-up's final sync
+  up.stage = Pinned();
+  a.B_off = h->B_off;
+  a.B = h->B;
+  a.sig_off = h->sig_off_d;
+  h->e = dalloc<double>(h, std::max<size_t>(1, P.B.size()));
+  h->couplings_on_device = true;
 }
 
 // Dense set-up from the values of K (caller order, device pointer): Section 3.1's
@@ -767,10 +799,6 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       hip_check(h, launch_gather(values, h->pmap, P.nnz, h->pval, s), "gather values");
       hip_check(h, launch_ell_fill(P.n, h->prow, h->pcol, h->pval, h->ell_off, h->ell_col,
                                    h->ell_val, s), "ELL fill");
-      hip_check(h, launch_gather(values, h->kcol_pos, int64_t(P.kcol_val.size()), h->kcol_v, s),
-                "gather couplings");
-      hip_check(h, launch_gather(values, h->krow_pos, int64_t(P.krow_val.size()), h->krow_v, s),
-                "gather couplings");
       const int64_t nflags = int64_t(P.leaf_node.size()) + int64_t(P.iface_node.size());
       hip_check(h, hipMemsetAsync(h->flags, 0, size_t(nflags) * 4, s), "hipMemsetAsync flags");
       if (h->opt.symmetric) {
@@ -832,6 +860,15 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
         hip_check(h, launch_gen_invert(h->gen, h->prow, h->segA, h->pcol, h->pval, h->flags, s),
                   "general sub-domain inverses");
     }
+    // the couplings (host analysis and upload, while the device inverts the sub-domains)
+    upload_couplings(h, s);
+    {
+      Timer tm(h, RSD_T_SETUP_EXTRACT, s);
+      hip_check(h, launch_gather(values, h->kcol_pos, int64_t(P.kcol_val.size()), h->kcol_v, s),
+                "gather couplings");
+      hip_check(h, launch_gather(values, h->krow_pos, int64_t(P.krow_val.size()), h->krow_v, s),
+                "gather couplings");
+    }
     double* W = dalloc<double>(h, size_t(std::max<int64_t>(1, P.w_total)));
     {
       Timer tm(h, RSD_T_SIGMA, s);
@@ -887,6 +924,8 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       dfree(h, cbuf[i]);
       dfree(h, bbuf[i]);
     }
+    for (Pinned& b : h->held) pfree(h, b);    // the uploads have completed
+    h->held.clear();
     h->setup_wall[3] = ms_since(w3);
     for (size_t i = 0; i < fl.size(); ++i)
       if (fl[i]) {
@@ -1765,6 +1804,9 @@ void engine_free(rsd_ctx* h) {
   h->device_bytes = 0;
   pfree(h, h->hhost_block);
   h->hhost = nullptr;
+  pfree(h, h->csr_stage);
+  for (Pinned& b : h->held) pfree(h, b);
+  h->held.clear();
 }
 
 void release_cache(int device) {

@@ -124,6 +124,15 @@ struct rsd_ctx {
   int64_t launches[RSD_T_COUNT] = {};
   double host_ms = 0.0;
   double setup_wall[4] = {};
+
+  // set-up: the host copy of K's structure kept for the second part of the analysis
+  // (build_plan_couplings), which runs while the device inverts the sub-domains, and
+  // pinned staging buffers released after the set-up's final synchronisation
+  rsd::Pinned csr_stage;
+  const int64_t* ana_rp = nullptr;
+  const int32_t* ana_ci = nullptr;
+  std::vector<rsd::Pinned> held;
+  bool couplings_on_device = false;   // upload_couplings has run (once per handle)
 };
 
 namespace rsd {

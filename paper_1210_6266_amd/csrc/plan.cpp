@@ -454,6 +454,47 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     }
   }
 
+  // ---- dense batches ---------------------------------------------------------------
+  P->leaf_batch = SymBatch();
+  P->leaf_batch.count = L;
+  P->leaf_batch.n.resize(L);
+  P->leaf_batch.vec_off.resize(L);
+  P->sum_leaf_sq = 0;
+  P->leaf_flops = 0;
+  P->max_leaf = 0;
+  for (int32_t l = 0; l < L; ++l) {
+    P->leaf_batch.n[l] = int32_t(P->leaf_n[l]);
+    P->leaf_batch.vec_off[l] = P->leaf_off[l];
+    P->sum_leaf_sq += P->leaf_n[l] * P->leaf_n[l];
+    P->leaf_flops += double(P->leaf_n[l]) * P->leaf_n[l] * P->leaf_n[l];
+    P->max_leaf = std::max<int32_t>(P->max_leaf, int32_t(P->leaf_n[l]));
+  }
+  layout_sym_batch(&P->leaf_batch);
+  P->level_batch.assign(NL, SymBatch());
+  P->sum_iface_sq = 0;
+  P->iface_flops = 0;
+  P->max_iface = 0;
+  for (int32_t q = 0; q < NL; ++q) {
+    SymBatch& b = P->level_batch[q];
+    b.count = P->level_iface_begin[q + 1] - P->level_iface_begin[q];
+    for (int32_t s = P->level_iface_begin[q]; s < P->level_iface_begin[q + 1]; ++s) {
+      b.n.push_back(int32_t(P->iface_n[s]));
+      b.vec_off.push_back(P->iface_off[s]);
+      P->sum_iface_sq += P->iface_n[s] * P->iface_n[s];
+      P->iface_flops += double(P->iface_n[s]) * P->iface_n[s] * P->iface_n[s];
+      P->max_iface = std::max<int32_t>(P->max_iface, int32_t(P->iface_n[s]));
+    }
+    layout_sym_batch(&b);
+  }
+  P->coupled = false;
+  return PlanError::kOk;
+}
+
+PlanError build_plan_couplings(const int64_t* row_ptr, const int32_t* col_idx, Plan* P,
+                               std::string* msg) {
+  const int32_t L = int32_t(P->leaf_node.size());
+  const int64_t nB = P->n - P->n_leaf;
+  const int32_t NL = int32_t(P->level_depth.size());
   // ---- per leaf: B_l, shell_l, K_{l,B_l} by columns, K_{B_l,l} by rows ----------------
   // (read from the caller's CSR; value positions are the caller's).  Pass 1 finds B_l and
   // the shell and counts the couplings; pass 2 writes both coupling blocks straight into
@@ -616,38 +657,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       if (r1 > r0) P->level_sigma_own[q].push_back({l, r0, r1});
     }
 
-  // ---- dense batches ---------------------------------------------------------------
-  P->leaf_batch = SymBatch();
-  P->leaf_batch.count = L;
-  P->leaf_batch.n.resize(L);
-  P->leaf_batch.vec_off.resize(L);
-  P->sum_leaf_sq = 0;
-  P->leaf_flops = 0;
-  P->max_leaf = 0;
-  for (int32_t l = 0; l < L; ++l) {
-    P->leaf_batch.n[l] = int32_t(P->leaf_n[l]);
-    P->leaf_batch.vec_off[l] = P->leaf_off[l];
-    P->sum_leaf_sq += P->leaf_n[l] * P->leaf_n[l];
-    P->leaf_flops += double(P->leaf_n[l]) * P->leaf_n[l] * P->leaf_n[l];
-    P->max_leaf = std::max<int32_t>(P->max_leaf, int32_t(P->leaf_n[l]));
-  }
-  layout_sym_batch(&P->leaf_batch);
-  P->level_batch.assign(NL, SymBatch());
-  P->sum_iface_sq = 0;
-  P->iface_flops = 0;
-  P->max_iface = 0;
-  for (int32_t q = 0; q < NL; ++q) {
-    SymBatch& b = P->level_batch[q];
-    b.count = P->level_iface_begin[q + 1] - P->level_iface_begin[q];
-    for (int32_t s = P->level_iface_begin[q]; s < P->level_iface_begin[q + 1]; ++s) {
-      b.n.push_back(int32_t(P->iface_n[s]));
-      b.vec_off.push_back(P->iface_off[s]);
-      P->sum_iface_sq += P->iface_n[s] * P->iface_n[s];
-      P->iface_flops += double(P->iface_n[s]) * P->iface_n[s] * P->iface_n[s];
-      P->max_iface = std::max<int32_t>(P->max_iface, int32_t(P->iface_n[s]));
-    }
-    layout_sym_batch(&b);
-  }
+  P->coupled = true;
   return PlanError::kOk;
 }
 

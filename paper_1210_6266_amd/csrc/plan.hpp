@@ -134,6 +134,7 @@ struct Plan {
   std::vector<SymBatch> level_batch;         // per level
 
   // totals for roofline accounting
+  bool coupled = false;                      // build_plan_couplings has run
   int64_t sum_leaf_sq = 0, sum_iface_sq = 0, sum_sigma_sq = 0, sum_sigma_apply = 0;
   double leaf_flops = 0.0, iface_flops = 0.0;
   int32_t max_leaf = 0, max_iface = 0, max_m = 0;
@@ -142,9 +143,17 @@ struct Plan {
 enum class PlanError { kOk = 0, kInvalid = 1, kNotSeparable = 2 };
 
 // Builds the plan from host arrays (multithreaded).  Returns kOk, or an error with *msg.
+// The analysis in two parts.  build_plan validates K and the hierarchy and computes the
+// ordering, the internal row pointers, the ELL layout and the dense batches (all the first
+// device work needs); build_plan_couplings then adds, from the same (validated) CSR, the
+// per-leaf coupling blocks, the adjacency lists and the Sigma layout and apply schedule
+// (coupled = true).  A set-up runs the second part on the host while the device inverts
+// the sub-domains.
 PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                      int32_t num_nodes, const int32_t* parent, const int32_t* dof_node,
                      Plan* plan, std::string* msg);
+PlanError build_plan_couplings(const int64_t* row_ptr, const int32_t* col_idx, Plan* plan,
+                               std::string* msg);
 
 // Tile layout and symmetric-product work items of a batch.
 void layout_sym_batch(SymBatch* b);
