@@ -206,7 +206,10 @@ rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analys
  *  1. Host analysis: validates the CSR, the tree and dof_node; checks that the
  *     decomposition separates K (every non-zero K_ij joins dofs whose nodes lie
  *     on one root-to-leaf path -- the block structure of eq. (matPart)); orders
- *     dofs as [leaf interiors | interfaces, deepest level first].
+ *     dofs as [leaf interiors | interfaces, deepest level first].  The check of
+ *     the pattern's symmetry and the per-sub-domain coupling blocks follow on the
+ *     host while the device inverts the sub-domains (a non-symmetric pattern is
+ *     reported once that queued work has finished).
  *  2. Device: extracts every true sub-domain matrix K_ll and inverts it exactly
  *     (the direct sub-domain solve of Section 3.1), forms the leaf boundary
  *     blocks Sigma_l = K_Bl K_ll^-1 K_lB, assembles for every internal node t the
@@ -217,7 +220,8 @@ rsd_status rsd_analyze(const rsd_csr* csr, const rsd_hierarchy* hier, rsd_analys
  * csr / hier: device pointers unless opt->host_pointers = 1.  opt may be NULL
  * (defaults).  On success *out receives a new handle; on failure *out = NULL and
  * rsd_last_error(NULL) describes the error (thread-local).  Synchronises `stream`
- * once at the end (pivot status read-back).
+ * after copying the structure to the host (device pointers) and at the end (pivot
+ * status read-back).
  * Errors: INVALID_ARGUMENT, MAP_NOT_SEPARABLE, NOT_SPD, OUT_OF_MEMORY, DEVICE. */
 rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_options* opt,
                      void* stream, rsd_handle* out);

@@ -117,6 +117,113 @@ void parallel_items(int64_t count, const std::function<void(int64_t, int)>& fn) 
 
 }  // namespace
 
+namespace {
+
+// Structural symmetry of a CSR whose columns are in range and strictly increasing: every
+// entry above the diagonal matched with its transpose, with as many entries below the
+// diagonal as above (then that map is a bijection and the lower ones are covered too).  A
+// worker's rows come in increasing order, so the transposes it looks for in a row j come
+// in increasing column order: one cursor per row j (within the worker's window of rows)
+// replaces a search.  If a cursor finds anything else, an exact search over all rows
+// names the lowest row with a missing transpose (the message does not depend on the
+// thread schedule).
+PlanError check_symmetry(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                         std::string* msg) {
+  struct Worker {
+    int64_t up = 0, dn = 0;
+    bool asym = false;
+    int64_t row = INT64_MAX;                   // lowest row of an exact search's finding
+    std::string msg;
+  };
+  auto sym_error = [&](int64_t i, Worker* o) {  // the first missing transpose of row i
+    for (int64_t k = row_ptr[i + 1] - 1; k >= row_ptr[i] && col_idx[k] > i; --k) {
+      const int32_t j = col_idx[k];
+      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
+        o->row = i;
+        o->msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
+                     i, j);
+        return true;
+      }
+    }
+    return false;
+  };
+  std::vector<Worker> wk(size_t(Pool::get().size()));
+  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+    Worker& o = wk[size_t(w)];
+    int64_t jmax = lo;                         // window of rows searched: [lo, jmax]
+    for (int64_t i = lo; i < hi; ++i)
+      if (row_ptr[i + 1] > row_ptr[i]) jmax = std::max<int64_t>(jmax, col_idx[row_ptr[i + 1] - 1]);
+    const bool cursors = jmax - lo < std::max<int64_t>(4 * (hi - lo), int64_t(1) << 20);
+    std::vector<int32_t> cur;                  // per row of the window: next position, or -1
+    if (cursors) cur.assign(size_t(jmax - lo + 1), -1);
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t* cb = col_idx + row_ptr[i];
+      const int32_t* ce = col_idx + row_ptr[i + 1];
+      const int32_t* d = std::lower_bound(cb, ce, int32_t(i));   // first column >= i
+      const int32_t* u = d < ce && *d == i ? d + 1 : d;          // first column > i
+      o.dn += d - cb;
+      o.up += ce - u;
+      if (!cursors) {
+        if (o.row == INT64_MAX) sym_error(i, &o);
+        continue;
+      }
+      if (o.asym) continue;
+      for (const int32_t* q = u; q < ce; ++q) {
+        const int32_t j = *q;
+        const int64_t rj = row_ptr[j];
+        int32_t& cj = cur[size_t(j - lo)];
+        if (cj < 0)
+          cj = int32_t(std::lower_bound(col_idx + rj, col_idx + row_ptr[j + 1], int32_t(lo)) -
+                       (col_idx + rj));
+        if (rj + cj < row_ptr[j + 1] && col_idx[rj + cj] == i) {
+          ++cj;
+        } else {
+          o.asym = true;
+          break;
+        }
+      }
+    }
+  });
+  bool asym = false;
+  for (const Worker& o : wk) asym = asym || o.asym;
+  if (asym) {
+    for (Worker& o : wk) o.row = INT64_MAX;
+    parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+      for (int64_t i = lo; i < hi; ++i)
+        if (sym_error(i, &wk[size_t(w)])) return;
+    });
+  }
+  const Worker* best = nullptr;
+  for (const Worker& o : wk)
+    if (o.row != INT64_MAX && (best == nullptr || o.row < best->row)) best = &o;
+  if (best) {
+    *msg = best->msg;
+    return PlanError::kInvalid;
+  }
+  int64_t up = 0, dn = 0;
+  for (const Worker& o : wk) {
+    up += o.up;
+    dn += o.dn;
+  }
+  if (up != dn) {
+    // some entry below the diagonal has no transpose: report the first one
+    for (int32_t i = 0; i < n; ++i)
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] && col_idx[k] < i; ++k) {
+        const int32_t j = col_idx[k];
+        if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
+          *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
+                     i, j);
+          return PlanError::kInvalid;
+        }
+      }
+    *msg = "K is not structurally symmetric";
+    return PlanError::kInvalid;
+  }
+  return PlanError::kOk;
+}
+
+}  // namespace
+
 void layout_sym_batch(SymBatch* b) {
   const int64_t TT = int64_t(kTile) * kTile;
   b->nt.assign(b->count, 0);
@@ -214,51 +321,21 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     return tin[a] <= tin[b] && tout[b] <= tout[a];
   };
   // ---- one parallel pass over the rows --------------------------------------------------
-  // Per row: columns in range and strictly increasing; each entry above the diagonal
-  // matched with its transpose (structural symmetry: with as many entries below the
-  // diagonal as above, that map is a bijection and the lower ones are covered too); the
-  // counts of both; separability (every coupling joins nodes on one root-to-leaf path).
-  // A worker's rows come in increasing order, so the transposes it looks for in a row j
-  // come in increasing column order: one cursor per row j (within the worker's window of
-  // rows) replaces a search.  If a cursor finds anything else, the exact search runs over
-  // all rows afterwards to name the first missing transpose.  Each check reports its lowest
-  // failing row, so messages do not depend on the thread schedule; the checks are
-  // reported in that order, the tree's errors before separability.
+  // Per row: columns in range and strictly increasing; separability (every coupling joins
+  // nodes on one root-to-leaf path).  Each check reports its lowest failing row, so
+  // messages do not depend on the thread schedule; the CSR's errors come first, then the
+  // tree's, then separability.  (Structural symmetry, which no device work before the
+  // couplings relies on, is checked by build_plan_couplings.)
   struct RowErr {
     int64_t row = INT64_MAX;
     std::string msg;
   };
   struct Worker {
-    RowErr col, sym, sep;
-    int64_t up = 0, dn = 0;
-    bool asym = false;                         // a cursor met something other than a transpose
-  };
-  auto sym_error = [&](int64_t i, RowErr* e) {   // the first missing transpose of row i
-    for (int64_t k = row_ptr[i + 1] - 1; k >= row_ptr[i] && col_idx[k] > i; --k) {
-      const int32_t j = col_idx[k];
-      if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], int32_t(i))) {
-        *e = {i, fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
-                     i, j)};
-        return true;
-      }
-    }
-    return false;
+    RowErr col, sep;
   };
   std::vector<Worker> wk(size_t(Pool::get().size()));
   parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
     Worker& o = wk[size_t(w)];
-    // window of rows whose transposes this worker looks for: [lo, jmax]
-    int64_t jmax = lo;
-    bool cursors = true;
-    for (int64_t i = lo; i < hi && cursors; ++i)
-      if (row_ptr[i + 1] > row_ptr[i]) {
-        const int32_t c = col_idx[row_ptr[i + 1] - 1];
-        if (c < 0 || c >= n) cursors = false;  // reported by the row checks below
-        jmax = std::max<int64_t>(jmax, c);
-      }
-    cursors = cursors && jmax - lo < std::max<int64_t>(4 * (hi - lo), int64_t(1) << 20);
-    std::vector<int32_t> cur;                  // per row of the window: next position, or -1
-    if (cursors) cur.assign(size_t(jmax - lo + 1), -1);
     for (int64_t i = lo; i < hi; ++i) {
       const int64_t b = row_ptr[i], en = row_ptr[i + 1];
       for (int64_t k = b; k < en; ++k) {
@@ -271,31 +348,6 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
           o.col = {i, fmt("columns of row %lld not strictly increasing", i)};
           return;
         }
-      }
-      const int32_t* cb = col_idx + b;
-      const int32_t* ce = col_idx + en;
-      const int32_t* d = std::lower_bound(cb, ce, int32_t(i));   // first column >= i
-      o.dn += d - cb;
-      const int32_t* u = d < ce && *d == i ? d + 1 : d;          // first column > i
-      o.up += ce - u;
-      if (cursors) {
-        if (!o.asym)
-          for (const int32_t* q = u; q < ce; ++q) {
-            const int32_t j = *q;
-            const int64_t rj = row_ptr[j];
-            int32_t& cj = cur[size_t(j - lo)];
-            if (cj < 0)
-              cj = int32_t(std::lower_bound(col_idx + rj, col_idx + row_ptr[j + 1], int32_t(lo)) -
-                           (col_idx + rj));
-            if (rj + cj < row_ptr[j + 1] && col_idx[rj + cj] == i) {
-              ++cj;
-            } else {
-              o.asym = true;
-              break;
-            }
-          }
-      } else if (o.sym.row == INT64_MAX) {
-        sym_error(i, &o.sym);
       }
       if (tree_ok && o.sep.row == INT64_MAX) {
         const int32_t a = dof_node[i];
@@ -322,40 +374,6 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   if (const RowErr* r = lowest(&Worker::col)) {
     *msg = r->msg;
     return PlanError::kInvalid;
-  }
-  bool asym = false;
-  for (const Worker& o : wk) asym = asym || o.asym;
-  if (asym) {                                  // name the first missing transpose, if any
-    for (Worker& o : wk) o.sym = RowErr();
-    parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
-      for (int64_t i = lo; i < hi; ++i)
-        if (sym_error(i, &wk[size_t(w)].sym)) return;
-    });
-  }
-  if (const RowErr* r = lowest(&Worker::sym)) {
-    *msg = r->msg;
-    return PlanError::kInvalid;
-  }
-  {
-    int64_t up = 0, dn = 0;
-    for (const Worker& o : wk) {
-      up += o.up;
-      dn += o.dn;
-    }
-    if (up != dn) {
-      // some entry below the diagonal has no transpose: report the first one
-      for (int32_t i = 0; i < n; ++i)
-        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1] && col_idx[k] < i; ++k) {
-          const int32_t j = col_idx[k];
-          if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) {
-            *msg = fmt("K is not structurally symmetric: (%lld, %lld) present, transpose missing",
-                       i, j);
-            return PlanError::kInvalid;
-          }
-        }
-      *msg = "K is not structurally symmetric";
-      return PlanError::kInvalid;
-    }
   }
   if (!tree_ok) {
     *msg = tree_msg;
@@ -492,6 +510,10 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
 
 PlanError build_plan_couplings(const int64_t* row_ptr, const int32_t* col_idx, Plan* P,
                                std::string* msg) {
+  {
+    const PlanError e = check_symmetry(P->n, row_ptr, col_idx, msg);
+    if (e != PlanError::kOk) return e;
+  }
   const int32_t L = int32_t(P->leaf_node.size());
   const int64_t nB = P->n - P->n_leaf;
   const int32_t NL = int32_t(P->level_depth.size());
