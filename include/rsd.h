@@ -27,8 +27,9 @@
  *   - Handles are not thread-safe; distinct handles may be used concurrently (each
  *     holds its own streams, events and device memory).
  *   - Process-wide caches: device blocks and pinned staging buffers released by
- *     handles, and the auxiliary streams of destroyed handles, are kept for the next
- *     handle (up to 48 GiB of device blocks per device) until rsd_release_cache.
+ *     handles, and the auxiliary streams and timing events of destroyed handles, are
+ *     kept for the next handle (up to 48 GiB of device blocks per device) until
+ *     rsd_release_cache.
  */
 #ifndef RSD_H_
 #define RSD_H_
@@ -128,9 +129,11 @@ typedef struct {
                             ignored while timing = 1                                       */
   int32_t autotune;      /* 1: before the first application to 2..8 columns, time the
                             candidate numbers of vectors per pass (1, 2, 4) of every dense
-                            batch's symmetric product on the handle's own blocks and keep
-                            the fastest; and on the first set-ups of each batch shape, time
-                            in turn the inversion schedules (look-ahead or serial steps;
+                            batch's symmetric product, each with one workgroup per item
+                            and as a persistent work-queue launch, on the handle's own
+                            blocks and keep the fastest; and on the first set-ups of
+                            each batch shape, time in turn the inversion schedules
+                            (look-ahead or serial steps;
                             128 x 128 or 256 x 256 update super-tiles for BF16-split
                             batches) and keep the fastest.  Results do not depend on any
                             choice; the choices are remembered per process for batches of
@@ -146,6 +149,11 @@ typedef struct {
                             each FP32 operand split exactly into three BF16 parts and six
                             products accumulated in FP32 (errors of FP32 order); 0 on the
                             FP32 matrix cores.  The FP64 blocks are unaffected.             */
+  int32_t sym_form;      /* symmetric products of the applies: 0 (default) one workgroup
+                            per 4 x 4 tile block, unless the autotuner picks the persistent
+                            form for a batch; 1 always the persistent work-queue form
+                            (resident workgroups take the blocks from a counter).  Same
+                            results either way                                               */
   /* Optional device allocator for the handle's memory (set both or neither; default
      NULL: the library's own cache of hipMalloc blocks).  dev_alloc(bytes, alloc_ctx)
      returns device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY);
@@ -307,13 +315,15 @@ typedef struct {
   rsd_analysis analysis;
   double time_ms[RSD_T_COUNT];
   int64_t launches[RSD_T_COUNT];
-  double host_analysis_ms; /* wall time of step 1 of rsd_setup                 */
+  double host_analysis_ms; /* host time of the analysis (step 1 of rsd_setup;
+                              its second part overlaps the device's set-up)     */
   int64_t device_bytes;    /* device memory held by the handle                */
   double setup_wall_ms[4]; /* last rsd_setup / rsd_update_values, host wall time:
-                              [0] structure copy to the host and analysis,
-                              [1] device allocation and index upload,
-                              [2] enqueueing the dense set-up,
-                              [3] waiting for it and releasing scratch memory  */
+                              [0] structure copy to the host and the analysis'
+                                  first part, [1] device allocation and index
+                                  upload, [2] enqueueing the dense set-up and the
+                                  analysis' second part, [3] waiting for the device
+                                  and releasing scratch memory                 */
   int32_t vec_pass[8];     /* vectors per pass of the symmetric products chosen by the
                               autotuner (0: not tuned): [0] sub-domains, then the dense
                               interface levels, deepest first                  */
@@ -322,6 +332,9 @@ typedef struct {
                               256 x 256 update super-tiles, 4 serial with them (the
                               set-up autotuner's choice, or the candidate it was timing;
                               every variant gives the same bits)              */
+  int32_t sym_persist[8];   /* the same batches: 1 where the autotuner chose the
+                              persistent work-queue form of the symmetric products
+                              (resident workgroups taking items from a counter)  */
 } rsd_stats;
 
 /* Copies the handle's statistics (synchronises `stream` when timing is on).
@@ -333,7 +346,8 @@ rsd_status rsd_get_stats(rsd_handle h, rsd_stats* out, int32_t reset, void* stre
 void rsd_destroy(rsd_handle h);
 
 /* Returns to the HIP runtime the device blocks and pinned host buffers that destroyed
- * handles left in the library's caches, and destroys the idle auxiliary streams, on
+ * handles left in the library's caches, and destroys the idle auxiliary streams and
+ * timing events, on
  * `device` (every device when device < 0).  Memory and streams held by live handles are
  * not touched.  Safe to call at any time from any thread; later set-ups refill the caches. */
 void rsd_release_cache(int32_t device);

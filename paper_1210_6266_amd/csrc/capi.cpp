@@ -54,6 +54,7 @@ void rsd_options_default(rsd_options* o) {
   o->symmetric = 1;
   o->g_coupling = RSD_COUPLING_FULL;
   o->bf16_split = 1;
+  o->sym_form = 0;
   o->dev_alloc = nullptr;
   o->dev_free = nullptr;
   o->alloc_ctx = nullptr;
@@ -109,6 +110,8 @@ rsd_status rsd_setup(const rsd_csr* csr, const rsd_hierarchy* hier, const rsd_op
       return fail(RSD_ERR_INVALID_ARGUMENT, "symmetric must be 0 or 1");
     if (opt->bf16_split != 0 && opt->bf16_split != 1)
       return fail(RSD_ERR_INVALID_ARGUMENT, "bf16_split must be 0 or 1");
+    if (opt->sym_form != 0 && opt->sym_form != 1)
+      return fail(RSD_ERR_INVALID_ARGUMENT, "sym_form must be 0 or 1");
     if (opt->g_coupling != RSD_COUPLING_FULL && opt->g_coupling != RSD_COUPLING_LEAF_ONLY)
       return fail(RSD_ERR_INVALID_ARGUMENT, "g_coupling must be RSD_COUPLING_FULL or "
                                             "RSD_COUPLING_LEAF_ONLY");

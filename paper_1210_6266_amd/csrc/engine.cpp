@@ -158,10 +158,12 @@ void pfree(rsd_ctx* h, Pinned& b) {
 // destroy, so the set-ups of distinct handles never share a stream; streams released by
 // destroyed handles wait in a per-device pool for the next handle (creating a stream is
 // not free) until release_cache.  Default priority; ordering between a handle's streams
-// is carried by its own events.
+// is carried by its own events.  The timing events of destroyed handles (timing = 1, two
+// per timed launch) wait in the same per-device pool.
 struct AuxPool {
   std::mutex mu;
   std::map<int, std::vector<hipStream_t>> idle;   // device -> streams no handle holds
+  std::map<int, std::vector<hipEvent_t>> events;  // device -> idle timing events
 };
 AuxPool& aux_pool() {
   static AuxPool* p = new AuxPool();
@@ -271,6 +273,14 @@ struct Timer {
     h->pending.push_back({cls, a, b});
   }
   hipEvent_t take() {
+    if (h->pool.empty()) {                     // refill from the process-wide pool
+      AuxPool& p = aux_pool();
+      std::lock_guard<std::mutex> lock(p.mu);
+      std::vector<hipEvent_t>& v = p.events[h->device];
+      const size_t k = std::min<size_t>(v.size(), 64);
+      h->pool.insert(h->pool.end(), v.end() - long(k), v.end());
+      v.resize(v.size() - k);
+    }
     if (!h->pool.empty()) {
       hipEvent_t e = h->pool.back();
       h->pool.pop_back();
@@ -655,6 +665,15 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     } else {
       up.commit(h, s);
     }
+    {                                   // counters of the persistent symmetric products
+      int32_t* q = dalloc<int32_t>(h, 2 * (h->lev.size() + 1));
+      hip_check(h, hipMemsetAsync(q, 0, sizeof(int32_t) * 2 * (h->lev.size() + 1), s),
+                "hipMemsetAsync queues");
+      h->leaf.queue = q;
+      for (size_t i = 0; i < h->lev.size(); ++i) h->lev[i].queue = q + 2 * (i + 1);
+    }
+    h->leaf.persist = h->opt.sym_form == 1 ? 1 : 0;
+    for (DevBatch& d : h->lev) d.persist = h->leaf.persist;
     h->leaf_apply = h->leaf;            // (device pointers are set by the commit above)
     if (half) {
       h->leaf_apply.half = half;
@@ -1117,13 +1136,15 @@ void permute(rsd_ctx* h, int nv, const double* x, int64_t ldx, double* y, int64_
 // Right-hand sides handled together by one apply, SpMV or Krylov iteration.
 constexpr int kRhsGroup = 8;
 
-// ---- autotuner: vectors per pass of the symmetric products -------------------------------
+// ---- autotuner: vectors per pass and launch form of the symmetric products --------------
 // For a column count nv in 2..8, every dense batch (the sub-domains, each exactly solved
-// interface level) times one product of nv vectors with passes of 1, 2 and 4 vectors on
-// the handle's own blocks (one warm-up, two timed runs each) and keeps the fastest; a
-// tie keeps more vectors per pass.  Every grouping gives the same bits, so only speed
-// depends on the choice.  Choices are remembered per process for batches of the same
-// shape (count, sizes, storage type, nv).
+// interface level) times one product of nv vectors with passes of 4, 2 and 1 vectors, each
+// as one workgroup per item and as a persistent work-queue launch, on the handle's own
+// blocks (one warm-up, two timed runs each) and keeps the fastest; a tie keeps the earlier
+// candidate (more vectors per pass, one workgroup per item).  Every choice gives the same
+// bits, so only speed depends on it.  Choices (vectors per pass + 16 for the persistent
+// form) are remembered per process for batches of the same shape (count, sizes, storage
+// type, nv).
 std::mutex g_tune_mu;
 std::unordered_map<std::string, int32_t> g_tune;
 
@@ -1151,8 +1172,9 @@ int32_t tune_batch(rsd_ctx* h, DevBatch& b, const SymBatch& sb, int nv, hipStrea
   hip_check(h, hipEventCreate(&e1), "hipEventCreate");
   int32_t best = 4;
   float best_ms = 0.0f;
-  for (int32_t cand : {4, 2, 1}) {
-    b.vec_pass = cand;
+  for (int32_t cand : {4, 2, 1, 16 + 4, 16 + 2, 16 + 1}) {
+    b.vec_pass = cand & 15;
+    b.persist = cand >> 4;
     hip_check(h, launch_symv(b, h->rin, h->sympart, -1.0, nullptr, h->zin, nv, n, s), "tune");
     hip_check(h, hipEventRecord(e0, s), "hipEventRecord");
     for (int r = 0; r < 2; ++r)
@@ -1166,6 +1188,7 @@ int32_t tune_batch(rsd_ctx* h, DevBatch& b, const SymBatch& sb, int nv, hipStrea
       best_ms = ms;
     }
   }
+  b.persist = 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1187,9 +1210,15 @@ void autotune_apply(rsd_ctx* h, int nv, hipStream_t s) {
 // the tuned vectors per pass for nv columns (0: the default) on every dense batch
 void set_vec_pass(rsd_ctx* h, int nv) {
   const bool have = nv >= 0 && size_t(nv) < h->vec_pass.size() && h->tuned[size_t(nv)];
-  h->leaf_apply.vec_pass = have ? h->vec_pass[size_t(nv)][0] : 0;
-  for (size_t q = 0; q < h->lev.size(); ++q)
-    h->lev[q].vec_pass = have && q < 8 ? h->vec_pass[size_t(nv)][1 + q] : 0;
+  const int32_t forced = h->opt.sym_form == 1 ? 1 : 0;
+  const int32_t c0 = have ? h->vec_pass[size_t(nv)][0] : 0;
+  h->leaf_apply.vec_pass = c0 & 15;
+  h->leaf_apply.persist = forced | (c0 >> 4);
+  for (size_t q = 0; q < h->lev.size(); ++q) {
+    const int32_t c = have && q < 8 ? h->vec_pass[size_t(nv)][1 + q] : 0;
+    h->lev[q].vec_pass = c & 15;
+    h->lev[q].persist = forced | (c >> 4);
+  }
 }
 
 void drop_graphs(rsd_ctx* h) {
@@ -1761,7 +1790,10 @@ rsd_status engine_stats(rsd_ctx* h, rsd_stats* out, int reset, hipStream_t s) {
     out->device_bytes = h->device_bytes;
     for (int i = 0; i < 4; ++i) out->setup_wall_ms[i] = h->setup_wall[i];
     if (h->last_tuned > 0)
-      for (int i = 0; i < 8; ++i) out->vec_pass[i] = h->vec_pass[size_t(h->last_tuned)][size_t(i)];
+      for (int i = 0; i < 8; ++i) {
+        out->vec_pass[i] = h->vec_pass[size_t(h->last_tuned)][size_t(i)] & 15;
+        out->sym_persist[i] = h->vec_pass[size_t(h->last_tuned)][size_t(i)] >> 4;
+      }
     for (int i = 0; i < 8; ++i) out->setup_variant[i] = h->setup_variant[i];
     if (reset) {
       std::memset(h->time_ms, 0, sizeof(h->time_ms));
@@ -1781,11 +1813,18 @@ void engine_free(rsd_ctx* h) {
   drop_graphs(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   h->cap = nullptr;
-  for (auto& p : h->pending) {
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+  {                                            // completed: back to the process-wide pool
+    AuxPool& ap = aux_pool();
+    std::lock_guard<std::mutex> lock(ap.mu);
+    std::vector<hipEvent_t>& v = ap.events[h->device];
+    for (auto& p : h->pending) {
+      v.push_back(p.a);
+      v.push_back(p.b);
+    }
+    v.insert(v.end(), h->pool.begin(), h->pool.end());
   }
-  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  h->pending.clear();
+  h->pool.clear();
   if (h->ev_main) (void)hipEventDestroy(h->ev_main);
   if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
   if (h->ev_last) (void)hipEventDestroy(h->ev_last);
@@ -1822,6 +1861,8 @@ void release_cache(int device) {
       std::lock_guard<std::mutex> lock(p.mu);
       for (hipStream_t st : p.idle[d]) (void)hipStreamDestroy(st);
       p.idle[d].clear();
+      for (hipEvent_t e : p.events[d]) (void)hipEventDestroy(e);
+      p.events[d].clear();
     }
     cache_drain(cache_of(d), false);
     cache_drain(cache_of(-1 - d), true);

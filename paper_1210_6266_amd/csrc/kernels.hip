@@ -3,6 +3,7 @@
 // the sub-domain hierarchy, and the Krylov vector kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -1469,143 +1470,171 @@ __device__ __forceinline__ void xor_fold(P* a, int lane, int o) {
   }
 }
 
-template <typename T, int KV>
+// PERSIST: a persistent work-queue form of the same kernel for uneven batches.  A grid
+// of about one resident workgroup per slot takes items from a counter (queue[0]) until
+// the items run out; the last workgroup to finish (queue[1] counts them) resets both
+// counters for the next launch.  Every item writes its own partial sums, so the results
+// do not depend on which workgroup computed an item.
+template <typename T, int KV, bool PERSIST = false>
 __global__ __launch_bounds__(kBlock) void k_symv1(
     const T* __restrict__ tiles, const int64_t* __restrict__ tile_off,
     const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
     const int64_t* __restrict__ vec_off, const int32_t* __restrict__ item_mat,
     const int32_t* __restrict__ item_BI, const int32_t* __restrict__ item_BJ,
     const double* __restrict__ x, int64_t ldx, int nv,
-    typename SymPart<T>::type* __restrict__ part) {
+    typename SymPart<T>::type* __restrict__ part, int32_t* __restrict__ queue,
+    int64_t num_items) {
   using P = typename SymPart<T>::type;
   constexpr int B = kSymB;
   // elements per load: 16-byte loads of FP64 / FP32, 8-byte loads of 16-bit values
   constexpr int VEC = sizeof(T) == 8 ? 2 : 4;
   constexpr int LPC = 4 / VEC;                 // loads per column (four rows per thread)
   typedef T V __attribute__((ext_vector_type(VEC)));
-  const int it = blockIdx.x;
-  const int m = item_mat[it], BI = item_BI[it], BJ = item_BJ[it];
-  const int n = n_arr[m], nt = nt_arr[m];
-  const int64_t xo = vec_off[m];
-  // thread t: rows q4(v) of the tile (q = t % 16), columns g + 16 u (g = t / 16, u < 4);
-  // FP32 and 16-bit: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1,
-  // 32 + 2q, 33 + 2q (two loads per column, each contiguous over 16 lanes)
-  const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
-  auto q4 = [&](int v) { return sizeof(T) <= 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
   constexpr bool kColLds = sizeof(T) == 8;
   __shared__ P xs[KV][2][B][TS];               // x in the product's precision
   __shared__ P red[KV][4][B][TS];
   __shared__ P colr[kColLds ? KV : 1][B][TS];
-  for (int e = t; e < KV * 2 * B * TS; e += kBlock) {
-    const int k = e / (2 * B * TS), sd = (e / (B * TS)) % 2, b = (e / TS) % B, r = e % TS;
-    const int idx = ((sd == 0 ? BI : BJ) * B + b) * TS + r;
-    xs[k][sd][b][r] = P(idx < n && k < nv ? x[k * ldx + xo + idx] : 0.0);
-  }
-  if (kColLds)
-    for (int e = t; e < KV * B * TS; e += kBlock) (&colr[0][0][0])[e] = P(0);
-  __syncthreads();
-  P cacc[kColLds ? 1 : KV][B * 4];             // [vector][block column b][column u]
-#pragma unroll
-  for (int k = 0; k < (kColLds ? 1 : KV); ++k)
-#pragma unroll
-    for (int i = 0; i < B * 4; ++i) cacc[k][i] = P(0);
-  const int usel = (q >> 2) & 3;               // LDS columns: column g + 16 usel after the fold
-  const T* base = tiles + tile_off[m] + q4(0) + g * TS;
-#pragma unroll
-  for (int bi = 0; bi < B; ++bi) {
-    const int I = BI * B + bi;
-    P ra[KV][4];                               // row part of tile row I, rows q4(v)
-#pragma unroll
-    for (int k = 0; k < KV; ++k)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) ra[k][v] = P(0);
-    if (I < nt) {
-      // x_I: in registers for FP32 tiles, read from LDS at each use for FP64 tiles
-      P xi[kColLds ? 1 : KV][4];
-      if constexpr (!kColLds)
-#pragma unroll
-        for (int k = 0; k < KV; ++k)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) xi[k][v] = xs[k][0][bi][q4(v)];
-#pragma unroll
-      for (int bj = 0; bj < B; ++bj) {
-        const int J = BJ * B + bj;
-        if (J > I) break;
-        const T* tl = base + tile_index(I, J) * TT;
-        V a[4][LPC];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int h = 0; h < LPC; ++h) a[u][h] = ld_stream((const V*)(tl + 16 * u * TS + 32 * h));
-        P cf[KV][4];                           // column parts of this tile, columns g + 16 u
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          P xk[KV];
-#pragma unroll
-          for (int k = 0; k < KV; ++k) {
-            xk[k] = xs[k][1][bj][g + 16 * u];
-            cf[k][u] = P(0);
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const P av = P(a[u][v / VEC][v % VEC]);
-#pragma unroll
+  __shared__ int s_item;
+  for (int round = 0;; ++round) {
+    int it;
+    if constexpr (PERSIST) {
+      if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+      __syncthreads();
+      it = s_item;
+      if (int64_t(it) >= num_items) break;       // the same for the whole workgroup
+    } else {
+      if (round > 0) break;
+      it = blockIdx.x;
+    }
+    const int m = item_mat[it], BI = item_BI[it], BJ = item_BJ[it];
+    const int n = n_arr[m], nt = nt_arr[m];
+    const int64_t xo = vec_off[m];
+    // thread t: rows q4(v) of the tile (q = t % 16), columns g + 16 u (g = t / 16, u < 4);
+    // FP32 and 16-bit: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1,
+    // 32 + 2q, 33 + 2q (two loads per column, each contiguous over 16 lanes)
+    const int t = threadIdx.x, q = t & 15, g = t >> 4, w = t >> 6, lane = t & 63;
+    auto q4 = [&](int v) { return sizeof(T) <= 4 ? 4 * q + v : (v < 2 ? 2 * q + v : 30 + 2 * q + v); };
+    for (int e = t; e < KV * 2 * B * TS; e += kBlock) {
+      const int k = e / (2 * B * TS), sd = (e / (B * TS)) % 2, b = (e / TS) % B, r = e % TS;
+      const int idx = ((sd == 0 ? BI : BJ) * B + b) * TS + r;
+      xs[k][sd][b][r] = P(idx < n && k < nv ? x[k * ldx + xo + idx] : 0.0);
+    }
+    if (kColLds)
+      for (int e = t; e < KV * B * TS; e += kBlock) (&colr[0][0][0])[e] = P(0);
+    __syncthreads();
+    P cacc[kColLds ? 1 : KV][B * 4];             // [vector][block column b][column u]
+    #pragma unroll
+    for (int k = 0; k < (kColLds ? 1 : KV); ++k)
+      #pragma unroll
+      for (int i = 0; i < B * 4; ++i) cacc[k][i] = P(0);
+    const int usel = (q >> 2) & 3;               // LDS columns: column g + 16 usel after the fold
+    const T* base = tiles + tile_off[m] + q4(0) + g * TS;
+    #pragma unroll
+    for (int bi = 0; bi < B; ++bi) {
+      const int I = BI * B + bi;
+      P ra[KV][4];                               // row part of tile row I, rows q4(v)
+      #pragma unroll
+      for (int k = 0; k < KV; ++k)
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) ra[k][v] = P(0);
+      if (I < nt) {
+        // x_I: in registers for FP32 tiles, read from LDS at each use for FP64 tiles
+        P xi[kColLds ? 1 : KV][4];
+        if constexpr (!kColLds)
+          #pragma unroll
+          for (int k = 0; k < KV; ++k)
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) xi[k][v] = xs[k][0][bi][q4(v)];
+        #pragma unroll
+        for (int bj = 0; bj < B; ++bj) {
+          const int J = BJ * B + bj;
+          if (J > I) break;
+          const T* tl = base + tile_index(I, J) * TT;
+          V a[4][LPC];
+          #pragma unroll
+          for (int u = 0; u < 4; ++u)
+            #pragma unroll
+            for (int h = 0; h < LPC; ++h) a[u][h] = ld_stream((const V*)(tl + 16 * u * TS + 32 * h));
+          P cf[KV][4];                           // column parts of this tile, columns g + 16 u
+          #pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            P xk[KV];
+            #pragma unroll
             for (int k = 0; k < KV; ++k) {
-              const P xv = kColLds ? xs[k][0][bi][q4(v)] : xi[kColLds ? 0 : k][v];
-              cf[k][u] = fma(av, xv, cf[k][u]);
-              ra[k][v] = fma(av, xk[k], ra[k][v]);
+              xk[k] = xs[k][1][bj][g + 16 * u];
+              cf[k][u] = P(0);
             }
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const P av = P(a[u][v / VEC][v % VEC]);
+              #pragma unroll
+              for (int k = 0; k < KV; ++k) {
+                const P xv = kColLds ? xs[k][0][bi][q4(v)] : xi[kColLds ? 0 : k][v];
+                cf[k][u] = fma(av, xv, cf[k][u]);
+                ra[k][v] = fma(av, xk[k], ra[k][v]);
+              }
+            }
+            if (!kColLds && J < I)
+              #pragma unroll
+              for (int k = 0; k < KV; ++k) cacc[kColLds ? 0 : k][bj * 4 + u] += cf[k][u];
           }
-          if (!kColLds && J < I)
-#pragma unroll
-            for (int k = 0; k < KV; ++k) cacc[kColLds ? 0 : k][bj * 4 + u] += cf[k][u];
-        }
-        if (J < I) {
-          if constexpr (kColLds) {
-            // fold over the 16 row lanes (bits 3..0): lanes q with q % 4 == 0 then hold
-            // column g + 16 usel of this tile, which only they update
-#pragma unroll
-            for (int k = 0; k < KV; ++k) {
-              xor_fold<4>(cf[k], lane, 8);
-              xor_fold<2>(cf[k], lane, 4);
-              P c = cf[k][0];
-              c += __shfl_xor(c, 2, 64);
-              c += __shfl_xor(c, 1, 64);
-              if ((q & 3) == 0) colr[k][bj][g + 16 * usel] += c;
+          if (J < I) {
+            if constexpr (kColLds) {
+              // fold over the 16 row lanes (bits 3..0): lanes q with q % 4 == 0 then hold
+              // column g + 16 usel of this tile, which only they update
+              #pragma unroll
+              for (int k = 0; k < KV; ++k) {
+                xor_fold<4>(cf[k], lane, 8);
+                xor_fold<2>(cf[k], lane, 4);
+                P c = cf[k][0];
+                c += __shfl_xor(c, 2, 64);
+                c += __shfl_xor(c, 1, 64);
+                if ((q & 3) == 0) colr[k][bj][g + 16 * usel] += c;
+              }
             }
           }
         }
       }
+      // fold over the wave's four column groups (lane bits 5, 4): lane (q, g) then holds
+      // row q4(g % 4) of tile row I; the four waves are summed in LDS at the end
+      #pragma unroll
+      for (int k = 0; k < KV; ++k) {
+        xor_fold<4>(ra[k], lane, 32);
+        xor_fold<2>(ra[k], lane, 16);
+        red[k][w][bi][q4(g & 3)] = ra[k][0];
+      }
     }
-    // fold over the wave's four column groups (lane bits 5, 4): lane (q, g) then holds
-    // row q4(g % 4) of tile row I; the four waves are summed in LDS at the end
-#pragma unroll
-    for (int k = 0; k < KV; ++k) {
-      xor_fold<4>(ra[k], lane, 32);
-      xor_fold<2>(ra[k], lane, 16);
-      red[k][w][bi][q4(g & 3)] = ra[k][0];
+    // part of item it, side sd (0 rows, 1 columns), vector k
+    auto partp = [&](int sd, int k) { return part + ((int64_t(2 * it + sd) * KV + k) * B) * TS; };
+    if constexpr (!kColLds) {
+      #pragma unroll
+      for (int k = 0; k < KV; ++k) {
+        // columns: fold over the 16 row lanes (bits 3..0); lane q holds block column q / 4,
+        // column g + 16 (q % 4), summed over the block's rows -- written directly
+        xor_fold<B * 4>(cacc[k], lane, 8);
+        xor_fold<B * 2>(cacc[k], lane, 4);
+        xor_fold<B>(cacc[k], lane, 2);
+        xor_fold<B / 2>(cacc[k], lane, 1);
+        if (k < nv) partp(1, k)[(q >> 2) * TS + g + 16 * (q & 3)] = cacc[k][0];
+      }
     }
+    __syncthreads();
+    for (int e = t; e < KV * B * TS; e += kBlock) {
+      const int k = e / (B * TS), b = (e / TS) % B, r = e % TS;
+      if (k < nv) {
+        partp(0, k)[b * TS + r] = (red[k][0][b][r] + red[k][1][b][r]) + (red[k][2][b][r] + red[k][3][b][r]);
+        if constexpr (kColLds) partp(1, k)[b * TS + r] = colr[k][b][r];
+      }
+    }
+    __syncthreads();                             // LDS (and s_item) free for the next item
   }
-  // part of item it, side sd (0 rows, 1 columns), vector k
-  auto partp = [&](int sd, int k) { return part + ((int64_t(2 * it + sd) * KV + k) * B) * TS; };
-  if constexpr (!kColLds) {
-#pragma unroll
-    for (int k = 0; k < KV; ++k) {
-      // columns: fold over the 16 row lanes (bits 3..0); lane q holds block column q / 4,
-      // column g + 16 (q % 4), summed over the block's rows -- written directly
-      xor_fold<B * 4>(cacc[k], lane, 8);
-      xor_fold<B * 2>(cacc[k], lane, 4);
-      xor_fold<B>(cacc[k], lane, 2);
-      xor_fold<B / 2>(cacc[k], lane, 1);
-      if (k < nv) partp(1, k)[(q >> 2) * TS + g + 16 * (q & 3)] = cacc[k][0];
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < KV * B * TS; e += kBlock) {
-    const int k = e / (B * TS), b = (e / TS) % B, r = e % TS;
-    if (k < nv) {
-      partp(0, k)[b * TS + r] = (red[k][0][b][r] + red[k][1][b][r]) + (red[k][2][b][r] + red[k][3][b][r]);
-      if constexpr (kColLds) partp(1, k)[b * TS + r] = colr[k][b][r];
+  if constexpr (PERSIST) {
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(queue + 1, 1) == int(gridDim.x) - 1) {   // the last workgroup: reset
+        atomicExch(queue, 0);
+        atomicExch(queue + 1, 0);
+      }
     }
   }
 }
@@ -2656,6 +2685,21 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
   return hipGetLastError();
 }
 
+// workgroups of a persistent launch: as many as the device holds at once (occupancy of
+// the kernel times the compute units, looked up once per kernel), at most one per item
+template <typename K>
+unsigned persistent_grid(K kernel, int64_t items) {
+  static const int64_t slots = [&] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess)
+      return int64_t(256);
+    return int64_t(std::max(1, cus)) * std::max(1, per);
+  }();
+  return unsigned(std::max<int64_t>(1, std::min<int64_t>(items, slots)));
+}
+
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
                        const double* base, double* y, int nv, int64_t ld, hipStream_t s) {
   if (b.count == 0 || b.num_items == 0 || nv <= 0) return hipSuccess;
@@ -2667,9 +2711,17 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
     const double* bb = base ? base + v0 * ld : nullptr;
     double* yb = y + v0 * ld;
 #define RSD_SYMV(T, KV)                                                                         \
-  k_symv1<T, KV><<<b.num_items, kBlock, 0, s>>>((const T*)b.tiles, b.tile_off, b.n, b.nt,       \
-                                                b.vec_off, b.item_mat, b.item_BI, b.item_BJ, xb, \
-                                                ld, c, (typename SymPart<T>::type*)part)
+  do {                                                                                          \
+    if (b.persist && b.queue)                                                                   \
+      k_symv1<T, KV, true><<<persistent_grid(k_symv1<T, KV, true>, b.num_items), kBlock, 0, s>>>( \
+          (const T*)b.tiles, b.tile_off, b.n, b.nt, b.vec_off, b.item_mat, b.item_BI,           \
+          b.item_BJ, xb, ld, c, (typename SymPart<T>::type*)part, b.queue, b.num_items);        \
+    else                                                                                        \
+      k_symv1<T, KV><<<b.num_items, kBlock, 0, s>>>((const T*)b.tiles, b.tile_off, b.n, b.nt,   \
+                                                    b.vec_off, b.item_mat, b.item_BI, b.item_BJ, \
+                                                    xb, ld, c, (typename SymPart<T>::type*)part, \
+                                                    nullptr, b.num_items);                      \
+  } while (0)
     if (b.half) {
       if (b.half == 1) {
         if (kv == 1) RSD_SYMV(_Float16, 1); else if (kv == 2) RSD_SYMV(_Float16, 2); else RSD_SYMV(_Float16, 4);

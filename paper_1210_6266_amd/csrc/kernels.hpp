@@ -32,6 +32,8 @@ struct DevBatch {
   int32_t fp32 = 0;
   int32_t half = 0;       // apply-side 16-bit copy of FP32 tiles: 1 FP16, 2 BF16 (0: none)
   int32_t vec_pass = 0;   // vectors per pass of the symmetric product (0: symv_vectors)
+  int32_t persist = 0;    // symmetric products as a persistent work-queue launch
+  int32_t* queue = nullptr;   // its two counters (zero between launches)
   int32_t split16 = 0;    // FP32 batches: sweep updates on the BF16 matrix cores, operands
                           // split exactly into three BF16 parts (k_sweep_update_bf3s)
   int32_t upd_shape = 0;  // split16 update form, bitwise alike: 0 128 x 128 super-tiles

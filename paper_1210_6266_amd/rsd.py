@@ -51,7 +51,7 @@ class rsd_options(C.Structure):
                 ("host_pointers", C.c_int32), ("timing", C.c_int32),
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
                 ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32),
-                ("g_coupling", C.c_int32), ("bf16_split", C.c_int32),
+                ("g_coupling", C.c_int32), ("bf16_split", C.c_int32), ("sym_form", C.c_int32),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
 
@@ -79,7 +79,8 @@ class rsd_stats(C.Structure):
     _fields_ = [("analysis", rsd_analysis), ("time_ms", C.c_double * 14),
                 ("launches", C.c_int64 * 14), ("host_analysis_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("setup_wall_ms", C.c_double * 4),
-                ("vec_pass", C.c_int32 * 8), ("setup_variant", C.c_int32 * 8)]
+                ("vec_pass", C.c_int32 * 8), ("setup_variant", C.c_int32 * 8),
+                ("sym_persist", C.c_int32 * 8)]
 
 
 class rsd_fe_map(C.Structure):
@@ -274,6 +275,7 @@ def rsd_get_stats(handle, reset=False, stream=None) -> dict:
     out["setup_wall_ms"] = list(s.setup_wall_ms)
     out["vec_pass"] = list(s.vec_pass)
     out["setup_variant"] = list(s.setup_variant)
+    out["sym_persist"] = list(s.sym_persist)
     return out
 
 
@@ -299,7 +301,8 @@ class RSD:
     def __init__(self, row_ptr, col_idx, values, parent, dof_node, leaf_prec="fp64",
                  sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
                  interface="dense", gamma=8, dense_max=32768, graphs=True, autotune=True,
-                 symmetric=True, coupling="full", allocator=None, bf16_split=True):
+                 symmetric=True, coupling="full", allocator=None, bf16_split=True,
+                 persistent_symv=False):
         """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
         every interface system, the paper's mode) or "hybrid" (gamma steps where an
         interface has more than dense_max dofs).  coupling: "full" or "leaf_only" (the
@@ -310,7 +313,9 @@ class RSD:
         from that stream's pool too).  stream: None (torch's current stream at each
         call) or a fixed stream; calls on other streams are ordered by the library.
         bf16_split: FP32 blocks inverted with their trailing updates on the BF16 matrix
-        cores (operands split exactly into three BF16 parts), rsd_options.bf16_split."""
+        cores (operands split exactly into three BF16 parts), rsd_options.bf16_split.
+        persistent_symv: the applies' symmetric products always as persistent work-queue
+        launches (rsd_options.sym_form = 1; otherwise the autotuner may pick them)."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -339,6 +344,7 @@ class RSD:
         o.autotune = 1 if autotune else 0
         o.g_coupling = COUPLING[coupling]
         o.bf16_split = 1 if bf16_split else 0
+        o.sym_form = 1 if persistent_symv else 0
         self._alloc_cbs = None
         if allocator == "torch":
             if stream is None:

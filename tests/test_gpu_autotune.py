@@ -38,9 +38,11 @@ def test_autotuned_applies_match_untuned(opts):
         zu = hu.apply(_cm(R[:, :k])).cpu().numpy()
         assert np.array_equal(zt, zu), k
     vp = ht.stats()["vec_pass"]
+    sp = ht.stats()["sym_persist"]
     nlev = 2                                  # octree of height 2: two dense levels
     assert all(v in (1, 2, 4) for v in vp[:1 + nlev]), vp
     assert all(v == 0 for v in vp[1 + nlev:]), vp
+    assert all(v in (0, 1) for v in sp), sp
     assert all(v == 0 for v in hu.stats()["vec_pass"])
     B = _cm(R[:, :4])
     Xt, st, it = ht.solve(B, rtol=1e-10)
@@ -74,3 +76,23 @@ def test_setup_autotuner_variants_bitwise(problem_cache, opts):
     ncand = 4 if opts else 2                            # BF16-split FP32 leaves: 4 candidates
     assert all(1 <= v <= ncand for v in seen), seen
     assert seen[-1] == seen[-2], seen                   # settled
+
+
+@pytest.mark.parametrize("leaf_prec", ["fp64", "fp32", "bf16"])
+def test_persistent_symmetric_products_bitwise(leaf_prec):
+    """The persistent work-queue form of the symmetric products (resident workgroups
+    taking 4 x 4 tile blocks from a counter, the last one resetting it) gives the bits of
+    one workgroup per item: a handle with rsd_options.sym_form = 1 (graph replays) and
+    one with the default form (eager) apply 8, 5, 2 and again 8 columns identically on
+    an uneven elasticity tree (the counters are reset between launches)."""
+    p = elasticity_problem(12, 2, 1, nrhs=1)
+    R = np.random.default_rng(7).uniform(-1, 1, size=(p.n, 8))
+    hu = _handle(p, autotune=False, leaf_prec=leaf_prec, graphs=False)
+    hp = _handle(p, autotune=False, leaf_prec=leaf_prec, graphs=True, persistent_symv=True)
+    for k in (8, 5, 2, 8):
+        zu = hu.apply(_cm(R[:, :k])).cpu().numpy()
+        zp = hp.apply(_cm(R[:, :k])).cpu().numpy()
+        assert np.array_equal(zu, zp), k
+    hu.close()
+    hp.close()
+

@@ -152,3 +152,30 @@ def test_calls_on_two_streams_are_ordered(problem_cache):
     assert torch.equal(out[0], ref[0])
     assert torch.equal(h.apply(R[0]), 0.5 * ref[0])
     h.close()
+
+
+def test_timing_events_pooled_and_cache_release(problem_cache):
+    """timing = 1: per-class kernel times and launch counts in rsd_get_stats; the timing
+    events of a destroyed handle serve the next handle (process-wide pool), and after
+    rsd_release_cache (idle streams, events and blocks returned to the runtime) a new
+    handle refills the pools and gives the same bits."""
+    from paper_1210_6266_amd.rsd import rsd_release_cache
+    _log("timing events and cache release")
+    p = problem_cache("diffusion", 20, 2, 1.0, 3)
+    r = torch.as_tensor(np.random.default_rng(9).uniform(-1, 1, p.n)).cuda()
+    ref = None
+    for k in range(3):
+        h = _handle(p, timing=True)
+        z = h.apply(r)
+        st = h.stats()
+        h.close()
+        assert st["launches"]["leaf_update"] > 0 and st["time_ms"]["leaf_update"] > 0.0, st
+        assert st["time_ms"]["leaf_apply"] > 0.0, st
+        if ref is None:
+            ref = z.clone()
+        assert torch.equal(z, ref)
+        if k == 1:
+            rsd_release_cache()
+    h = _handle(p)
+    assert torch.equal(h.apply(r), ref)
+    h.close()
