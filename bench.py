@@ -66,6 +66,11 @@ def parse():
                     help="forward+backward passes timed on the 32^3 adjoint workload (0: skip)")
     ap.add_argument("--elasticity-steps", type=int, default=2,
                     help="set-up + 8-RHS solves timed on the 48^3 elasticity workload (0: skip)")
+    ap.add_argument("--profile-setups", type=int, default=0,
+                    help="counter-run mode: K set-up + solve passes of the 64^3 headline "
+                         "workload (mixed) with the inversion schedule fixed to the one the "
+                         "autotuner keeps there (look-ahead, 128 x 128 super-tiles), one line "
+                         "of text, no benchmark line")
     ap.add_argument("--blocks", default="main,adjoint32,elasticity48,poisson256",
                     help="comma list of what to run: main (the 64^3 diffusion line), adjoint32, "
                          "elasticity48, poisson256; without main only the chosen blocks are run "
@@ -311,6 +316,24 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if a.profile_setups > 0:
+        p = config_problem("diffusion64", seed=a.seed)
+        rp, ci, v = p.csr_arrays()
+        d = [torch.as_tensor(t, device=dev) for t in
+             (rp, ci, v, p.parent.astype(np.int32), p.dof_node.astype(np.int32))]
+        b = torch.as_tensor(np.ascontiguousarray(p.b[:, 0]), device=dev)
+        its = []
+        t0 = time.perf_counter()
+        for _ in range(a.profile_setups):
+            h = RSD(*d, autotune=False, **MIXED)
+            _, st, info = h.solve(b, rtol=1e-10, restart=30, maxit=1000)
+            its.append(info[0]["iterations"])
+            h.close()
+        torch.cuda.synchronize()
+        print(f"profile-setups: {a.profile_setups} set-up + solve passes, "
+              f"{1e3 * (time.perf_counter() - t0) / a.profile_setups:.1f} ms each, "
+              f"iterations {its}", flush=True)
+        return
     if "main" not in a.blocks.split(","):
         blocks = set(a.blocks.split(","))
         out = {"adjoint32": bench_adjoint(a, dev) if "adjoint32" in blocks else None,
@@ -432,22 +455,22 @@ def main():
         per_launch = potrf_flops(sizes) / nl
         executed = update_flops(sizes) / nl
         peak = PEAK["fp32_TFLOPs"] if fp32 else PEAK["fp64_TFLOPs"]
-        roof = dict(kernel=("k_sweep_update2 (sub-domain batch)" if dom == "leaf_update"
-                            else "k_sweep_update2<double> (root interface)"),
+        roof = dict(kernel=("k_sweep_update_bf3s / k_sweep_update2 (sub-domain batch)"
+                            if dom == "leaf_update" else "k_sweep_update2<double> (root interface)"),
                     bound="mfma", achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s",
                     work_unit="n^3/3 flops per matrix (Cholesky-equivalent) over the "
                               "inversion's update launches",
                     executed_TFLOPs=executed / dur / 1e12,
                     executed_frac=executed / dur / 1e12 / peak,
-                    profile_key="k_sweep_update2<%s, %d>" % ("float" if fp32 else "double",
-                                                             group_tiles(max(sizes))))
+                    profile_key=("k_sweep_update_bf3s<%d>" % group_tiles(max(sizes)) if fp32
+                                 else "k_sweep_update2<double, %d>" % group_tiles(max(sizes))))
     else:
         es = 4 if fp32_leaf else 8
         per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
         dur = ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3
         roof = dict(kernel="k_symv1+k_symv2 (sub-domain batch)", bound="hbm",
                     achieved=per_launch / dur / 1e9, peak=PEAK["hbm_GBps"], unit="GB/s",
-                    profile_key="k_symv1<%s>" % ("float" if fp32_leaf else "double"))
+                    profile_key="k_symv1<%s, 1, false>" % ("float" if fp32_leaf else "double"))
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["avg_launch_ms"] = dur * 1e3
     roof["traffic"] = measured_traffic(roof.pop("profile_key"))
