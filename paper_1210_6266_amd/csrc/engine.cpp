@@ -1302,8 +1302,10 @@ void ensure_krylov(rsd_ctx* h, int m, int nr) {
   h->scal = dalloc<double>(h, 16 * r);
   h->bint = dalloc<double>(h, n * r);
   h->xint = dalloc<double>(h, n * r);
-  h->hhost_block = palloc(h, sizeof(double) * size_t(m + 16) * r);
+  h->hhost_block = palloc(h, sizeof(double) * (3 * size_t(m + 2) + 16) * r);
   h->hhost = static_cast<double*>(h->hhost_block.p);
+  for (hipEvent_t& e : h->ev_h)
+    if (!e) hip_check(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
   h->kry_m = m;
   h->kry_nr = nr;
 }
@@ -1347,6 +1349,7 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
   double* W = h->w;
   struct Rhs {
     double bnorm = 0, tol = 0, beta = 0;
+    double g_prev = 0;                   // residual estimate before the last step
     int its = 0, k = 0;
     bool done = false, stop = false, bad = false;
     std::vector<double> H, cs, sn, g, y;
@@ -1421,18 +1424,27 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
       q.k = 0;
       q.stop = q.bad = false;
     }
-    for (int j = 0; j < m; ++j) {
-      if (!range(true, &lo, &hi)) break;
-      const int nv = hi - lo;
-      const double* Vb = h->V + lo * n;                 // column 0 of right-hand side lo
-      double* Wb = W + lo * n;
-      apply_vectors(h, nv, h->V + (int64_t(j) * nr + lo) * n, h->Z + (int64_t(j) * nr + lo) * n,
+    // Arnoldi step j on the device: apply, SpMV, classical Gram-Schmidt twice, the new
+    // basis vector, and the Hessenberg columns copied to pinned half j % 2 of hhost.  Step
+    // j + 1 depends only on v_{j+1}, which the device forms, so it is queued before the
+    // host waits for step j's columns (the host's Givens rotations then overlap it),
+    // unless every right-hand side is expected to reach its tolerance at step j (its
+    // residual estimate falling at the rate of the last step).  A step queued ahead that
+    // is not needed is carried along like a stopped right-hand side: nothing reads it.
+    struct Queued { int lo = 0, hi = 0; bool on = false; };
+    Queued qd[2];
+    auto half = [&](int j) { return h->hhost + size_t(nr) * size_t(hs) * size_t(1 + (j & 1)); };
+    auto step = [&](int j, int slo, int shi) {
+      const int nv = shi - slo;
+      const double* Vb = h->V + slo * n;                // column 0 of right-hand side slo
+      double* Wb = W + slo * n;
+      apply_vectors(h, nv, h->V + (int64_t(j) * nr + slo) * n, h->Z + (int64_t(j) * nr + slo) * n,
                     s);
-      core_spmv(h, nv, h->Z + (int64_t(j) * nr + lo) * n, nullptr, 1.0, Wb, s);
+      core_spmv(h, nv, h->Z + (int64_t(j) * nr + slo) * n, nullptr, 1.0, Wb, s);
       {
         Timer tm(h, RSD_T_KRYLOV, s);
-        double* hd = h->hdev + lo * hs;
-        double* td = h->tmp + lo * hs;
+        double* hd = h->hdev + slo * hs;
+        double* td = h->tmp + slo * hs;
         // classical Gram-Schmidt, twice
         hip_check(h, launch_mdot(nv, Vb, ldV, n, j + 1, Wb, n, n, h->part, hd, hs, 0, s),
                   "cgs dots");
@@ -1446,17 +1458,36 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
         hip_check(h, launch_mdot(nv, Wb, n, n, 1, Wb, n, n, h->part, hd + j + 1, hs, 1, s),
                   "norm");
         hip_check(h, launch_scale_div(nv, Wb, n, hd + j + 1, hs,
-                                      h->V + (int64_t(j + 1) * nr + lo) * n, n, n, s),
+                                      h->V + (int64_t(j + 1) * nr + slo) * n, n, n, s),
                   "normalise");
       }
-      hip_check(h, hipMemcpyAsync(h->hhost, h->hdev + lo * hs, sizeof(double) * size_t(nv * hs),
+      hip_check(h, hipMemcpyAsync(half(j), h->hdev + slo * hs, sizeof(double) * size_t(nv * hs),
                                   hipMemcpyDeviceToHost, s), "h D2H");
-      hip_check(h, hipStreamSynchronize(s), "hipStreamSynchronize");
+      hip_check(h, hipEventRecord(h->ev_h[j & 1], s), "hipEventRecord");
+      qd[j & 1] = {slo, shi, true};
+    };
+    for (int j = 0; j < m; ++j) {
+      if (!range(true, &lo, &hi)) break;
+      if (!qd[j & 1].on) step(j, lo, hi);
+      if (j + 1 < m) {                   // queue step j + 1 ahead?
+        bool ahead = false;
+        for (int i = lo; i < hi; ++i) {
+          const Rhs& q = R[i];
+          if (q.done || q.stop || q.its + 1 >= o.maxit) continue;
+          const double r1 = std::fabs(q.g[j]);
+          const double r0 = j > 0 ? std::fabs(q.g_prev) : 0.0;
+          ahead = ahead || j == 0 || !(r0 > 0.0) || r1 * (r1 / r0) > q.tol;
+        }
+        if (ahead) step(j + 1, lo, hi);
+      }
+      hip_check(h, hipEventSynchronize(h->ev_h[j & 1]), "hipEventSynchronize");
+      const Queued cur = qd[j & 1];
+      qd[j & 1].on = false;
       for (int i = lo; i < hi; ++i) {
         Rhs& q = R[i];
         if (q.done || q.stop) continue;
         double* hc = &q.H[size_t(j) * (m + 1)];
-        const double* src = h->hhost + (i - lo) * hs;
+        const double* src = half(j) + (i - cur.lo) * hs;
         for (int t = 0; t <= j + 1; ++t) {
           hc[t] = src[t];
           if (!(hc[t] == hc[t]) || std::isinf(hc[t])) q.bad = true;
@@ -1476,6 +1507,7 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
         q.sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
         hc[j] = den;
         hc[j + 1] = 0.0;
+        q.g_prev = q.g[j];
         q.g[j + 1] = -q.sn[j] * q.g[j];
         q.g[j] = q.cs[j] * q.g[j];
         ++q.its;
@@ -1483,6 +1515,7 @@ void fgmres_group(rsd_ctx* h, int nr, const double* b, double* x, const rsd_solv
         if (std::fabs(q.g[j + 1]) <= q.tol || q.its >= o.maxit || hnext == 0.0) q.stop = true;
       }
     }
+    qd[0].on = qd[1].on = false;         // (a step queued ahead and not needed)
     // x_i += Z_i y_i with y_i = R_i^{-1} g_i (upper triangular k x k)
     bool any = false;
     for (int i = 0; i < nr; ++i) {
@@ -1843,6 +1876,10 @@ void engine_free(rsd_ctx* h) {
   h->device_bytes = 0;
   pfree(h, h->hhost_block);
   h->hhost = nullptr;
+  for (hipEvent_t& e : h->ev_h) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   pfree(h, h->csr_stage);
   for (Pinned& b : h->held) pfree(h, b);
   h->held.clear();

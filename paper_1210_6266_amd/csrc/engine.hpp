@@ -113,8 +113,9 @@ struct rsd_ctx {
   int kry_m = 0, kry_nr = 0;   // restart length, right-hand sides in lockstep
   double *V = nullptr, *Z = nullptr, *w = nullptr, *hdev = nullptr, *tmp = nullptr,
          *part = nullptr, *scal = nullptr, *bint = nullptr, *xint = nullptr;
-  double* hhost = nullptr;   // pinned (hhost_block)
-  rsd::Pinned hhost_block;
+  double* hhost = nullptr;   // pinned (hhost_block): general use, then two halves that
+  rsd::Pinned hhost_block;   // take the Hessenberg columns of alternate Arnoldi steps
+  hipEvent_t ev_h[2] = {};   // those columns' copies have landed
 
   // timing
   struct Pending { int cls; hipEvent_t a, b; };
