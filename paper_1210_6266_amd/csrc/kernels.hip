@@ -1300,9 +1300,10 @@ __global__ __launch_bounds__(512, 1) void k_sweep_update_bf3w(float* tiles, cons
 // after the previous chunk's products the workgroup splits them and writes the three
 // BF16 parts straight into the MFMA operand layout in LDS ([panel][part][row block]
 // [k-group][row] of 16-byte fragments), so each MFMA operand is one conflict-free 16-byte
-// LDS read.  48 KB of LDS, one stage.
+// LDS read.  48 KB of LDS, one stage; three workgroups per compute unit (168 registers:
+// the LDS stores and operand reads are constant offsets from one base address each).
 template <int G>
-__global__ __launch_bounds__(kBlock, 2) void k_sweep_update_bf3s(float* tiles, const int64_t* tile_off,
+__global__ __launch_bounds__(kBlock, 3) void k_sweep_update_bf3s(float* tiles, const int64_t* tile_off,
                                                               const int32_t* nt_arr, int c0,
                                                               const float* cbuf, const float* bbuf,
                                                               int64_t stride, int64_t per_xcd,
@@ -1392,6 +1393,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update_bf3s(float* tiles, c
       for (int v = 0; v < 4; ++v)
         acc[bi][bj][v] = valid ? At[(16 * bi + li) + (16 * bj + 4 * g + v) * TS] : 0.0f;
   const int ra = 4 * (w >> 1), rbb = 4 * (w & 1);   // the wave's first row block per panel
+  // one base address for this thread's fragment stores and one for the wave's operand
+  // reads; every other position is a constant offset from them
+  bf8* const fw = frag + fidx(0, 0, r >> 4, kq, r & 15);
+  const bf8* const fa = frag + fidx(0, 0, ra, lk, li);
   load(0);
   for (int ch = 0; ch < NCH; ++ch) {
 #pragma unroll
@@ -1401,25 +1406,25 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_update_bf3s(float* tiles, c
       for (int e = 0; e < 8; ++e) x[e] = (u >> 1) == 0 ? -pre[u][e] : pre[u][e];
       bf8 h, md, lo;
       split_bf3(x, h, md, lo);
-      const int pp = u >> 1, q = kq + 2 * (u & 1);
-      frag[fidx(pp, 0, r >> 4, q, r & 15)] = h;
-      frag[fidx(pp, 1, r >> 4, q, r & 15)] = md;
-      frag[fidx(pp, 2, r >> 4, q, r & 15)] = lo;
+      const int pp = u >> 1, dq = 2 * (u & 1);
+      fw[fidx(pp, 0, 0, dq, 0)] = h;
+      fw[fidx(pp, 1, 0, dq, 0)] = md;
+      fw[fidx(pp, 2, 0, dq, 0)] = lo;
     }
     __syncthreads();
     if (ch + 1 < NCH) load(ch + 1);
     bf8 bh[4], bm[4], bl[4];                   // the wave's B_i row blocks (negated)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      bh[q] = frag[fidx(0, 0, ra + q, lk, li)];
-      bm[q] = frag[fidx(0, 1, ra + q, lk, li)];
-      bl[q] = frag[fidx(0, 2, ra + q, lk, li)];
+      bh[q] = fa[fidx(0, 0, q, 0, 0)];
+      bm[q] = fa[fidx(0, 1, q, 0, 0)];
+      bl[q] = fa[fidx(0, 2, q, 0, 0)];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {              // C row block j
-      const bf8 chh = frag[fidx(1, 0, rbb + j, lk, li)];
-      const bf8 cmm = frag[fidx(1, 1, rbb + j, lk, li)];
-      const bf8 cll = frag[fidx(1, 2, rbb + j, lk, li)];
+      const bf8 chh = fa[fidx(1, 0, rbb - ra + j, 0, 0)];
+      const bf8 cmm = fa[fidx(1, 1, rbb - ra + j, 0, 0)];
+      const bf8 cll = fa[fidx(1, 2, rbb - ra + j, 0, 0)];
 #define RSD_BF3S_TERM(CA, BB)                                                                   \
   _Pragma("unroll") for (int q = 0; q < 4; ++q)                                                 \
       acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CA, BB[q], acc[q][j], 0, 0, 0);
