@@ -939,12 +939,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update(T* tiles, const int64_t
 // C_j (128 x 128) stream through double-buffered, bank-padded LDS in k-chunks.
 // Super-tile ids are spread so that each XCD (every 8th workgroup) owns a
 // contiguous range, i.e. shares the panels of a few super-rows in its L2.
+// KC k-rows per LDS chunk, LD padded k-row length, NS ring stages, minb(G) workgroups per
+// compute unit: FP64 in four-tile groups runs three (4-deep chunks, 37 KB of LDS, at most
+// 168 registers), the rest two.
 template <typename T>
 struct Upd2Cfg;
 template <>
-struct Upd2Cfg<double> { static constexpr int KC = 8, LD = 144, NS = 4; };
+struct Upd2Cfg<double> {
+  static constexpr int KC = 4, LD = 144, NS = 4;
+  static constexpr int minb(int g) { return g >= 4 ? 3 : 2; }
+};
 template <>
-struct Upd2Cfg<float> { static constexpr int KC = 8, LD = 144, NS = 4; };
+struct Upd2Cfg<float> {
+  static constexpr int KC = 8, LD = 144, NS = 4;
+  static constexpr int minb(int) { return 2; }
+};
 
 // s_waitcnt for vmcnt <= N (expcnt and lgkmcnt unconstrained; gfx9 field layout)
 template <int N>
@@ -972,7 +981,7 @@ __device__ __forceinline__ void wait_ring(int younger) {
 }
 
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock, 2) void k_sweep_update2(T* tiles, const int64_t* tile_off,
+__global__ __launch_bounds__(kBlock, Upd2Cfg<T>::minb(G)) void k_sweep_update2(T* tiles, const int64_t* tile_off,
                                                           const int32_t* nt_arr, int c0,
                                                           const T* cbuf, const T* bbuf,
                                                           int64_t stride, int64_t per_xcd,
@@ -1300,10 +1309,11 @@ __global__ __launch_bounds__(512, 1) void k_sweep_update_bf3w(float* tiles, cons
 // after the previous chunk's products the workgroup splits them and writes the three
 // BF16 parts straight into the MFMA operand layout in LDS ([panel][part][row block]
 // [k-group][row] of 16-byte fragments), so each MFMA operand is one conflict-free 16-byte
-// LDS read.  48 KB of LDS, one stage; three workgroups per compute unit (168 registers:
-// the LDS stores and operand reads are constant offsets from one base address each).
+// LDS read.  48 KB of LDS, one stage; three workgroups per compute unit in four-tile
+// groups (168 registers: the LDS stores and operand reads are constant offsets from one
+// base address each), two in two-tile groups.
 template <int G>
-__global__ __launch_bounds__(kBlock, 3) void k_sweep_update_bf3s(float* tiles, const int64_t* tile_off,
+__global__ __launch_bounds__(kBlock, G >= 4 ? 3 : 2) void k_sweep_update_bf3s(float* tiles, const int64_t* tile_off,
                                                               const int32_t* nt_arr, int c0,
                                                               const float* cbuf, const float* bbuf,
                                                               int64_t stride, int64_t per_xcd,
