@@ -776,24 +776,35 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel(const T* tiles, const in
 
 // (2') panel for two- and four-tile groups: B_i = C_i P with C_i (64 x PB) and the
 // rows of P (= its columns: P is symmetric) streamed through double-buffered LDS in
-// k-chunks; wave w owns output column block w (64 x 64, 16 MFMA accumulators).
+// k-chunks; wave w owns output columns ob .. ob + NB - 1 (64 x NB, NB / 4 MFMA
+// accumulators).  FP32: NB = 64, one workgroup per row tile.  FP64: NB = 32, a workgroup
+// per 128 output columns (two per row tile in four-tile groups): its waves then need at
+// most 166 registers, so that a workgroup starts in the place of any one finished
+// workgroup of a running FP64 update (a 64-column FP64 wave needs 192 and waited for two).
 template <typename T>
 struct PanelCfg;
 template <>
-struct PanelCfg<double> { static constexpr int KC = 8; };
+struct PanelCfg<double> { static constexpr int KC = 8, NB = 32; };
 template <>
-struct PanelCfg<float> { static constexpr int KC = 16; };
+struct PanelCfg<float> { static constexpr int KC = 16, NB = 64; };
+// workgroups of k_sweep_panel2 per row tile
+template <typename T>
+constexpr int panel_wgs(int G) {
+  return G * TS > 4 * PanelCfg<T>::NB ? G * TS / (4 * PanelCfg<T>::NB) : 1;
+}
 
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const int64_t* tile_off,
                                                          const int32_t* nt_arr, int c0,
                                                          const T* pbuf, T* cbuf, T* bbuf,
                                                          int64_t stride) {
-  constexpr int PB = G * TS, KC = PanelCfg<T>::KC, NCH = PB / KC;
-  constexpr int LDC = TS + 16, LDP = PB + 16;         // padded LDS rows (bank-spread)
-  constexpr int NC = KC * TS / kBlock, NP = KC * PB / kBlock;   // loads per thread and chunk
+  constexpr int PB = G * TS, KC = PanelCfg<T>::KC, NCH = PB / KC, NB = PanelCfg<T>::NB;
+  constexpr int NWG = panel_wgs<T>(G), WC = PB / NWG;  // output columns per workgroup
+  constexpr int LDC = TS + 16, LDP = WC + 16;         // padded LDS rows (bank-spread)
+  constexpr int NC = KC * TS / kBlock, NP = KC * WC / kBlock;   // loads per thread and chunk
+  static_assert(WC <= 4 * NB && WC % NB == 0, "panel columns per workgroup");
   __builtin_amdgcn_s_setprio(3);               // critical path, as the pivot
-  const int m = blockIdx.y, i = blockIdx.x;
+  const int m = blockIdx.y, i = blockIdx.x / NWG, hb = blockIdx.x % NWG;
   const int nt = nt_arr[m];
   if (c0 >= nt || i >= nt) return;
   const int g = min(G, nt - c0);
@@ -801,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
   const T* base = tiles + tile_off[m];
   T* Cout = cbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
   T* Bout = bbuf + int64_t(m) * stride + int64_t(i) * TS * PB;
-  const T* P = pbuf + int64_t(m) * PB * PB;
+  const T* P = pbuf + int64_t(m) * PB * PB + hb * WC;
   __shared__ T sC[2][KC * LDC], sP[2][KC * LDP];
   T rc[NC], rp[NP];
   auto gload = [&](int ch) {
@@ -819,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int e = threadIdx.x + u * kBlock;
-      const int c = e % PB, kk = e / PB;
+      const int c = e % WC, kk = e / WC;
       rp[u] = P[c + int64_t(ch * KC + kk) * PB];
     }
   };
@@ -829,22 +840,24 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
       const int e = threadIdx.x + u * kBlock;
       const int r = e % TS, kk = e / TS;
       sC[buf][kk * LDC + r] = rc[u];
-      Cout[r + int64_t(ch * KC + kk) * TS] = rc[u];
+      if (hb == 0) Cout[r + int64_t(ch * KC + kk) * TS] = rc[u];
     }
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int e = threadIdx.x + u * kBlock;
-      sP[buf][(e / PB) * LDP + (e % PB)] = rp[u];
+      sP[buf][(e / WC) * LDP + (e % WC)] = rp[u];
     }
   };
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  typename Mfma<T>::v4 acc[4][4];
+  constexpr int NJ = NB / 16;                  // accumulator columns per wave
+  typename Mfma<T>::v4 acc[4][NJ];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
-  const bool active = w < G;
-  const int ob = 64 * (active ? w : 0);
+    for (int bj = 0; bj < NJ; ++bj) acc[bi][bj] = typename Mfma<T>::v4{0, 0, 0, 0};
+  const bool active = NB * w < WC;
+  const int ol = NB * (active ? w : 0);        // the wave's first column in the workgroup's
+  const int ob = hb * WC + ol;                 // and in the panel
   gload(0);
   sstore(0, 0);
   __syncthreads();
@@ -855,16 +868,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
     if (active) {
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
-        T a[4], b[4];
+        T a[4], b[NJ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = C_[(kk + lk) * LDC + 16 * q + li];
-          b[q] = P_[(kk + lk) * LDP + ob + 16 * q + li];
-        }
+        for (int q = 0; q < 4; ++q) a[q] = C_[(kk + lk) * LDC + 16 * q + li];
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) b[q] = P_[(kk + lk) * LDP + ol + 16 * q + li];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
+          for (int bj = 0; bj < NJ; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], b[bj], acc[bi][bj]);
       }
     }
     if (ch + 1 < NCH) sstore(ch + 1, (ch + 1) & 1);
@@ -874,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_panel2(const T* tiles, const i
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < NJ; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         Bout[acc_row64<T>(bi, v) + int64_t(ob + 16 * bj + li) * TS] = acc[bi][bj][v];
@@ -1123,6 +1135,96 @@ __global__ __launch_bounds__(kBlock, Upd2Cfg<T>::minb(G)) void k_sweep_update2(T
     for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) At[(16 * bi + li) + acc_col(bj, v) * TS] = acc[bi][bj][v];
+}
+
+// (3f) the look-ahead part of a step (the next group's tile rows and columns) for batches
+// of few matrices, whose 128 x 128 super-tiles leave most compute units idle while the
+// part runs alone on the critical path: one workgroup per 64 x 64 tile, each wave a
+// 32 x 32 quadrant.  Every tile element receives the MFMA products of k_sweep_update2 in
+// the same order (same instruction, operands and k-steps), so the results are the same
+// bits.  The operand rows of the tile pair stream through a double-buffered LDS area,
+// staged in registers one chunk ahead.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep_update_la(T* tiles, const int64_t* tile_off,
+                                                         const int32_t* nt_arr, int c0,
+                                                         const T* cbuf, const T* bbuf,
+                                                         int64_t stride) {
+  constexpr int PB = G * TS, KC = 16, NCH = PB / KC;
+  constexpr int LDF = TS + 16;                 // padded k-row (conflict-free 8-byte reads)
+  const int m = blockIdx.y, t = blockIdx.x / G, x = c0 + G + int(blockIdx.x % G);
+  const int nt = nt_arr[m];
+  if (x >= nt || t >= nt) return;
+  if (t >= c0 + G && t < c0 + 2 * G && t > x) return;   // counted as (t, x)
+  T* base = tiles + tile_off[m];
+  const T* Bb = bbuf + int64_t(m) * stride;
+  const T* Cb = cbuf + int64_t(m) * stride;
+  if (t >= c0 && t < c0 + G) {                 // pivot-group column: A_xt <- B_x[:, t block]
+    T* A = base + tile_index(x, t) * TT;
+    const T* Bx = Bb + int64_t(x) * TS * PB + int64_t(t - c0) * TS * TS;
+    for (int e = threadIdx.x; e < TT; e += kBlock) A[e] = Bx[e];
+    return;
+  }
+  const int I = x > t ? x : t, J = x > t ? t : x;
+  T* A = base + tile_index(I, J) * TT;
+  const T* gB = Bb + int64_t(I) * TS * PB;     // rows of B_I, k-major
+  const T* gC = Cb + int64_t(J) * TS * PB;     // rows of C_J
+  __shared__ T sB[2][KC * LDF], sC[2][KC * LDF];
+  const int r = threadIdx.x % TS, kq = threadIdx.x / TS;
+  T rb[KC / 4], rc[KC / 4];
+  auto gload = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < KC / 4; ++u) {
+      const int k = ch * KC + kq + 4 * u;
+      rb[u] = gB[r + int64_t(k) * TS];
+      rc[u] = gC[r + int64_t(k) * TS];
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < KC / 4; ++u) {
+      sB[buf][(kq + 4 * u) * LDF + r] = rb[u];
+      sC[buf][(kq + 4 * u) * LDF + r] = rc[u];
+    }
+  };
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int qr = 32 * (w >> 1), qc = 32 * (w & 1);
+  auto acc_col = [&](int bj, int v) { return 16 * bj + ((sizeof(T) == 8) ? 4 * v + g : 4 * g + v); };
+  typename Mfma<T>::v4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[(qr + 16 * bi + li) + (qc + acc_col(bj, v)) * TS];
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (ch + 1 < NCH) gload(ch + 1);
+    const T* B_ = sB[ch & 1];
+    const T* C_ = sC[ch & 1];
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = -B_[(kk + g) * LDF + qr + 16 * q + li];
+        b[q] = C_[(kk + g) * LDF + qc + 16 * q + li];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::op(b[bj], a[bi], acc[bi][bj]);
+    }
+    if (ch + 1 < NCH) sstore((ch + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(qr + 16 * bi + li) + (qc + acc_col(bj, v)) * TS] = acc[bi][bj][v];
 }
 
 // (3'') the update of an FP32 batch on the BF16 matrix cores.  Same super-tiles, XCD
@@ -2633,6 +2735,10 @@ size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, si
   return *pbytes + 2 * *cbytes;
 }
 
+// FP64 look-ahead parts use k_sweep_update_la (a workgroup per tile) while the batch has
+// at most this many 128 x 128 super-tiles in the next group's rows and columns
+constexpr int64_t kFineLookAhead = 1024;
+
 hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, void* cbuf,
                              void* bbuf, int32_t* flags, int group, hipStream_t s, int part) {
   if (b.count == 0 || b.max_nt == 0) return hipSuccess;
@@ -2672,11 +2778,16 @@ hipError_t launch_sweep_step(const DevBatch& b, int c0, int stage, void* pbuf, v
       k_sweep_pivot_blk<T, G><<<b.count, PivCfg<T>::threads, 0, s>>>(                          \
           (T*)b.tiles, b.tile_off, b.nt, c0, (T*)pbuf, flags);                                  \
     else if (stage == 1 && G >= 2)                                                              \
-      k_sweep_panel2<T, (G >= 2 ? G : 2)><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(           \
+      k_sweep_panel2<T, (G >= 2 ? G : 2)><<<dim3(b.max_nt * panel_wgs<T>(G), b.count), kBlock, 0, s>>>( \
           (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
     else if (stage == 1)                                                                        \
       k_sweep_panel<T, G><<<dim3(b.max_nt, b.count), kBlock, 0, s>>>(                           \
           (const T*)b.tiles, b.tile_off, b.nt, c0, (const T*)pbuf, (T*)cbuf, (T*)bbuf, stride); \
+    else if (G >= 2 && part == 1 && sizeof(T) == 8 &&                                         \
+             int64_t(b.count) * ((b.max_nt + 1) / 2) * (G / 2) <= kFineLookAhead)               \
+      k_sweep_update_la<T, (G >= 2 ? G : 2)><<<dim3(unsigned(b.max_nt * G), b.count), kBlock, 0, \
+                                               s>>>((T*)b.tiles, b.tile_off, b.nt, c0,          \
+                                                    (const T*)cbuf, (const T*)bbuf, stride);    \
     else if (G >= 2) {                                                                          \
       const int64_t nsb = (b.max_nt + 1) / 2, ns = nsb * (nsb + 1) / 2;                         \
       const bool major = part != 1 && b.count >= 8;                                             \
