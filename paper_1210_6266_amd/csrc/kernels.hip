@@ -1143,7 +1143,7 @@ __global__ __launch_bounds__(kBlock, Upd2Cfg<T>::minb(G)) void k_sweep_update2(T
 // 32 x 32 quadrant.  Every tile element receives the MFMA products of k_sweep_update2 in
 // the same order (same instruction, operands and k-steps), so the results are the same
 // bits.  The operand rows of the tile pair stream through a double-buffered LDS area,
-// staged in registers one chunk ahead.
+// staged in registers two chunks ahead.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_sweep_update_la(T* tiles, const int64_t* tile_off,
                                                          const int32_t* nt_arr, int c0,
@@ -1170,20 +1170,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update_la(T* tiles, const int6
   const T* gC = Cb + int64_t(J) * TS * PB;     // rows of C_J
   __shared__ T sB[2][KC * LDF], sC[2][KC * LDF];
   const int r = threadIdx.x % TS, kq = threadIdx.x / TS;
-  T rb[KC / 4], rc[KC / 4];
-  auto gload = [&](int ch) {
+  T rb[2][KC / 4], rc[2][KC / 4];              // two chunks in flight: [chunk % 2]
+  auto gload = [&](int ch, T (&pb)[KC / 4], T (&pc)[KC / 4]) {
 #pragma unroll
     for (int u = 0; u < KC / 4; ++u) {
       const int k = ch * KC + kq + 4 * u;
-      rb[u] = gB[r + int64_t(k) * TS];
-      rc[u] = gC[r + int64_t(k) * TS];
+      pb[u] = gB[r + int64_t(k) * TS];
+      pc[u] = gC[r + int64_t(k) * TS];
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const T (&pb)[KC / 4], const T (&pc)[KC / 4]) {
 #pragma unroll
     for (int u = 0; u < KC / 4; ++u) {
-      sB[buf][(kq + 4 * u) * LDF + r] = rb[u];
-      sC[buf][(kq + 4 * u) * LDF + r] = rc[u];
+      sB[buf][(kq + 4 * u) * LDF + r] = pb[u];
+      sC[buf][(kq + 4 * u) * LDF + r] = pc[u];
     }
   };
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
@@ -1196,11 +1196,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update_la(T* tiles, const int6
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[(qr + 16 * bi + li) + (qc + acc_col(bj, v)) * TS];
-  gload(0);
-  sstore(0);
+  static_assert(NCH % 2 == 0 && NCH >= 2, "chunks are taken in pairs");
+  gload(0, rb[0], rc[0]);
+  gload(1, rb[1], rc[1]);
+  sstore(0, rb[0], rc[0]);
   __syncthreads();
-  for (int ch = 0; ch < NCH; ++ch) {
-    if (ch + 1 < NCH) gload(ch + 1);
+  // chunk ch is in LDS buffer ch % 2 and chunk ch + 1 in registers p (set ch % 2 ^ 1);
+  // the registers of chunk ch (set ch % 2) take chunk ch + 2
+  auto step = [&](int ch, T (&pb)[KC / 4], T (&pc)[KC / 4], T (&nb)[KC / 4], T (&nc)[KC / 4]) {
+    if (ch + 2 < NCH) gload(ch + 2, pb, pc);
     const T* B_ = sB[ch & 1];
     const T* C_ = sC[ch & 1];
 #pragma unroll
@@ -1216,8 +1220,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_update_la(T* tiles, const int6
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::op(b[bj], a[bi], acc[bi][bj]);
     }
-    if (ch + 1 < NCH) sstore((ch + 1) & 1);
+    if (ch + 1 < NCH) sstore((ch + 1) & 1, nb, nc);
     __syncthreads();
+  };
+  for (int ch = 0; ch < NCH; ch += 2) {
+    step(ch, rb[0], rc[0], rb[1], rc[1]);
+    step(ch + 1, rb[1], rc[1], rb[0], rc[0]);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
