@@ -456,14 +456,16 @@ def main():
         executed = update_flops(sizes) / nl
         peak = PEAK["fp32_TFLOPs"] if fp32 else PEAK["fp64_TFLOPs"]
         roof = dict(kernel=("k_sweep_update_bf3s / k_sweep_update2 (sub-domain batch)"
-                            if dom == "leaf_update" else "k_sweep_update2<double> (root interface)"),
+                            if dom == "leaf_update" else
+                            "k_sweep_update2<double> + k_sweep_update_la<double> (root interface: "
+                            "bulk and look-ahead launches of each step)"),
                     bound="mfma", achieved=per_launch / dur / 1e12, peak=peak, unit="TFLOP/s",
                     work_unit="n^3/3 flops per matrix (Cholesky-equivalent) over the "
                               "inversion's update launches",
                     executed_TFLOPs=executed / dur / 1e12,
                     executed_frac=executed / dur / 1e12 / peak,
                     profile_key=("k_sweep_update_bf3s<%d>" % group_tiles(max(sizes)) if fp32
-                                 else "k_sweep_update2<double, %d>" % group_tiles(max(sizes))))
+                                 else "root_update"))
     else:
         es = 4 if fp32_leaf else 8
         per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
