@@ -543,6 +543,8 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     // auxiliary stream (the handle's own, default priority), events of the inversion
     // look-ahead and of the ordering between calls
     h->aux = take_aux(h);
+    h->upl = take_aux(h);
+    hip_check(h, hipEventCreateWithFlags(&h->ev_upl, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming), "hipEventCreate");
@@ -705,8 +707,9 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
 }
 
 // The second part of the analysis (build_plan_couplings: per-leaf coupling blocks, adjacency,
-// Sigma layout and apply schedule) and its upload, queued on s.  A set-up runs it after
-// queueing the sub-domain inversions, so the host work overlaps them.
+// Sigma layout and apply schedule) and its upload, for the kernels queued on s after it.  A
+// set-up runs it after queueing the sub-domain inversions, so that the host work and the
+// copy overlap them.
 void upload_couplings(rsd_ctx* h, hipStream_t s) {
   if (h->couplings_on_device) return;          // a refresh of the values: same structure
   const Plan& P = h->P;
@@ -794,7 +797,11 @@ void upload_couplings(rsd_ctx* h, hipStream_t s) {
     items(P.level_sigma[q], false, &deep[q], &h->lev_items[q]);
     if (h->gam_level[q]) items(P.level_sigma_own[q], true, &own[q], &h->lev_own_items[q]);
   }
-  up.commit(h, s);
+  // the copy runs on the upload stream while s still inverts the sub-domains (queued on s
+  // it would wait for them); s waits for it before the first kernel that reads the arrays
+  up.commit(h, h->upl);
+  hip_check(h, hipEventRecord(h->ev_upl, h->upl), "hipEventRecord");
+  hip_check(h, hipStreamWaitEvent(s, h->ev_upl, 0), "hipStreamWaitEvent");
   h->held.push_back(up.stage);                 // released after the set-up's final sync
   up.stage = Pinned();
   a.B_off = h->B_off;
@@ -1860,11 +1867,18 @@ void engine_free(rsd_ctx* h) {
   h->pool.clear();
   if (h->ev_main) (void)hipEventDestroy(h->ev_main);
   if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
+  if (h->ev_upl) (void)hipEventDestroy(h->ev_upl);
+  h->ev_upl = nullptr;
   if (h->ev_last) (void)hipEventDestroy(h->ev_last);
   h->ev_main = h->ev_aux = h->ev_last = nullptr;
   h->has_last = false;
   if (h->aux) give_aux(h->device, h->aux);   // idle: its work was joined and completed
   h->aux = nullptr;
+  if (h->upl) {                                // (its one copy was joined onto the set-up's
+    (void)hipStreamSynchronize(h->upl);        // stream; a failed set-up may have stopped
+    give_aux(h->device, h->upl);               // before that wait)
+  }
+  h->upl = nullptr;
   BlockCache& c = cache_of(h->device);
   for (auto& p : h->allocs) {                                           // work is complete
     if (h->opt.dev_free)
