@@ -54,9 +54,10 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    # (the library's set-up autotuner times up to four inversion schedules per batch shape
-    # on the first set-ups of a process: the warm-up steps cover them)
-    ap.add_argument("--warmup", type=int, default=4)
+    # (the library's set-up autotuner times up to four inversion schedules per batch shape,
+    # the first of them twice, on the first five set-ups of a process: the warm-up steps
+    # cover them)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--reuse-solves", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -400,8 +400,10 @@ void invert_batch(rsd_ctx* h, const DevBatch& b, void* pbuf, void* cbuf[2], void
 // update); for BF16-split batches in four-tile groups also 2 / 3, the same with 256 x 256
 // update super-tiles.  The first set-ups of a batch shape in the process try the candidates
 // in turn, each timed with HIP events around the batch's inversion (read back after the
-// set-up's final synchronisation); once all are timed the fastest is kept for the shape (a
-// tie keeps the lower index).  With rsd_options.autotune = 0, candidate 0 throughout.
+// set-up's final synchronisation), and then candidate 0 once more: its first timing comes
+// from the process's first set-up, slowed by cold caches and first-use costs.  With every
+// candidate timed (candidate 0 by the faster of its two) the fastest is kept for the shape
+// (a tie keeps the lower index).  With rsd_options.autotune = 0, candidate 0 throughout.
 struct InvTune {
   std::vector<float> ms;
   int32_t best = -1;
@@ -433,15 +435,17 @@ int inv_pick(rsd_ctx* h, const std::string& key, int ncand, bool* tuning) {
   if (t.best >= 0) return t.best;
   if (!h->opt.autotune) return 0;
   *tuning = true;
-  return int(t.ms.size());
+  return int(t.ms.size()) % ncand;      // 0, 1, ..., ncand - 1, then 0 again
 }
 
 void inv_record(const std::string& key, int ncand, int cand, float ms) {
   std::lock_guard<std::mutex> lk(g_inv_mu);
   InvTune& t = g_inv[key];
-  if (t.best >= 0 || int(t.ms.size()) != cand) return;   // another handle timed it first
+  // another handle timed this candidate first
+  if (t.best >= 0 || int(t.ms.size()) % ncand != cand) return;
   t.ms.push_back(ms);
-  if (int(t.ms.size()) == ncand) {
+  if (int(t.ms.size()) == ncand + 1) {
+    t.ms[0] = std::min(t.ms[0], t.ms[size_t(ncand)]);
     t.best = 0;
     for (int c = 1; c < ncand; ++c)
       if (t.ms[size_t(c)] < t.ms[size_t(t.best)]) t.best = c;
@@ -545,6 +549,10 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
     h->aux = take_aux(h);
     h->upl = take_aux(h);
     hip_check(h, hipEventCreateWithFlags(&h->ev_upl, hipEventDisableTiming), "hipEventCreate");
+    hip_check(h, hipEventCreateWithFlags(&h->ev_sig, hipEventDisableTiming), "hipEventCreate");
+    h->ev_lev.assign(h->P.level_depth.size(), nullptr);
+    for (hipEvent_t& e : h->ev_lev)
+      hip_check(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_aux, hipEventDisableTiming), "hipEventCreate");
     hip_check(h, hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming), "hipEventCreate");
@@ -910,20 +918,31 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
                                  h->leaf_elems, h->leaf_apply.half, s), "16-bit leaf copy");
     }
     int32_t* iflags = h->flags + P.leaf_node.size();
+    // Every dense level's S~ depends only on K and the Sigma blocks: the assemblies run on
+    // the upload stream, deepest level first, while s inverts the deeper levels (the
+    // inversion of a few interfaces leaves most compute units idle between its pivots).
+    hip_check(h, hipEventRecord(h->ev_sig, s), "hipEventRecord");
+    hip_check(h, hipStreamWaitEvent(h->upl, h->ev_sig, 0), "hipStreamWaitEvent");
     for (size_t q = 0; q < h->lev.size(); ++q) {
       if (h->gam_level[q]) continue;   // S~ is applied matrix-free (Alg. 1), never formed
+      hipStream_t u = h->upl;
       {
-        Timer tm(h, RSD_T_IFACE_ASSEMBLY, s);
+        Timer tm(h, RSD_T_IFACE_ASSEMBLY, u);
         int32_t maxn = 0;
         for (int32_t v : P.level_batch[q].n) maxn = std::max(maxn, v);
-        hip_check(h, launch_sym_fill(h->lev[q], s), "iface fill");
-        hip_check(h, launch_sym_extract(h->lev[q], h->segB, h->segC, h->pcol, h->pval, maxn, s),
+        hip_check(h, launch_sym_fill(h->lev[q], u), "iface fill");
+        hip_check(h, launch_sym_extract(h->lev[q], h->segB, h->segC, h->pcol, h->pval, maxn, u),
                   "iface extract");
         hip_check(h, launch_schur_assemble(h->lev[q], h->adj_ptr, h->adj_leaf, h->adj_pos,
                                            h->B_off, h->sig_off_d, h->sigma, h->sigma_fp32,
-                                           P.n_leaf, s),
+                                           P.n_leaf, u),
                   "schur assembly");
       }
+      hip_check(h, hipEventRecord(h->ev_lev[q], u), "hipEventRecord");
+    }
+    for (size_t q = 0; q < h->lev.size(); ++q) {
+      if (h->gam_level[q]) continue;
+      hip_check(h, hipStreamWaitEvent(s, h->ev_lev[q], 0), "hipStreamWaitEvent");
       {
         Timer tm(h, RSD_T_IFACE_INVERSE, s);
         invert(h->lev[q], P.level_batch[q], iflags + P.level_iface_begin[q],
@@ -1868,7 +1887,11 @@ void engine_free(rsd_ctx* h) {
   if (h->ev_main) (void)hipEventDestroy(h->ev_main);
   if (h->ev_aux) (void)hipEventDestroy(h->ev_aux);
   if (h->ev_upl) (void)hipEventDestroy(h->ev_upl);
-  h->ev_upl = nullptr;
+  if (h->ev_sig) (void)hipEventDestroy(h->ev_sig);
+  h->ev_upl = h->ev_sig = nullptr;
+  for (hipEvent_t& e : h->ev_lev)
+    if (e) (void)hipEventDestroy(e);
+  h->ev_lev.clear();
   if (h->ev_last) (void)hipEventDestroy(h->ev_last);
   h->ev_main = h->ev_aux = h->ev_last = nullptr;
   h->has_last = false;

@@ -72,8 +72,10 @@ struct rsd_ctx {
   int32_t* flags = nullptr;  // one per leaf, then one per interface
   hipStream_t aux = nullptr;          // look-ahead stream of the inversions (held exclusively)
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
-  hipStream_t upl = nullptr;          // the couplings' upload, beside the sub-domain inversion
-  hipEvent_t ev_upl = nullptr;        // (held exclusively, from the same pool as aux)
+  hipStream_t upl = nullptr;          // the couplings' upload, beside the sub-domain inversion,
+  hipEvent_t ev_upl = nullptr;        // and the dense levels' Schur assemblies (held
+  hipEvent_t ev_sig = nullptr;        // exclusively, from the same pool as aux): the Sigma
+  std::vector<hipEvent_t> ev_lev;     // blocks are done / each level's S~ is assembled
   int group = 0;             // pivot tiles per sweep step (0: by batch size)
   int split16 = 0;           // FP32 batches: sweep updates on the BF16 matrix cores (bf16_split)
 
