@@ -45,6 +45,32 @@ FP64 = dict(leaf_prec="fp64", sigma_prec="fp64", iface_prec="fp64", root_prec="f
 TILE = 64
 
 
+def leaf_apply_bytes(p, es):
+    """Algorithmic bytes of one leaf pass of an apply, averaged over its two passes.  The
+    first reads the lower triangle of every sub-domain inverse (es bytes per entry) and
+    16 bytes of vectors per leaf dof; the second (the back-substitution's correction
+    K_ll^{-1} w, w zero outside the leaf's shell, which the library orders last) only the
+    tile rows from the first one that holds shell rows, and 24 bytes per leaf dof (w, the
+    first pass's result and the sum).  The shell: leaf dofs coupled to a dof of another
+    tree node."""
+    K = p.K.tocsr()
+    node = np.asarray(p.dof_node)
+    rows = np.repeat(np.arange(p.n), np.diff(K.indptr))
+    outer = np.bincount(rows[node[K.indices] != node[rows]], minlength=p.n) > 0
+    T = len(p.parent)
+    has_child = np.zeros(T, bool)
+    has_child[np.asarray(p.parent)[1:]] = True
+    n_of = np.bincount(node, minlength=T)
+    s_of = np.bincount(node[outer], minlength=T)
+    full = corr = 0
+    for t in np.nonzero(~has_child)[0]:
+        n, r0 = int(n_of[t]), (int(n_of[t] - s_of[t]) // TILE) * TILE
+        full += n * (n + 1) // 2
+        corr += n * (n + 1) // 2 - r0 * (r0 + 1) // 2
+    nleaf = int(n_of[~has_child].sum())
+    return ((full + corr) * es + (16 + 24) * nleaf) / 2
+
+
 def group_tiles(n):
     """Pivot tiles per sweep step that the library picks for matrices of order n."""
     return 4 if (n + TILE - 1) // TILE >= 16 else 2
@@ -468,8 +494,7 @@ def main():
                     profile_key=("k_sweep_update_bf3s<%d>" % group_tiles(max(sizes)) if fp32
                                  else "root_update"))
     else:
-        es = 4 if fp32_leaf else 8
-        per_launch = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
+        per_launch = leaf_apply_bytes(p, 4 if fp32_leaf else 8)
         dur = ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3
         roof = dict(kernel="k_symv1+k_symv2 (sub-domain batch)", bound="hbm",
                     achieved=per_launch / dur / 1e9, peak=PEAK["hbm_GBps"], unit="GB/s",
@@ -480,8 +505,7 @@ def main():
     # secondary figures (not the roofline object): leaf apply bandwidth, root update rate
     extra = {}
     if R0["launches"].get("leaf_apply"):
-        es = 4 if fp32_leaf else 8
-        lb = sum(n * (n + 1) // 2 for n in leaf_sizes) * es + 2 * ana["leaf_dofs"] * 8
+        lb = leaf_apply_bytes(p, 4 if fp32_leaf else 8)
         extra["leaf_apply_GBps"] = lb / (ms["leaf_apply"] / nlch["leaf_apply"] * 1e-3) / 1e9
     if R0["launches"].get("spmv"):
         # K in internal order: values 8 B + column 4 B per nonzero, row pointers 8 B per

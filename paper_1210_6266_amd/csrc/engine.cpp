@@ -563,8 +563,13 @@ rsd_status engine_init(rsd_ctx* h, const rsd_csr* csr, const rsd_hierarchy* hier
       h->group = (v == 1 || v == 2 || v == 4) ? v : 0;
     }
     h->split16 = h->opt.bf16_split ? 1 : 0;
+    // per leaf, the first tile row that holds shell rows (the leaf's dofs coupled to
+    // interface dofs come last): the back-substitution's correction skips those before it
+    std::vector<int32_t> row0(P.leaf_inner.size());
+    for (size_t l = 0; l < row0.size(); ++l) row0[l] = P.leaf_inner[l] / kTile;
     // ---- upload structure (one allocation, one copy)
     Uploader up;
+    up.add(&h->leaf_row0, row0);
     up.add(&h->prow, P.prow);
     up.add(&h->perm, P.perm);
     up.add(&h->iperm, P.iperm);
@@ -1127,18 +1132,22 @@ void core_apply(rsd_ctx* h, const ApplyWork& wk, int nv, const double* r, double
                   "interface symv");
     }
   }
+  // back-substitution, u_l = K_ll^{-1} (r_l - K_{l,B} u_B).  Symmetric K: the leaf rows of z
+  // still hold K_ll^{-1} r_l from the first leaf pass, so u_l = z_l + K_ll^{-1} w with
+  // w = -K_{l,B} u_B, which is zero outside the leaf's shell (its last rows): the product
+  // skips the tile rows before the shell, whose products with w are zero.
   {
     Timer tm(h, RSD_T_COUPLING, s);
-    // leaf rows: r_l - K_{l,B} u_B
     hip_check(h, launch_ell_spmv(0, nl, h->segA, h->prow + 1, h->prow, h->ell_off, h->ell_col,
-                                 h->ell_val, z, r, -1.0, wk.t, nv, n, wk.xil, nl, n, s),
+                                 h->ell_val, z, h->opt.symmetric ? nullptr : r, -1.0, wk.t, nv,
+                                 n, wk.xil, nl, n, s),
               "back-substitution rhs");
   }
   {
     Timer tm(h, RSD_T_LEAF_APPLY, s);
-    if (h->opt.symmetric)
-      hip_check(h, launch_symv(h->leaf_apply, wk.t, wk.sympart, -1.0, nullptr, z, nv, n, s),
-                "leaf symv");
+    if (h->opt.symmetric)    // tiles hold -K_ll^{-1}
+      hip_check(h, launch_symv(h->leaf_apply, wk.t, wk.sympart, -1.0, z, z, nv, n, s,
+                               h->leaf_row0), "leaf symv (correction)");
     else
       hip_check(h, launch_gen_matvec(h->gen, wk.t, 1.0, z, nv, n, s), "leaf matvec");
   }

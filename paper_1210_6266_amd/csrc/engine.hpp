@@ -65,6 +65,7 @@ struct rsd_ctx {
   rsd::DevBatch leaf{};
   std::vector<rsd::DevBatch> lev;
   rsd::DevBatch leaf_apply;    // the leaf batch as the applies read it (16-bit copy or leaf)
+  int32_t* leaf_row0 = nullptr; // per leaf: its first tile row holding shell rows
   rsd::GenBatch gen;           // symmetric = 0: dense general sub-domain inverses
   int64_t leaf_elems = 0;
   std::vector<rsd::SigmaLevelItems> lev_items;       // Sigma products against deeper levels

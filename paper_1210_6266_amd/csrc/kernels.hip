@@ -1608,7 +1608,7 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
     const int32_t* __restrict__ item_BI, const int32_t* __restrict__ item_BJ,
     const double* __restrict__ x, int64_t ldx, int nv,
     typename SymPart<T>::type* __restrict__ part, int32_t* __restrict__ queue,
-    int64_t num_items) {
+    int64_t num_items, const int32_t* __restrict__ row0) {
   using P = typename SymPart<T>::type;
   constexpr int B = kSymB;
   // elements per load: 16-byte loads of FP64 / FP32, 8-byte loads of 16-bit values
@@ -1633,6 +1633,15 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
     }
     const int m = item_mat[it], BI = item_BI[it], BJ = item_BJ[it];
     const int n = n_arr[m], nt = nt_arr[m];
+    const int r0 = row0 ? row0[m] : 0;         // tile rows below r0 meet only zeros of x
+    if ((BI + 1) * B <= r0) {                  // the whole item: no partial sums (k_symv2
+      if constexpr (PERSIST) {                 // skips them), next item
+        __syncthreads();                       // (s_item read by every thread)
+        continue;
+      } else {
+        return;
+      }
+    }
     const int64_t xo = vec_off[m];
     // thread t: rows q4(v) of the tile (q = t % 16), columns g + 16 u (g = t / 16, u < 4);
     // FP32 and 16-bit: rows 4q .. 4q + 3 (one load per column); FP64: rows 2q, 2q + 1,
@@ -1662,7 +1671,7 @@ __global__ __launch_bounds__(kBlock) void k_symv1(
       for (int k = 0; k < KV; ++k)
         #pragma unroll
         for (int v = 0; v < 4; ++v) ra[k][v] = P(0);
-      if (I < nt) {
+      if (I < nt && I >= r0) {
         // x_I: in registers for FP32 tiles, read from LDS at each use for FP64 tiles
         P xi[kColLds ? 1 : KV][4];
         if constexpr (!kColLds)
@@ -1768,8 +1777,8 @@ template <typename P>
 __global__ __launch_bounds__(kBlock) void k_symv2(
     const int32_t* __restrict__ n_arr, const int32_t* __restrict__ nt_arr,
     const int64_t* __restrict__ vec_off, const int64_t* __restrict__ item_base,
-    const P* __restrict__ part, int kv, double alpha, const double* __restrict__ base,
-    double* __restrict__ y, int64_t ld) {
+    const P* __restrict__ part, int kv, double alpha, const double* base, double* y,
+    int64_t ld, const int32_t* __restrict__ row0) {
   // block (tile row I, matrix m, vector k); the parts of phase 1 hold kv vectors
   constexpr int B = kSymB;
   const int m = blockIdx.y, I = blockIdx.x, k = blockIdx.z, r = threadIdx.x & 63,
@@ -1778,11 +1787,14 @@ __global__ __launch_bounds__(kBlock) void k_symv2(
   if (I >= nt) return;
   const int nb = (nt + B - 1) / B, BI = I / B, b = I % B;
   const int64_t ib = item_base[m];
+  const int r0 = row0 ? row0[m] : 0;           // items of block rows below r0: no parts
   double s = 0.0;
-  for (int BJ = prt; BJ <= BI; BJ += 4)        // row parts of block row BI
-    s += double(part[((2 * (ib + tri(BI) + BJ) * kv + k) * B + b) * TS + r]);
+  if ((BI + 1) * B > r0)
+    for (int BJ = prt; BJ <= BI; BJ += 4)      // row parts of block row BI
+      s += double(part[((2 * (ib + tri(BI) + BJ) * kv + k) * B + b) * TS + r]);
   for (int B2 = BI + prt; B2 < nb; B2 += 4)    // column parts of block column BI
-    s += double(part[(((2 * (ib + tri(B2) + BI) + 1) * kv + k) * B + b) * TS + r]);
+    if ((B2 + 1) * B > r0)
+      s += double(part[(((2 * (ib + tri(B2) + BI) + 1) * kv + k) * B + b) * TS + r]);
   __shared__ double red[4][TS];
   red[prt][r] = s;
   __syncthreads();
@@ -2835,7 +2847,8 @@ unsigned persistent_grid(K kernel, int64_t items) {
 }
 
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
-                       const double* base, double* y, int nv, int64_t ld, hipStream_t s) {
+                       const double* base, double* y, int nv, int64_t ld, hipStream_t s,
+                       const int32_t* row0) {
   if (b.count == 0 || b.num_items == 0 || nv <= 0) return hipSuccess;
   const int kmax = b.vec_pass > 0 ? min(b.vec_pass, symv_vectors(b)) : symv_vectors(b);
   for (int v0 = 0; v0 < nv; v0 += kmax) {
@@ -2849,12 +2862,12 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
     if (b.persist && b.queue)                                                                   \
       k_symv1<T, KV, true><<<persistent_grid(k_symv1<T, KV, true>, b.num_items), kBlock, 0, s>>>( \
           (const T*)b.tiles, b.tile_off, b.n, b.nt, b.vec_off, b.item_mat, b.item_BI,           \
-          b.item_BJ, xb, ld, c, (typename SymPart<T>::type*)part, b.queue, b.num_items);        \
+          b.item_BJ, xb, ld, c, (typename SymPart<T>::type*)part, b.queue, b.num_items, row0);  \
     else                                                                                        \
       k_symv1<T, KV><<<b.num_items, kBlock, 0, s>>>((const T*)b.tiles, b.tile_off, b.n, b.nt,   \
                                                     b.vec_off, b.item_mat, b.item_BI, b.item_BJ, \
                                                     xb, ld, c, (typename SymPart<T>::type*)part, \
-                                                    nullptr, b.num_items);                      \
+                                                    nullptr, b.num_items, row0);                \
   } while (0)
     if (b.half) {
       if (b.half == 1) {
@@ -2863,15 +2876,15 @@ hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double al
         if (kv == 1) RSD_SYMV(__bf16, 1); else if (kv == 2) RSD_SYMV(__bf16, 2); else RSD_SYMV(__bf16, 4);
       }
       k_symv2<float><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
-          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld);
+          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld, row0);
     } else if (b.fp32) {
       if (kv == 1) RSD_SYMV(float, 1); else if (kv == 2) RSD_SYMV(float, 2); else RSD_SYMV(float, 4);
       k_symv2<float><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
-          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld);
+          b.n, b.nt, b.vec_off, b.item_base, (const float*)part, kv, alpha, bb, yb, ld, row0);
     } else {
       if (kv == 1) RSD_SYMV(double, 1); else if (kv == 2) RSD_SYMV(double, 2); else RSD_SYMV(double, 4);
       k_symv2<double><<<dim3(b.max_nt, b.count, c), kBlock, 0, s>>>(
-          b.n, b.nt, b.vec_off, b.item_base, (const double*)part, kv, alpha, bb, yb, ld);
+          b.n, b.nt, b.vec_off, b.item_base, (const double*)part, kv, alpha, bb, yb, ld, row0);
     }
 #undef RSD_SYMV
   }

@@ -93,9 +93,13 @@ size_t sym_invert_scratch_bytes(const DevBatch& b, int group, size_t* pbytes, si
 // y_k = base_k + alpha * A x_k for every matrix of the batch and the nv vectors
 // x_k = x + k ld (likewise base, y; internal order), read in groups of up to
 // symv_vectors(b) vectors per pass over the tiles
-// (part: symv_part_bytes(b) of scratch for the per-item partial sums)
+// (part: symv_part_bytes(b) of scratch for the per-item partial sums).  base may be y.
+// row0 (optional, per matrix): x is zero on the matrix's rows below 64 row0[m], so the
+// tile rows I < row0[m] add nothing (their row parts multiply x_J, J <= I, their column
+// parts x_I) and are not read
 hipError_t launch_symv(const DevBatch& b, const double* x, void* part, double alpha,
-                       const double* base, double* y, int nv, int64_t ld, hipStream_t s);
+                       const double* base, double* y, int nv, int64_t ld, hipStream_t s,
+                       const int32_t* row0 = nullptr);
 inline int symv_vectors(const DevBatch&) { return 4; }
 // dst (count 16-bit values, FP16 for kind 1, BF16 for kind 2) = src rounded to nearest
 hipError_t launch_narrow(const float* src, void* dst, int64_t count, int kind, hipStream_t s);

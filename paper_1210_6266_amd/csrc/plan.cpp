@@ -334,6 +334,9 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     RowErr col, sep;
   };
   std::vector<Worker> wk(size_t(Pool::get().size()));
+  // 1 for a dof coupled to a dof of another tree node (for a leaf's dof: an interface dof,
+  // the leaf's shell); every row is written by the worker that checks it
+  std::vector<uint8_t> outer(size_t(n), 0);
   parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
     Worker& o = wk[size_t(w)];
     for (int64_t i = lo; i < hi; ++i) {
@@ -354,6 +357,7 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
         int32_t ok = a;                        // last node seen on a's path
         for (int64_t k = b; k < en; ++k) {
           const int32_t bn = dof_node[col_idx[k]];
+          if (bn != a) outer[size_t(i)] = 1;
           if (bn == ok) continue;
           if (!anc(a, bn) && !anc(bn, a)) {
             o.sep = {i, fmt("K couples dof %lld and dof %lld whose tree nodes are not on one "
@@ -406,11 +410,19 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   int64_t pos = 0;
   P->leaf_off.assign(L, 0);
   P->leaf_n.assign(L, 0);
+  P->leaf_inner.assign(L, 0);
   for (int32_t l = 0; l < L; ++l) {
+    // the leaf's dofs in increasing caller index, those coupled to no interface dof first:
+    // the back-substitution's correction K_ll^{-1} K_{l,B} u_B then reads only the tile
+    // rows of the inverse that hold shell rows (engine's core_apply)
     const int32_t t = P->leaf_node[l];
     P->leaf_off[l] = pos;
     P->leaf_n[l] = owned_n(t);
-    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q) P->perm[pos++] = own[q];
+    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q)
+      if (!outer[size_t(own[q])]) P->perm[pos++] = own[q];
+    P->leaf_inner[l] = int32_t(pos - P->leaf_off[l]);
+    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q)
+      if (outer[size_t(own[q])]) P->perm[pos++] = own[q];
   }
   P->n_leaf = pos;
   std::vector<int32_t> inodes;

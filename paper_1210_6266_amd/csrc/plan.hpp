@@ -80,6 +80,8 @@ struct Plan {
   // leaves (true sub-domains), in node-id order
   std::vector<int32_t> leaf_node;            // leaf index -> node id
   std::vector<int64_t> leaf_off, leaf_n;     // internal dof range of each leaf interior
+  std::vector<int32_t> leaf_inner;           // its dofs coupled to no interface dof: they
+                                             // come first, the shell (the rest) last
   int64_t n_leaf = 0;                        // sum of leaf sizes: first interface dof
 
   // internal nodes that own interface dofs, in processing order
