@@ -261,10 +261,15 @@ __global__ __launch_bounds__(kBlock) void k_ell_spmv(
 }
 
 // Row r of K in internal order: row perm[r] of the caller's CSR with columns renamed by
-// iperm and sorted (insertion sort in place: the renamed row is a few increasing runs),
-// the caller's value position of each entry, and the row segments: first interface
-// column (segA); for interface rows the end of the deeper-level columns (segB) and of
-// the own node's columns (segC).
+// iperm and sorted, the caller's value position of each entry, and the row segments:
+// first interface column (segA); for interface rows the end of the deeper-level columns
+// (segB) and of the own node's columns (segC).  One wave per row: lane l holds entries
+// l, l + 64, ... (up to kPermSlots each); the columns are distinct, so an entry's place
+// is the number of smaller columns, counted by broadcasting every column once, and a
+// segment bound is the number of columns below it (ballots).  Longer rows: one lane
+// sorts by insertion.
+constexpr int kPermSlots = 4;
+constexpr int kPermRows = kBlock / 64;         // rows per workgroup
 __global__ __launch_bounds__(kBlock) void k_permute_csr(
     int32_t n, int64_t n_leaf, const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -272,36 +277,75 @@ __global__ __launch_bounds__(kBlock) void k_permute_csr(
     const int32_t* __restrict__ skel_own_end, int32_t* __restrict__ pcol,
     int64_t* __restrict__ pmap, int64_t* __restrict__ segA, int64_t* __restrict__ segB,
     int64_t* __restrict__ segC) {
-  const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (r >= n) return;
+  const int64_t r = int64_t(blockIdx.x) * kPermRows + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;                          // (the same for the whole wave)
   const int32_t o = perm[r];
   const int64_t k0 = rp[o], len = rp[o + 1] - k0, base = prow[r];
-  int32_t* c = pcol + base;
-  int64_t* v = pmap + base;
-  for (int64_t e = 0; e < len; ++e) {
-    const int32_t nc = iperm[ci[k0 + e]];
-    int64_t w = e;
-    while (w > 0 && c[w - 1] > nc) {
-      c[w] = c[w - 1];
-      v[w] = v[w - 1];
-      --w;
+  const int32_t lb = r < n_leaf ? 0 : skel_lvl_begin[r - n_leaf];
+  const int32_t oe = r < n_leaf ? 0 : skel_own_end[r - n_leaf];
+  int64_t na = 0, nb = 0, nc = 0;              // columns below n_leaf, lb, oe
+  if (len <= 64 * kPermSlots) {
+    int32_t key[kPermSlots];
+    int32_t rank[kPermSlots];
+#pragma unroll
+    for (int sl = 0; sl < kPermSlots; ++sl) {
+      const int64_t e = int64_t(sl) * 64 + lane;
+      key[sl] = e < len ? iperm[ci[k0 + e]] : INT32_MAX;
+      rank[sl] = 0;
     }
-    c[w] = nc;
-    v[w] = k0 + e;
+#pragma unroll
+    for (int sj = 0; sj < kPermSlots; ++sj) {
+      const int cnt = int(min<int64_t>(64, len - int64_t(sj) * 64));
+      for (int j = 0; j < cnt; ++j) {
+        const int32_t kj = __shfl(key[sj], j, 64);
+#pragma unroll
+        for (int sl = 0; sl < kPermSlots; ++sl) rank[sl] += kj < key[sl] ? 1 : 0;
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < kPermSlots; ++sl) {
+      const int64_t e = int64_t(sl) * 64 + lane;
+      const bool ok = e < len;
+      if (ok) {
+        pcol[base + rank[sl]] = key[sl];
+        pmap[base + rank[sl]] = k0 + e;
+      }
+      na += __popcll(__ballot(ok && key[sl] < n_leaf));
+      nb += __popcll(__ballot(ok && key[sl] < lb));
+      nc += __popcll(__ballot(ok && key[sl] < oe));
+    }
+  } else {
+    if (lane != 0) return;
+    int32_t* c = pcol + base;
+    int64_t* v = pmap + base;
+    for (int64_t e = 0; e < len; ++e) {
+      const int32_t kc = iperm[ci[k0 + e]];
+      int64_t w = e;
+      while (w > 0 && c[w - 1] > kc) {
+        c[w] = c[w - 1];
+        v[w] = v[w - 1];
+        --w;
+      }
+      c[w] = kc;
+      v[w] = k0 + e;
+    }
+    for (int64_t e = 0; e < len; ++e) {
+      na += c[e] < n_leaf;
+      nb += c[e] < lb;
+      nc += c[e] < oe;
+    }
   }
-  int64_t a = 0;
-  while (a < len && c[a] < n_leaf) ++a;
-  segA[r] = base + a;
+  if (lane != 0) return;
+  segA[r] = base + na;
   if (r < n_leaf) {
-    segB[r] = segC[r] = base + a;
+    segB[r] = segC[r] = base + na;
     return;
   }
-  const int32_t lb = skel_lvl_begin[r - n_leaf], oe = skel_own_end[r - n_leaf];
-  int64_t b = a;
-  while (b < len && c[b] < lb) ++b;
+  // (sorted columns: the deeper-level segment starts at the first interface column)
+  const int64_t b = na > nb ? na : nb;
   segB[r] = base + b;
-  while (b < len && c[b] < oe) ++b;
-  segC[r] = base + b;
+  segC[r] = base + (b > nc ? b : nc);
 }
 
 __global__ void k_fill(double* p, int64_t count, double v) {
@@ -2711,7 +2755,8 @@ hipError_t launch_permute_csr(int32_t n, int64_t n_leaf, const int32_t* perm, co
                               int32_t* pcol, int64_t* pmap, int64_t* segA, int64_t* segB,
                               int64_t* segC, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_permute_csr<<<blocks_for(n), kBlock, 0, s>>>(n, n_leaf, perm, iperm, rp, ci, prow,
+  k_permute_csr<<<unsigned((int64_t(n) + kPermRows - 1) / kPermRows), kBlock, 0, s>>>(
+      n, n_leaf, perm, iperm, rp, ci, prow,
                                                  skel_lvl_begin, skel_own_end, pcol, pmap, segA,
                                                  segB, segC);
   return hipGetLastError();
