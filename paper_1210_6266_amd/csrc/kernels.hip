@@ -646,6 +646,13 @@ __global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
   __shared__ T Bs[(G > 1 ? G - 1 : 1) * TT];
   __shared__ T col[2 * TS];
   __shared__ int fail;
+  // FP32: the sub-step's pivot-column tiles C_r (r != s) are staged in LDS by the other
+  // waves while wave 0 sweeps the diagonal tile, for the panel and the in-group update
+  // (FP64 reads them from global memory: 96 KB more would not fit).  Cs[r'][k][row] with
+  // k-rows padded to LDC (conflict-free reads of 16 rows x 4 k-rows per instruction).
+  constexpr bool kStageC = sizeof(T) == 4 && G > 1;
+  constexpr int LDC = TS + 16, CST = TS * LDC;
+  __shared__ T Cs[kStageC ? (G - 1) * CST : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
   if (threadIdx.x == 0) fail = 0;
   __syncthreads();
@@ -653,7 +660,17 @@ __global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
   auto pel = [&](int I, int J, int r, int c) -> T& { return P[(I * TS + r) + int64_t(J * TS + c) * PB]; };
   for (int s = 0; s < g; ++s) {
     const bool last = s == g - 1;
-    if (w == 0) wave_sweep64(tl(s, s), Ps, col, &fail);
+    if (w == 0) {
+      wave_sweep64(tl(s, s), Ps, col, &fail);
+    } else if constexpr (kStageC) {
+      // C_r(row, k) = A[r][s](row, k) for r > s, A[s][r](k, row) for r < s (r' = the index
+      // of r among the group's rows other than s)
+      for (int e = threadIdx.x - 64; e < (g - 1) * TT; e += NTH - 64) {
+        const int rr = e / TT, x = e % TT, row = x % TS, k = x / TS;
+        const int r = rr < s ? rr : rr + 1;
+        Cs[rr * CST + k * LDC + row] = r > s ? tl(r, s)[row + k * TS] : tl(s, r)[k + row * TS];
+      }
+    }
     __syncthreads();
     if (last)                                  // P_ss = -(swept diagonal tile) = Ps
       for (int e = threadIdx.x; e < TT; e += NTH) pel(s, s, e % TS, e / TS) = Ps[e];
@@ -676,7 +693,10 @@ __global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int row = 16 * q + li, kk = k + lk;
-          a[q] = tr ? Cr[kk + row * TS] : Cr[row + kk * TS];
+          if constexpr (kStageC)
+            a[q] = Cs[rr * CST + kk * LDC + row];
+          else
+            a[q] = tr ? Cr[kk + row * TS] : Cr[row + kk * TS];
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) b[q] = Ps[(32 * hf + 16 * q + li) + (k + lk) * TS];
@@ -713,8 +733,12 @@ __global__ __launch_bounds__(PivCfg<T>::threads) void k_sweep_pivot_blk(
             for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
               for (int v = 0; v < 4; ++v) acc[bi][bj][v] = A[acc_row64<T>(bi, v) + (16 * bj + li) * TS];
+          const T* Cqs = Cs + (kStageC ? (q < s ? q : q - 1) * CST : 0);
           wave_gemm64<T>([&](int row, int k) { return -Br[row + k * TS]; },
-                         [&](int k, int c) { return tq ? Cq[k + c * TS] : Cq[c + k * TS]; }, acc);
+                         [&](int k, int c) {
+                           if constexpr (kStageC) return Cqs[k * LDC + c];
+                           else return tq ? Cq[k + c * TS] : Cq[c + k * TS];
+                         }, acc);
 #pragma unroll
           for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
