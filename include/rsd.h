@@ -126,7 +126,7 @@ typedef struct {
   int32_t dense_max;     /* RSD_IFACE_HYBRID: largest interface solved exactly              */
   int32_t graphs;        /* 1: replay each preconditioner application from a HIP graph
                             captured on first use (one per number of columns, 1..8);
-                            ignored while timing = 1                                       */
+                            ignored while a class of the applications is timed (below)     */
   int32_t autotune;      /* 1: before the first application to 2..8 columns, time the
                             candidate numbers of vectors per pass (1, 2, 4) of every dense
                             batch's symmetric product, each with one workgroup per item
@@ -154,6 +154,11 @@ typedef struct {
                             form for a batch; 1 always the persistent work-queue form
                             (resident workgroups take the blocks from a counter).  Same
                             results either way                                               */
+  int32_t timing_classes; /* with timing = 1: bit mask of the kernel classes timed (bit c for
+                            class c of the RSD_T_* list below; the others report 0 ms and
+                            add no events between launches); 0 (default): every class.
+                            Graphs stay off while a class that the applications launch
+                            (leaf or interface apply, coupling, SpMV, Krylov) is timed      */
   /* Optional device allocator for the handle's memory (set both or neither; default
      NULL: the library's own cache of hipMalloc blocks).  dev_alloc(bytes, alloc_ctx)
      returns device memory on the current device, or NULL (RSD_ERR_OUT_OF_MEMORY);
@@ -293,7 +298,8 @@ rsd_status rsd_solve(rsd_handle h, int32_t nrhs, const double* b, int64_t ldb, d
 rsd_status rsd_update_values(rsd_handle h, const double* values, void* stream);
 
 /* Per-handle statistics.  Times are accumulated device times in milliseconds
- * measured with HIP events when the handle was created with timing = 1. */
+ * measured with HIP events when the handle was created with timing = 1 (for the
+ * classes selected by timing_classes). */
 enum {
   RSD_T_SETUP_EXTRACT = 0, /* value gathers, dense block extraction                    */
   RSD_T_LEAF_INVERSE,      /* batched in-place inversion of the K_ll (all kernels)    */

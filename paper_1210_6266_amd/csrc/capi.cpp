@@ -55,6 +55,7 @@ void rsd_options_default(rsd_options* o) {
   o->g_coupling = RSD_COUPLING_FULL;
   o->bf16_split = 1;
   o->sym_form = 0;
+  o->timing_classes = 0;
   o->dev_alloc = nullptr;
   o->dev_free = nullptr;
   o->alloc_ctx = nullptr;

@@ -254,7 +254,19 @@ struct Uploader {
   void done(rsd_ctx* h) { pfree(h, stage); }
 };
 
-// Times the launches enqueued during its lifetime on stream s (when timing is on).
+// Is kernel class cls timed with HIP events (timing on, the class selected)?
+bool timed(const rsd_ctx* h, int cls) {
+  if (!h->opt.timing || h->no_events) return false;
+  return h->opt.timing_classes == 0 || ((h->opt.timing_classes >> cls) & 1) != 0;
+}
+// ...any of the classes the applications launch (they then run eagerly, not from graphs)
+bool apply_timed(const rsd_ctx* h) {
+  for (int c : {RSD_T_LEAF_APPLY, RSD_T_IFACE_APPLY, RSD_T_COUPLING, RSD_T_SPMV, RSD_T_KRYLOV})
+    if (timed(h, c)) return true;
+  return false;
+}
+
+// Times the launches enqueued during its lifetime on stream s (when its class is timed).
 struct Timer {
   rsd_ctx* h;
   int cls;
@@ -262,7 +274,7 @@ struct Timer {
   hipEvent_t a = nullptr;
   Timer(rsd_ctx* h_, int cls_, hipStream_t s_) : h(h_), cls(cls_), s(s_) {
     h->launches[cls]++;
-    if (!h->opt.timing || h->no_events) return;
+    if (!timed(h, cls)) return;
     a = take();
     hip_check(h, hipEventRecord(a, s), "hipEventRecord");
   }
@@ -1270,7 +1282,7 @@ void drop_graphs(rsd_ctx* h) {
 void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   if (h->opt.autotune && nv >= 2 && nv <= kRhsGroup && !h->tuned[size_t(nv)])
     autotune_apply(h, nv, s);            // before this nv's graph is captured
-  if (!h->opt.graphs || h->opt.timing) {
+  if (!h->opt.graphs || apply_timed(h)) {
     core_apply(h, own_work(h), nv, r, z, s);
     return;
   }

@@ -52,6 +52,7 @@ class rsd_options(C.Structure):
                 ("iface_mode", C.c_int32), ("gamma", C.c_int32), ("dense_max", C.c_int32),
                 ("graphs", C.c_int32), ("autotune", C.c_int32), ("symmetric", C.c_int32),
                 ("g_coupling", C.c_int32), ("bf16_split", C.c_int32), ("sym_form", C.c_int32),
+                ("timing_classes", C.c_int32),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
 
@@ -302,7 +303,7 @@ class RSD:
                  sigma_prec=None, iface_prec=None, root_prec="fp64", timing=False, stream=None,
                  interface="dense", gamma=8, dense_max=32768, graphs=True, autotune=True,
                  symmetric=True, coupling="full", allocator=None, bf16_split=True,
-                 persistent_symv=False):
+                 persistent_symv=False, timed_classes=None):
         """interface: "dense" (exact interface solves), "gamma" (gamma steps of GMRES on
         every interface system, the paper's mode) or "hybrid" (gamma steps where an
         interface has more than dense_max dofs).  coupling: "full" or "leaf_only" (the
@@ -315,7 +316,9 @@ class RSD:
         bf16_split: FP32 blocks inverted with their trailing updates on the BF16 matrix
         cores (operands split exactly into three BF16 parts), rsd_options.bf16_split.
         persistent_symv: the applies' symmetric products always as persistent work-queue
-        launches (rsd_options.sym_form = 1; otherwise the autotuner may pick them)."""
+        launches (rsd_options.sym_form = 1; otherwise the autotuner may pick them).
+        timed_classes: with timing, the names (TIMER_NAMES) of the kernel classes timed
+        (rsd_options.timing_classes); None: all."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
 
@@ -336,6 +339,13 @@ class RSD:
         o.iface_prec = PREC[iface_prec or low]
         o.root_prec = PREC[root_prec]
         o.timing = 1 if timing else 0
+        if timed_classes is not None:
+            mask = 0
+            for name in timed_classes:
+                mask |= 1 << TIMER_NAMES.index(name)
+            if mask == 0:
+                raise ValueError("timed_classes: no class")
+            o.timing_classes = mask
         o.iface_mode = IFACE[interface]
         o.gamma = int(gamma)
         o.dense_max = int(dense_max)

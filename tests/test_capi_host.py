@@ -36,9 +36,11 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header(lib):
     o = R.rsd_options_default()
-    # 16 int32 fields, then the allocator's two function pointers and its context
-    assert o.struct_size == 16 * 4 + 3 * 8 == ctypes.sizeof(R.rsd_options)
-    assert R.rsd_options.dev_alloc.offset == 16 * 4
+    # 17 int32 fields (4 bytes of padding), then the allocator's two function pointers
+    # and its context
+    assert o.struct_size == 18 * 4 + 3 * 8 == ctypes.sizeof(R.rsd_options)
+    assert R.rsd_options.dev_alloc.offset == 18 * 4
+    assert R.rsd_options.timing_classes.offset == 16 * 4 and o.timing_classes == 0
     assert R.rsd_options.bf16_split.offset == 14 * 4 and o.bf16_split == 1
     assert R.rsd_options.sym_form.offset == 15 * 4 and o.sym_form == 0
     assert o.leaf_prec == 0 and o.timing == 0 and o.graphs == 1

@@ -179,3 +179,33 @@ def test_timing_events_pooled_and_cache_release(problem_cache):
     h = _handle(p)
     assert torch.equal(h.apply(r), ref)
     h.close()
+
+
+def test_timing_classes_selects_the_timed_classes(problem_cache):
+    """rsd_options.timing_classes: with timing = 1, only the selected kernel classes are
+    timed (the others report 0 ms), every class still counts its launches, the
+    applications replay from graphs when none of their classes is timed, and the results
+    are those of an untimed handle."""
+    _log("timing classes")
+    p = problem_cache("diffusion", 20, 2, 1.0, 3)
+    r = torch.as_tensor(np.random.default_rng(10).uniform(-1, 1, p.n)).cuda()
+    hu = _handle(p)
+    zu = hu.apply(r)
+    Xu, su, iu = hu.solve(r, rtol=1e-10)
+    hu.close()
+    for classes in (["leaf_update"], ["leaf_update", "leaf_apply"]):
+        h = _handle(p, timing=True, timed_classes=classes)
+        assert torch.equal(h.apply(r), zu)
+        X, s, info = h.solve(r, rtol=1e-10)
+        assert s == su == 0 and info[0]["iterations"] == iu[0]["iterations"]
+        assert torch.equal(X, Xu)
+        st = h.stats()
+        h.close()
+        for name, ms in st["time_ms"].items():
+            if name in classes:
+                assert ms > 0.0, (name, st["time_ms"])
+            else:
+                assert ms == 0.0, (name, st["time_ms"])
+        assert st["launches"]["leaf_apply"] > 0 and st["launches"]["krylov"] > 0, st["launches"]
+    with pytest.raises(ValueError):
+        _handle(p, timing=True, timed_classes=[])
