@@ -1918,10 +1918,10 @@ void engine_free(rsd_ctx* h) {
   h->has_last = false;
   if (h->aux) give_aux(h->device, h->aux);   // idle: its work was joined and completed
   h->aux = nullptr;
-  if (h->upl) {                                // (its one copy was joined onto the set-up's
-    (void)hipStreamSynchronize(h->upl);        // stream; a failed set-up may have stopped
-    give_aux(h->device, h->upl);               // before that wait)
-  }
+  if (h->upl) {                                // (its work, the couplings' copy and the
+    (void)hipStreamSynchronize(h->upl);        // Schur assemblies, was joined onto the
+    give_aux(h->device, h->upl);               // set-up's stream; a failed set-up may have
+  }                                            // stopped before those waits)
   h->upl = nullptr;
   BlockCache& c = cache_of(h->device);
   for (auto& p : h->allocs) {                                           // work is complete

@@ -578,47 +578,6 @@ __device__ __forceinline__ void wave_gemm64(LA lda, LB ldb, typename Mfma<T>::v4
   }
 }
 
-// wave_gemm64 with one operand read from (global) memory for all 64 k up front: the
-// loads of a 64 x 64 operand are issued together (one memory round trip instead of one
-// per k-step), then the MFMAs consume them with the other operand from LDS.
-template <typename T, typename LA, typename LB>
-__device__ __forceinline__ void wave_gemm64_pa(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[4][4]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  T pa[16][4];
-#pragma unroll
-  for (int t = 0; t < 16; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pa[t][q] = lda(16 * q + li, 4 * t + lk);
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    T b[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b[q] = ldb(4 * t + lk, 16 * q + li);
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(pa[t][bi], b[bj], acc[bi][bj]);
-  }
-}
-template <typename T, typename LA, typename LB>
-__device__ __forceinline__ void wave_gemm64_pb(LA lda, LB ldb, typename Mfma<T>::v4 (&acc)[4][4]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  T pb[16][4];
-#pragma unroll
-  for (int t = 0; t < 16; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pb[t][q] = ldb(4 * t + lk, 16 * q + li);
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    T a[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = lda(16 * q + li, 4 * t + lk);
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::op(a[bi], pb[t][bj], acc[bi][bj]);
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ int acc_row64(int bi, int v) {
