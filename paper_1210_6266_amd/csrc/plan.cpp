@@ -95,10 +95,13 @@ class Pool {
   uint64_t gen_ = 0;
 };
 
-// Runs fn(lo, hi, worker) over [0, count) split into contiguous chunks, one per worker.
-void parallel_for(int64_t count, const std::function<void(int64_t, int64_t, int)>& fn) {
+// Runs fn(lo, hi, worker) over [0, count) split into contiguous chunks, one per worker
+// (at most one worker per `grain` items).  The split depends only on count, grain and the
+// pool's size: loops over the same count hand worker w the same chunk.
+void parallel_for(int64_t count, const std::function<void(int64_t, int64_t, int)>& fn,
+                  int64_t grain = 4096) {
   Pool& pool = Pool::get();
-  const int nt = int(std::min<int64_t>(pool.size(), std::max<int64_t>(1, count / 4096 + 1)));
+  const int nt = int(std::min<int64_t>(pool.size(), std::max<int64_t>(1, count / grain + 1)));
   const int64_t chunk = (count + nt - 1) / nt;
   pool.run(nt, [&](int w) {
     const int64_t lo = std::min(count, int64_t(w) * chunk), hi = std::min(count, lo + chunk);
@@ -259,7 +262,7 @@ void layout_sym_batch(SymBatch* b) {
 PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                      int32_t T, const int32_t* parent, const int32_t* dof_node, Plan* P,
                      std::string* msg) {
-  // ---- validation of the CSR --------------------------------------------------------
+  // ---- validation of the CSR (its rows are checked by the passes below) ---------------
   if (n <= 0) { *msg = "n must be positive"; return PlanError::kInvalid; }
   if (nnz < 0 || row_ptr == nullptr || (nnz > 0 && col_idx == nullptr)) {
     *msg = "null CSR array or negative nnz";
@@ -269,11 +272,6 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     *msg = fmt("row_ptr[0] must be 0 and row_ptr[n] = nnz (%lld), got %lld", nnz, row_ptr[n]);
     return PlanError::kInvalid;
   }
-  for (int32_t i = 0; i < n; ++i)
-    if (row_ptr[i + 1] < row_ptr[i]) {
-      *msg = fmt("row_ptr decreases at row %lld", i);
-      return PlanError::kInvalid;
-    }
   // ---- validation of the tree (reported after the CSR's errors) ---------------------
   std::string tree_msg;
   if (T <= 0 || parent == nullptr || dof_node == nullptr) {
@@ -284,10 +282,56 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
     for (int32_t t = 1; t < T && tree_msg.empty(); ++t)
       if (parent[t] < 0 || parent[t] >= t)
         tree_msg = fmt("parent[%lld] = %lld must lie in [0, %lld)", t, parent[t], t);
-    for (int32_t i = 0; i < n && tree_msg.empty(); ++i)
-      if (dof_node[i] < 0 || dof_node[i] >= T)
-        tree_msg = fmt("dof_node[%lld] = %lld out of range", i, dof_node[i]);
   }
+  const bool parents_ok = tree_msg.empty();
+  // Each check below reports its lowest failing row, so messages do not depend on the
+  // thread schedule; the CSR's errors come first, then the tree's, then separability.
+  struct RowErr {
+    int64_t row = INT64_MAX;
+    std::string msg;
+  };
+  struct Worker {
+    RowErr rp, dn, col, sep;
+  };
+  const int NW = Pool::get().size();
+  std::vector<Worker> wk(static_cast<size_t>(NW));
+  auto lowest = [&](RowErr Worker::*f) {
+    const RowErr* best = nullptr;
+    for (const Worker& o : wk)
+      if ((o.*f).row != INT64_MAX && (best == nullptr || (o.*f).row < best->row)) best = &(o.*f);
+    return best;
+  };
+  // Per worker (the three passes over the rows split them alike) and node: its rows, and
+  // those of them coupled to no dof of another node (rows of TS counts, padded so that no
+  // two workers write one cache line).
+  const size_t TS = (size_t(T) + 31) / 16 * 16;
+  const size_t WT = parents_ok ? size_t(NW) * TS : 0;
+  std::vector<int32_t> cnt(WT, 0), icnt(WT, 0);
+  // ---- first pass: row_ptr non-decreasing, dof_node in range, the rows of each node ----
+  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+    Worker& o = wk[size_t(w)];
+    for (int64_t i = lo; i < hi; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) {
+        o.rp = {i, fmt("row_ptr decreases at row %lld", i)};
+        break;
+      }
+    if (!parents_ok) return;
+    int32_t* const c = cnt.data() + size_t(w) * TS;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t t = dof_node[i];
+      if (t < 0 || t >= T) {
+        o.dn = {i, fmt("dof_node[%lld] = %lld out of range", i, t)};
+        break;
+      }
+      ++c[t];
+    }
+  });
+  if (const RowErr* r = lowest(&Worker::rp)) {   // (then every row lies in [0, nnz])
+    *msg = r->msg;
+    return PlanError::kInvalid;
+  }
+  if (parents_ok)
+    if (const RowErr* r = lowest(&Worker::dn)) tree_msg = r->msg;
   const bool tree_ok = tree_msg.empty();
   // Euler tour for ancestor tests (parent[t] < t: ids are topologically ordered)
   std::vector<int32_t> tin, tout;
@@ -317,64 +361,65 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       }
     }
   }
-  auto anc = [&](int32_t a, int32_t b) {  // a is an ancestor of b, or a == b
-    return tin[a] <= tin[b] && tout[b] <= tout[a];
-  };
-  // ---- one parallel pass over the rows --------------------------------------------------
-  // Per row: columns in range and strictly increasing; separability (every coupling joins
-  // nodes on one root-to-leaf path).  Each check reports its lowest failing row, so
-  // messages do not depend on the thread schedule; the CSR's errors come first, then the
-  // tree's, then separability.  (Structural symmetry, which no device work before the
-  // couplings relies on, is checked by build_plan_couplings.)
-  struct RowErr {
-    int64_t row = INT64_MAX;
-    std::string msg;
-  };
-  struct Worker {
-    RowErr col, sep;
-  };
-  std::vector<Worker> wk(size_t(Pool::get().size()));
-  // 1 for a dof coupled to a dof of another tree node (for a leaf's dof: an interface dof,
-  // the leaf's shell); every row is written by the worker that checks it
-  std::vector<uint8_t> outer(size_t(n), 0);
+  // ---- second pass: columns in range and strictly increasing; separability ------------
+  // (every coupling joins nodes on one root-to-leaf path).  Structural symmetry, which no
+  // device work before the couplings relies on, is checked by build_plan_couplings.
+  // outer[i] = 1 for a dof coupled to a dof of another tree node (for a leaf's dof: an
+  // interface dof, the leaf's shell).
+  hvec<uint8_t> outer(static_cast<size_t>(n));
   parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
     Worker& o = wk[size_t(w)];
+    const int32_t* const ti = tin.data();
+    const int32_t* const to = tout.data();
+    auto anc = [&](int32_t a, int32_t b) {  // a is an ancestor of b, or a == b
+      return ti[a] <= ti[b] && to[b] <= to[a];
+    };
+    int32_t* const ic = tree_ok ? icnt.data() + size_t(w) * TS : nullptr;
+    uint8_t* const out = outer.data();
+    bool sep = tree_ok;                        // no separability error seen yet
     for (int64_t i = lo; i < hi; ++i) {
       const int64_t b = row_ptr[i], en = row_ptr[i + 1];
+      bool bad = false;
+      int32_t prev = -1;
       for (int64_t k = b; k < en; ++k) {
         const int32_t c = col_idx[k];
-        if (c < 0 || c >= n) {
-          o.col = {i, fmt("column index %lld out of range in row %lld", c, i)};
-          return;
-        }
-        if (k > b && c <= col_idx[k - 1]) {
-          o.col = {i, fmt("columns of row %lld not strictly increasing", i)};
-          return;
-        }
+        bad |= (c <= prev) | (c >= n);
+        prev = c;
       }
-      if (tree_ok && o.sep.row == INT64_MAX) {
-        const int32_t a = dof_node[i];
-        int32_t ok = a;                        // last node seen on a's path
+      if (bad) {                               // name the first offending entry
         for (int64_t k = b; k < en; ++k) {
-          const int32_t bn = dof_node[col_idx[k]];
-          if (bn != a) outer[size_t(i)] = 1;
-          if (bn == ok) continue;
-          if (!anc(a, bn) && !anc(bn, a)) {
-            o.sep = {i, fmt("K couples dof %lld and dof %lld whose tree nodes are not on one "
-                            "root-to-leaf path (node %lld)", i, col_idx[k], a)};
-            break;
+          const int32_t c = col_idx[k];
+          if (c < 0 || c >= n) {
+            o.col = {i, fmt("column index %lld out of range in row %lld", c, i)};
+            return;
           }
-          ok = bn;
+          if (k > b && c <= col_idx[k - 1]) {
+            o.col = {i, fmt("columns of row %lld not strictly increasing", i)};
+            return;
+          }
         }
       }
+      if (!sep) continue;
+      const int32_t a = dof_node[i];
+      int32_t ok = a;                          // a node of a's path seen last
+      bool sh = false;
+      for (int64_t k = b; k < en; ++k) {
+        const int32_t bn = dof_node[col_idx[k]];
+        if (bn == a) continue;
+        sh = true;
+        if (bn == ok) continue;
+        if (!anc(a, bn) && !anc(bn, a)) {
+          o.sep = {i, fmt("K couples dof %lld and dof %lld whose tree nodes are not on one "
+                          "root-to-leaf path (node %lld)", i, col_idx[k], a)};
+          sep = false;
+          break;
+        }
+        ok = bn;
+      }
+      out[i] = sh;
+      ic[a] += !sh;
     }
   });
-  auto lowest = [&](RowErr Worker::*f) {
-    const RowErr* best = nullptr;
-    for (const Worker& o : wk)
-      if ((o.*f).row != INT64_MAX && (best == nullptr || (o.*f).row < best->row)) best = &(o.*f);
-    return best;
-  };
   if (const RowErr* r = lowest(&Worker::col)) {
     *msg = r->msg;
     return PlanError::kInvalid;
@@ -392,42 +437,42 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   P->T = T;
 
   // ---- orderings ---------------------------------------------------------------------
-  std::vector<int64_t> own_ptr(size_t(T) + 1, 0);
-  std::vector<int32_t> own(n);
-  for (int32_t i = 0; i < n; ++i) own_ptr[dof_node[i] + 1]++;
-  for (int32_t t = 0; t < T; ++t) own_ptr[t + 1] += own_ptr[t];
-  {
-    std::vector<int64_t> fill(own_ptr.begin(), own_ptr.end() - 1);
-    for (int32_t i = 0; i < n; ++i) own[fill[dof_node[i]]++] = i;
-  }
-  auto owned_n = [&](int32_t t) { return own_ptr[t + 1] - own_ptr[t]; };
+  // Internal order: the leaves in node-id order, each with its dofs coupled to no
+  // interface dof first (the back-substitution's correction K_ll^{-1} K_{l,B} u_B then
+  // reads only the tile rows of the inverse that hold shell rows: engine's core_apply),
+  // then the interface nodes deepest level first; within each group, caller order.
+  std::vector<int64_t> owned(size_t(T), 0), inner(size_t(T), 0);
+  for (int w = 0; w < NW; ++w)
+    for (int32_t t = 0; t < T; ++t) {
+      owned[t] += cnt[size_t(w) * TS + t];
+      inner[t] += icnt[size_t(w) * TS + t];
+    }
   P->leaf_node.clear();
   for (int32_t t = 0; t < T; ++t)
     if (P->children[t].empty()) P->leaf_node.push_back(t);
   const int32_t L = int32_t(P->leaf_node.size());
-  P->perm.resize(n);
-  P->iperm.resize(n);
+  // first position of each node's group(s): [2t] its dofs (a leaf's inner ones), [2t + 1]
+  // a leaf's shell
+  std::vector<int64_t> first(2 * size_t(T), 0);
+  std::vector<uint8_t> is_leaf(size_t(T), 0);
   int64_t pos = 0;
   P->leaf_off.assign(L, 0);
   P->leaf_n.assign(L, 0);
   P->leaf_inner.assign(L, 0);
   for (int32_t l = 0; l < L; ++l) {
-    // the leaf's dofs in increasing caller index, those coupled to no interface dof first:
-    // the back-substitution's correction K_ll^{-1} K_{l,B} u_B then reads only the tile
-    // rows of the inverse that hold shell rows (engine's core_apply)
     const int32_t t = P->leaf_node[l];
+    is_leaf[t] = 1;
     P->leaf_off[l] = pos;
-    P->leaf_n[l] = owned_n(t);
-    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q)
-      if (!outer[size_t(own[q])]) P->perm[pos++] = own[q];
-    P->leaf_inner[l] = int32_t(pos - P->leaf_off[l]);
-    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q)
-      if (outer[size_t(own[q])]) P->perm[pos++] = own[q];
+    P->leaf_n[l] = owned[t];
+    P->leaf_inner[l] = int32_t(inner[t]);
+    first[2 * t] = pos;
+    first[2 * t + 1] = pos + inner[t];
+    pos += owned[t];
   }
   P->n_leaf = pos;
   std::vector<int32_t> inodes;
   for (int32_t t = 0; t < T; ++t)
-    if (!P->children[t].empty() && owned_n(t) > 0) inodes.push_back(t);
+    if (!P->children[t].empty() && owned[t] > 0) inodes.push_back(t);
   std::stable_sort(inodes.begin(), inodes.end(),
                    [&](int32_t a, int32_t b) { return P->depth[a] > P->depth[b]; });
   P->iface_node = inodes;
@@ -447,13 +492,44 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
       P->level_dof_begin.push_back(pos);
     }
     P->iface_off[s] = pos;
-    P->iface_n[s] = owned_n(t);
-    for (int64_t q = own_ptr[t]; q < own_ptr[t + 1]; ++q) P->perm[pos++] = own[q];
+    P->iface_n[s] = owned[t];
+    first[2 * t] = pos;
+    pos += owned[t];
   }
   if (NI > 0) P->level_dof_end.push_back(pos);
   P->level_iface_begin.push_back(NI);
   const int32_t NL = int32_t(P->level_depth.size());
-  for (int32_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = i;
+  // each worker's first position in each group: the rows of the workers before it come first
+  hvec<int64_t> cur(size_t(NW) * 2 * T);
+  parallel_for(T, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t t = lo; t < hi; ++t) {
+      int64_t g0 = first[2 * t], g1 = first[2 * t + 1];
+      for (int w = 0; w < NW; ++w) {
+        const size_t wt = size_t(w) * TS + t, wc = size_t(w) * T + t;
+        cur[2 * wc] = g0;
+        cur[2 * wc + 1] = g1;
+        g0 += is_leaf[t] ? icnt[wt] : cnt[wt];
+        g1 += is_leaf[t] ? cnt[wt] - icnt[wt] : 0;
+      }
+    }
+  }, 256);
+  // ---- third pass: perm, iperm and the row lengths in internal order ------------------
+  P->perm.resize(n);
+  P->iperm.resize(n);
+  P->prow.resize(size_t(n) + 1);
+  parallel_for(n, [&](int64_t lo, int64_t hi, int w) {
+    int64_t* const c = cur.data() + size_t(w) * 2 * T;
+    int32_t* const pm = P->perm.data();
+    int32_t* const ip = P->iperm.data();
+    int64_t* const pr = P->prow.data();
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t t = dof_node[i];
+      const int64_t p = c[2 * t + (outer[i] & is_leaf[t])]++;
+      pm[p] = int32_t(i);
+      ip[i] = int32_t(p);
+      pr[p + 1] = row_ptr[i + 1] - row_ptr[i];
+    }
+  });
   const int64_t nB = n - P->n_leaf;
   P->dof_level.assign(nB, 0);
   P->skel_lvl_begin.assign(nB, 0);
@@ -466,22 +542,35 @@ PlanError build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32
   for (int32_t s = 0; s < NI; ++s)
     for (int64_t d = P->iface_off[s]; d < P->iface_off[s] + P->iface_n[s]; ++d)
       P->skel_own_end[d - P->n_leaf] = int32_t(P->iface_off[s] + P->iface_n[s]);
-  // row pointers of K in internal order
-  P->prow.resize(size_t(n) + 1);
-  P->prow[0] = 0;
-  for (int32_t r = 0; r < n; ++r) {
-    const int32_t o = P->perm[r];
-    P->prow[r + 1] = P->prow[r] + (row_ptr[o + 1] - row_ptr[o]);
-  }
+  // row pointers of K in internal order (a prefix sum of the lengths, by slices of
+  // kEllSlice rows), and the sliced ELL layout: slice s padded to its longest row
   {
     const int64_t ns = (int64_t(n) + kEllSlice - 1) / kEllSlice;
+    int64_t* const pr = P->prow.data();
+    pr[0] = 0;
     P->ell_off.assign(size_t(ns) + 1, 0);
-    for (int64_t sl = 0; sl < ns; ++sl) {
-      int64_t w = 0;
-      for (int64_t r = sl * kEllSlice; r < std::min<int64_t>(n, (sl + 1) * kEllSlice); ++r)
-        w = std::max(w, P->prow[r + 1] - P->prow[r]);
-      P->ell_off[sl + 1] = P->ell_off[sl] + w * kEllSlice;
-    }
+    std::vector<int64_t> part(size_t(NW) + 1, 0);
+    parallel_for(ns, [&](int64_t lo, int64_t hi, int w) {
+      int64_t sum = 0;
+      for (int64_t sl = lo; sl < hi; ++sl) {
+        int64_t wd = 0;
+        for (int64_t r = sl * kEllSlice; r < std::min<int64_t>(n, (sl + 1) * kEllSlice); ++r) {
+          wd = std::max(wd, pr[r + 1]);
+          sum += pr[r + 1];
+        }
+        P->ell_off[sl + 1] = wd * kEllSlice;
+      }
+      part[size_t(w) + 1] = sum;
+    }, 64);
+    for (int w = 0; w < NW; ++w) part[size_t(w) + 1] += part[size_t(w)];
+    for (int64_t sl = 0; sl < ns; ++sl) P->ell_off[sl + 1] += P->ell_off[sl];
+    parallel_for(ns, [&](int64_t lo, int64_t hi, int w) {
+      int64_t acc = part[size_t(w)];
+      for (int64_t r = lo * kEllSlice; r < std::min<int64_t>(n, hi * kEllSlice); ++r) {
+        acc += pr[r + 1];
+        pr[r + 1] = acc;
+      }
+    }, 64);
   }
 
   // ---- dense batches ---------------------------------------------------------------

@@ -163,6 +163,43 @@ def test_rejects_invalid_input(problem_cache, lib, case):
         assert "structurally symmetric" in msg
 
 
+def test_reports_the_lowest_failing_row(problem_cache, lib):
+    """The analysis checks the rows in parallel chunks (23^3 dofs: several chunks); with
+    the same defect planted in two rows of different chunks, the message names the lower
+    row, and a defect of the CSR is reported before one of the tree."""
+    p = problem_cache("diffusion", 24, 1, 0.0, 0)
+    base = _arrays(p)
+    n, T = p.n, len(base[2])
+    lo_row, hi_row = 100, n - 100
+
+    def planted(kind, rows):
+        rp, ci, par, dn = [x.copy() for x in base]
+        for r in rows:
+            if kind == "row_ptr":
+                rp[r + 1] = rp[r] - 1
+            elif kind == "col_range":
+                ci[rp[r + 1] - 1] = n
+            elif kind == "unsorted":
+                ci[rp[r]], ci[rp[r] + 1] = ci[rp[r] + 1], ci[rp[r]]
+            elif kind == "dof_node":
+                dn[r] = T
+        return rp, ci, par, dn
+
+    expect = {"row_ptr": f"row_ptr decreases at row {lo_row}",
+              "col_range": f"column index {n} out of range in row {lo_row}",
+              "unsorted": f"columns of row {lo_row} not strictly increasing",
+              "dof_node": f"dof_node[{lo_row}] = {T} out of range"}
+    for kind, want in expect.items():
+        for rows in ((lo_row, hi_row), (hi_row, lo_row)):
+            msg = _expect(1, lambda: R.rsd_analyze(*planted(kind, rows)))
+            assert want in msg, (kind, msg)
+    # a column defect in a late row and a tree defect in an early one: the CSR's first
+    rp, ci, par, dn = planted("col_range", (hi_row,))
+    dn[lo_row] = T
+    msg = _expect(1, lambda: R.rsd_analyze(rp, ci, par, dn))
+    assert f"out of range in row {hi_row}" in msg, msg
+
+
 def test_setup_validates_before_device_work(problem_cache, lib):
     """With host pointers and an invalid map, rsd_setup fails in the host analysis
     (no device call is reached) and reports the error thread-locally."""

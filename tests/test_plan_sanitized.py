@@ -61,8 +61,21 @@ def test_host_analysis_under_sanitizers(problem_cache):
     cases["valid_h1"] = _arrays(p)
     cases["valid_h2"] = _arrays(problem_cache("diffusion", 13, 2, 1.0, 2))
     cases["valid_strip"] = _arrays(problem_cache("strip", 9, 8, "poisson", 0))
+    # 23^3 dofs: the passes over the rows run in several chunks
+    big = problem_cache("diffusion", 24, 2, 0.0, 0)
+    cases["valid_chunks"] = _arrays(big)
+    rp, ci, par, dn = [x.copy() for x in _arrays(big)]
+    for r in (100, big.n - 100):
+        rp[r + 1] = rp[r] - 1
+    cases["row_ptr_chunks"] = (rp, ci, par, dn)
+    rp, ci, par, dn = [x.copy() for x in _arrays(big)]
+    for r in (100, big.n - 100):
+        ci[rp[r + 1] - 1] = big.n
+        dn[r] = len(par)
+    cases["col_range_chunks"] = (rp, ci, par, dn)
     expect = {name: 1 for name in INVALID_CASES}
-    expect.update(not_separable=2, valid_h1=0, valid_h2=0, valid_strip=0)
+    expect.update(not_separable=2, valid_h1=0, valid_h2=0, valid_strip=0, valid_chunks=0,
+                  row_ptr_chunks=1, col_range_chunks=1)
     tmp = tempfile.mkdtemp(prefix="rsd_san_")
     try:
         gxx, so = _build(tmp)
