@@ -337,7 +337,9 @@ typedef struct {
                               0 none, 1 look-ahead, 2 serial steps, 3 look-ahead with
                               256 x 256 update super-tiles, 4 serial with them (the
                               set-up autotuner's choice, or the candidate it was timing;
-                              every variant gives the same bits)              */
+                              every variant gives the same bits).  With symmetric K the
+                              dense levels other than the shallowest one are inverted
+                              beside it on a second stream, in serial steps (2 or 4) */
   int32_t sym_persist[8];   /* the same batches: 1 where the autotuner chose the
                               persistent work-queue form of the symmetric products
                               (resident workgroups taking items from a counter)  */

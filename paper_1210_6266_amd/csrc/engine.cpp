@@ -865,16 +865,34 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       need_p = pb;
       need_c = cb;
     }
+    // The dense levels other than the shallowest (the last in processing order, the
+    // largest systems) are inverted on the upload stream, beside it: each level's S~
+    // depends only on K and the Sigma blocks, and the shallowest level's sweep leaves
+    // most compute units idle around its pivots.  They take the serial schedule (the
+    // auxiliary stream carries the shallowest level's look-ahead) and scratch of their own.
+    int last_dense = -1;
+    for (size_t q = 0; q < h->lev.size(); ++q)
+      if (!h->gam_level[q]) last_dense = int(q);
+    size_t side_p = 0, side_c = 0;
     for (size_t q = 0; q < h->lev.size(); ++q) {
       if (h->gam_level[q]) continue;   // no dense factor at the levels solved matrix-free
       const DevBatch& L = h->lev[q];
       sym_invert_scratch_bytes(L, group_for(h, L), &pb, &cb);
-      need_p = std::max(need_p, pb);
-      need_c = std::max(need_c, cb);
+      if (int(q) == last_dense || !h->opt.symmetric) {
+        need_p = std::max(need_p, pb);
+        need_c = std::max(need_c, cb);
+      } else {
+        side_p = std::max(side_p, pb);
+        side_c = std::max(side_c, cb);
+      }
     }
+    const bool side = side_p > 0 || side_c > 0;
     char* pbuf = dalloc<char>(h, need_p);
     void* cbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
     void* bbuf[2] = {dalloc<char>(h, need_c), dalloc<char>(h, need_c)};
+    char* side_pbuf = side ? dalloc<char>(h, side_p) : nullptr;
+    void* side_cbuf[2] = {side ? dalloc<char>(h, side_c) : nullptr, nullptr};
+    void* side_bbuf[2] = {side ? dalloc<char>(h, side_c) : nullptr, nullptr};
     // one batch's inversion with the autotuner's candidate (timed while tuning)
     struct Pending {
       std::string key;
@@ -882,24 +900,31 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       hipEvent_t a, b;
     };
     std::vector<Pending> tuned;
-    auto invert = [&](DevBatch bb, const SymBatch& sb, int32_t* fl, int upd, int slot) {
+    // (on_side: on the upload stream, serial candidates only: 1, 3, ...)
+    auto invert = [&](DevBatch bb, const SymBatch& sb, int32_t* fl, int upd, int slot,
+                      bool on_side = false) {
+      const hipStream_t st = on_side ? h->upl : s;
       const int G = group_for(h, bb);
-      const int ncand = inv_candidates(bb, G);
-      const std::string key = inv_key(sb, bb, G);
+      const int ncand = on_side ? std::max(1, inv_candidates(bb, G) / 2) : inv_candidates(bb, G);
+      const std::string key = inv_key(sb, bb, G) + (on_side ? ":serial" : "");
       bool tuning = false;
-      const int cand = inv_pick(h, key, ncand, &tuning);
+      const int pick = inv_pick(h, key, ncand, &tuning);
+      const int cand = on_side ? 2 * pick + 1 : pick;
       bb.upd_shape = cand / 2;
       if (slot < 8) h->setup_variant[slot] = cand + 1;
       hipEvent_t a = nullptr, b = nullptr;
       if (tuning) {
         hip_check(h, hipEventCreate(&a), "hipEventCreate");
         hip_check(h, hipEventCreate(&b), "hipEventCreate");
-        hip_check(h, hipEventRecord(a, s), "hipEventRecord");
+        hip_check(h, hipEventRecord(a, st), "hipEventRecord");
       }
-      invert_batch(h, bb, pbuf, cbuf, bbuf, fl, upd, (cand & 1) == 0, s);
+      if (on_side)
+        invert_batch(h, bb, side_pbuf, side_cbuf, side_bbuf, fl, upd, false, st);
+      else
+        invert_batch(h, bb, pbuf, cbuf, bbuf, fl, upd, (cand & 1) == 0, st);
       if (tuning) {
-        hip_check(h, hipEventRecord(b, s), "hipEventRecord");
-        tuned.push_back({key, ncand, cand, a, b});
+        hip_check(h, hipEventRecord(b, st), "hipEventRecord");
+        tuned.push_back({key, ncand, pick, a, b});
       }
     };
     for (int32_t& v : h->setup_variant) v = 0;
@@ -959,12 +984,19 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     }
     for (size_t q = 0; q < h->lev.size(); ++q) {
       if (h->gam_level[q]) continue;
-      hip_check(h, hipStreamWaitEvent(s, h->ev_lev[q], 0), "hipStreamWaitEvent");
+      const bool on_side = side && int(q) != last_dense;
+      if (!on_side)      // (the upload stream runs its levels after their assemblies)
+        hip_check(h, hipStreamWaitEvent(s, h->ev_lev[q], 0), "hipStreamWaitEvent");
       {
-        Timer tm(h, RSD_T_IFACE_INVERSE, s);
+        Timer tm(h, RSD_T_IFACE_INVERSE, on_side ? h->upl : s);
         invert(h->lev[q], P.level_batch[q], iflags + P.level_iface_begin[q],
-               P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, int(1 + q));
+               P.level_depth[q] == 0 ? RSD_T_ROOT_UPDATE : RSD_T_IFACE_UPDATE, int(1 + q),
+               on_side);
       }
+    }
+    if (side) {        // s waits for the levels on the upload stream
+      hip_check(h, hipEventRecord(h->ev_upl, h->upl), "hipEventRecord");
+      hip_check(h, hipStreamWaitEvent(s, h->ev_upl, 0), "hipStreamWaitEvent");
     }
     h->setup_wall[2] = ms_since(w2);
     const auto w3 = std::chrono::steady_clock::now();
@@ -985,6 +1017,11 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
     for (int i = 0; i < 2; ++i) {
       dfree(h, cbuf[i]);
       dfree(h, bbuf[i]);
+    }
+    if (side) {
+      dfree(h, side_pbuf);
+      dfree(h, side_cbuf[0]);
+      dfree(h, side_bbuf[0]);
     }
     for (Pinned& b : h->held) pfree(h, b);    // the uploads have completed
     h->held.clear();
