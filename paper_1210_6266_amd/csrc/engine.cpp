@@ -464,6 +464,8 @@ void inv_record(const std::string& key, int ncand, int cand, float ms) {
   }
 }
 
+void precapture_apply(rsd_ctx* h);
+
 }  // namespace
 
 // Scratch of the inexact interface solves for nv vectors (nothing without gamma levels);
@@ -998,6 +1000,7 @@ rsd_status engine_numeric(rsd_ctx* h, const double* values, hipStream_t s) {
       hip_check(h, hipEventRecord(h->ev_upl, h->upl), "hipEventRecord");
       hip_check(h, hipStreamWaitEvent(s, h->ev_upl, 0), "hipStreamWaitEvent");
     }
+    precapture_apply(h);
     h->setup_wall[2] = ms_since(w2);
     const auto w3 = std::chrono::steady_clock::now();
     std::vector<int32_t> fl(P.leaf_node.size() + P.iface_node.size());
@@ -1311,6 +1314,30 @@ void drop_graphs(rsd_ctx* h) {
   h->apply_graph.clear();
 }
 
+// The graph of the whole application for nv vectors on the fixed vectors rin -> zin,
+// captured on first use (on the handle's own stream: capturing executes nothing).
+hipGraphExec_t apply_graph(rsd_ctx* h, int nv) {
+  if (int(h->apply_graph.size()) <= nv) h->apply_graph.resize(size_t(nv) + 1, nullptr);
+  hipGraphExec_t& ex = h->apply_graph[size_t(nv)];
+  if (ex) return ex;
+  if (!h->cap)
+    hip_check(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreate");
+  hipGraph_t g = nullptr;
+  hip_check(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    core_apply(h, own_work(h), nv, h->rin, h->zin, h->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(h, hipStreamEndCapture(h->cap, &g), "end capture");
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(h, e, "hipGraphInstantiate");
+  return ex;
+}
+
 // z = M^{-1} r for nv vectors at stride n.  With graphs on (and timing off) the whole
 // application is replayed from a graph captured on first use for this nv on the fixed
 // vectors rin -> zin; r and z are copied in and out unless they are those vectors.  The
@@ -1326,27 +1353,7 @@ void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s
   const size_t bytes = sizeof(double) * size_t(nv) * size_t(h->P.n);
   if (r != h->rin)
     hip_check(h, hipMemcpyAsync(h->rin, r, bytes, hipMemcpyDeviceToDevice, s), "apply in");
-  if (int(h->apply_graph.size()) <= nv) h->apply_graph.resize(size_t(nv) + 1, nullptr);
-  hipGraphExec_t& ex = h->apply_graph[size_t(nv)];
-  if (!ex) {
-    if (!h->cap)
-      hip_check(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreate");
-    hipGraph_t g = nullptr;
-    hip_check(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal),
-              "begin capture");
-    try {
-      core_apply(h, own_work(h), nv, h->rin, h->zin, h->cap);
-    } catch (...) {
-      (void)hipStreamEndCapture(h->cap, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    hip_check(h, hipStreamEndCapture(h->cap, &g), "end capture");
-    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    hip_check(h, e, "hipGraphInstantiate");
-  }
-  hip_check(h, hipGraphLaunch(ex, s), "hipGraphLaunch");
+  hip_check(h, hipGraphLaunch(apply_graph(h, nv), s), "hipGraphLaunch");
   if (z != h->zin)
     hip_check(h, hipMemcpyAsync(z, h->zin, bytes, hipMemcpyDeviceToDevice, s), "apply out");
 }
@@ -1365,6 +1372,17 @@ void ensure_vectors(rsd_ctx* h, int nv) {
   h->rin = dalloc<double>(h, n * size_t(nv));
   h->zin = dalloc<double>(h, n * size_t(nv));
   h->nvec = nv;
+}
+
+// At the end of a set-up's enqueueing, while the device still runs it: the one-vector
+// application's work vectors and graph, which the first apply of a solve would otherwise
+// capture with the device idle (a handle whose applies run eagerly, or that has them
+// already, is left as it is).
+void precapture_apply(rsd_ctx* h) {
+  if (!h->opt.graphs || apply_timed(h)) return;
+  if (h->apply_graph.size() > 1 && h->apply_graph[1]) return;
+  ensure_vectors(h, 1);
+  (void)apply_graph(h, 1);
 }
 
 // Krylov work space for restart length m and nr right-hand sides in lockstep.
