@@ -125,8 +125,10 @@ typedef struct {
   int32_t gamma;         /* inner GMRES steps per interface solve (1..64; gamma modes)      */
   int32_t dense_max;     /* RSD_IFACE_HYBRID: largest interface solved exactly              */
   int32_t graphs;        /* 1: replay each preconditioner application from a HIP graph
-                            captured on first use (one per number of columns, 1..8);
-                            ignored while a class of the applications is timed (below)     */
+                            captured on first use (one per number of columns, 1..8; the
+                            one-column graph already during rsd_setup, while the device
+                            runs the set-up); ignored while a class of the applications
+                            is timed (below)                                              */
   int32_t autotune;      /* 1: before the first application to 2..8 columns, time the
                             candidate numbers of vectors per pass (1, 2, 4) of every dense
                             batch's symmetric product, each with one workgroup per item
