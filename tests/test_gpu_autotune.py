@@ -97,3 +97,26 @@ def test_persistent_symmetric_products_bitwise(leaf_prec):
     hu.close()
     hp.close()
 
+
+
+@pytest.mark.parametrize("height", [2, 3])
+def test_deeper_levels_invert_beside_the_shallowest(problem_cache, height):
+    """With symmetric K the dense interface levels other than the shallowest one are
+    inverted on a second stream beside it, in serial steps (that stream carries no
+    look-ahead): every level below the root reports serial steps (rsd_stats.setup_variant
+    2; FP64 batches have one update shape), the sub-domains and the root look-ahead or
+    serial steps (1 or 2: the schedule this process's autotuner may already have chosen
+    for their shapes), and the solve converges to 1e-10."""
+    p = problem_cache("diffusion", 24, height, 1.0, 3)
+    h = _handle(p, autotune=False)
+    v = h.stats()["setup_variant"]
+    assert v[0] in (1, 2) and v[height] in (1, 2), v
+    assert all(x == 2 for x in v[1:height]), v
+    assert all(x == 0 for x in v[height + 1:]), v
+    b = torch.as_tensor(np.random.default_rng(8).uniform(-1, 1, p.n)).cuda()
+    x, status, info = h.solve(b, rtol=1e-10)
+    assert status == 0
+    K = p.K.tocsr()
+    xs, bs = x.cpu().numpy(), b.cpu().numpy()
+    assert np.linalg.norm(bs - K @ xs) <= 1e-10 * np.linalg.norm(bs) * 1.01
+    h.close()
