@@ -1339,10 +1339,9 @@ hipGraphExec_t apply_graph(rsd_ctx* h, int nv) {
 }
 
 // z = M^{-1} r for nv vectors at stride n.  With graphs on (and timing off) the whole
-// application is replayed from a graph captured on first use for this nv on the fixed
-// vectors rin -> zin; r and z are copied in and out unless they are those vectors.  The
-// capture runs on the handle's own stream (capturing executes nothing); the replays run
-// on the caller's stream.
+// application is replayed from the graph of this nv on the fixed vectors rin -> zin
+// (apply_graph; the one-vector graph is captured during the set-up); r and z are copied
+// in and out unless they are those vectors.  The replays run on the caller's stream.
 void apply_vectors(rsd_ctx* h, int nv, const double* r, double* z, hipStream_t s) {
   if (h->opt.autotune && nv >= 2 && nv <= kRhsGroup && !h->tuned[size_t(nv)])
     autotune_apply(h, nv, s);            // before this nv's graph is captured
