@@ -209,7 +209,10 @@ def _golden_coupled_rows():
 def test_paper_coupled_iteration_counts_p8(problem_cache, prob, N, P, gamma, beta):
     """Tables 4 and 7 with LU sub-domain solves.  Problem 3 within +-2.  Problem 2
     (weak coupling) drifts below the printed counts as they grow (80 vs 87 at N = 33,
-    gamma = 2): within max(2, 12%) -- the reading of its scaling is stated in DESIGN."""
+    gamma = 2): within max(2, 12%).  The paper states neither the discretisation of the
+    coupling terms nor the domain size; here each sub-domain is a unit square with the
+    consistent mass matrix for the coupling, which sets the coupling's weight against
+    the scale-invariant stiffness and hence how far Problem 2's counts can match."""
     s = problem_cache("strip", N, P, prob, 0)
     assert abs(s.K - s.K.T).max() > 0                   # really non-symmetric
     o = RSDOracle(s.K, s.parent, s.dof_node, interface="gamma", gamma=gamma)
