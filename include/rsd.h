@@ -53,7 +53,7 @@ typedef enum {
   RSD_ERR_BREAKDOWN = 5,         /* NaN/Inf in the Krylov recurrence                     */
   RSD_ERR_OUT_OF_MEMORY = 6,     /* device allocation failed                             */
   RSD_ERR_DEVICE = 7,            /* any other HIP runtime error                          */
-  RSD_ERR_UNSUPPORTED = 8        /* valid request this build does not implement          */
+  RSD_ERR_UNSUPPORTED = 8        /* valid request the library does not implement         */
 } rsd_status;
 
 typedef struct rsd_ctx* rsd_handle;
