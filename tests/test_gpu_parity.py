@@ -232,6 +232,42 @@ def test_not_spd_leaf_is_reported(problem_cache):
     assert ei.value.status == 3 and f"leaf node {leaf}" in str(ei.value)
 
 
+def test_invalid_structure_on_the_device_is_reported(problem_cache):
+    """rsd_setup with the structure in device memory copies it to the host for the
+    analysis; a malformed CSR or map (23^3 dofs: the analysis checks the rows in several
+    parallel chunks) is rejected before any kernel with the message the host analysis
+    (rsd_analyze) gives, and a valid set-up in the same process still solves."""
+    from paper_1210_6266_amd import RSD, RSDError
+    from paper_1210_6266_amd import rsd as R
+    p = problem_cache("diffusion", 24, 2, 0.0, 0)
+    rp, ci, v = p.csr_arrays()
+    par, dn = p.parent.astype(np.int32), p.dof_node.astype(np.int32)
+    n, hi_row = p.n, p.n - 100
+    cases = {}
+    a = rp.copy()
+    a[hi_row + 1] = a[hi_row] - 1
+    cases["row_ptr"] = (a, ci, dn, 1)
+    c = ci.copy()
+    c[rp[hi_row + 1] - 1] = n
+    cases["col_range"] = (rp, c, dn, 1)
+    d = dn.copy()
+    T = len(par)
+    leaves = [t for t in range(T) if t not in set(par[1:].tolist())]
+    d[np.nonzero(dn == leaves[0])[0][0]] = leaves[-1]
+    cases["not_separable"] = (rp, ci, d, 2)
+    for name, (rpx, cix, dnx, status) in cases.items():
+        with pytest.raises(R.RSDError) as eh:
+            R.rsd_analyze(rpx, cix, par, dnx)
+        with pytest.raises(RSDError) as ed:
+            RSD(rpx, cix, v, par, dnx)
+        assert ed.value.status == eh.value.status == status, name
+        assert str(eh.value).split(": ", 1)[-1] in str(ed.value), (name, str(ed.value))
+    h = _handle(p)
+    x, st, info = h.solve(_dev(p.b[:, 0], torch.float64), rtol=1e-10)
+    assert st == 0
+    h.close()
+
+
 def test_nan_rhs_reports_breakdown(problem_cache):
     p = problem_cache("config", "poisson12")
     h = _handle(p)
